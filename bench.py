@@ -1,0 +1,170 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled HLBM + discrete-contact time step on one GPU.
+
+Default workload: dense settling box, 256^3 periodic lattice, 1834 cubes of
+edge 14 (phi = 0.30, s = 1.5, Ar = 1000), populations in FP32, synthetic
+seeded scene.  A step is the whole time step: contact treatment, particle
+motion and tile binning, contact carry-over, coupling map with rough
+detection, and the fused stream-collide pass with the momentum exchange.
+
+Prints ONE JSON line with the metric, the roofline of the dominant kernel
+(the fused lattice pass, HBM-bound) and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--precision fp32|fp64|fp16s]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+PREC = {"fp64": 0, "fp32": 1, "fp16s": 2}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f16-storage/f32-compute"}
+VALUE_BYTES = {0: 8, 1: 4, 2: 2}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lattice_c3_traffic.json")
+LATTICE_SRC = os.path.join(ROOT, "paper_2401_10878_amd", "csrc", "k_lattice.hip")
+
+
+def lattice_source_hash():
+    return hashlib.sha256(open(LATTICE_SRC, "rb").read()).hexdigest()[:16]
+
+
+def traffic_for(prec_name):
+    """HBM bytes per lattice launch from the committed rocprofv3 counters,
+    or None if the counters were taken on another version of the kernel."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != lattice_source_hash():
+        return None
+    e = d.get("per_precision", {}).get(prec_name)
+    return e.get("bytes_per_launch") if e else None
+
+
+def run_gpu(wl, prec, steps, warmup, graph):
+    import torch
+    from paper_2401_10878_amd import hlbm
+    p = wl.params.replace(precision=PREC[prec])
+    sim = hlbm.Simulation(p, wl.scene, device="cuda:0", graph=graph)
+    sim.init_equilibrium()
+    sim.step(warmup)
+    sim.sync()
+    c0 = sim.counters()
+    sim.timing_begin(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms, n = sim.timing_end()
+    c1 = sim.counters()
+    ncell = p.nx * p.ny * p.nz
+    wall = t1 - t0
+    out = dict(
+        mlups=ncell * steps / wall / 1e6,
+        ms_per_step=wall * 1e3 / steps,
+        contact_cells_per_s=(c1["total_cells"] - c0["total_cells"]) / wall,
+        kernel_ms_per_step={k: v / n for k, v in kms.items()},
+        pairs=c1["pairs"], overlap_cells=c1["cells"],
+    )
+    lat_s = kms["lattice"] / n / 1e3
+    bytes_alg = 2 * 19 * VALUE_BYTES[PREC[prec]] * ncell
+    out["lattice_gbs"] = bytes_alg / lat_s / 1e9
+    out["bytes_alg"] = bytes_alg
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(wl, steps):
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle as O
+    s = O.OracleSim(wl.params, wl.scene)
+    s.init_equilibrium()
+    t0 = time.perf_counter()
+    s.step(steps)
+    t1 = time.perf_counter()
+    ncell = wl.params.nx * wl.params.ny * wl.params.nz
+    res = dict(value=round(ncell * steps / (t1 - t0) / 1e6, 3), unit="MLUPS",
+               cores=O.threads(), kind="oracle",
+               sample=f"{wl.name}: {steps} coupled FP64 steps after the prologue "
+                      f"({ncell} nodes, {wl.scene.n} particles), {t1 - t0:.1f} s")
+    s.close()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fp32", choices=sorted(PREC))
+    ap.add_argument("--workload", default="C3", choices=["C1", "C2", "C3", "C4", "C5"])
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the step as a captured HIP graph")
+    ap.add_argument("--other-precisions", type=int, default=1,
+                    help="also time the other two storage precisions")
+    ap.add_argument("--cpu-steps", type=int, default=4,
+                    help="oracle steps timed for the CPU baseline (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU "
+              "path (see DESIGN.md for how it would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2401_10878_amd import workloads as W
+    wl = W.WORKLOADS[args.workload]()
+    main_res = run_gpu(wl, args.precision, args.steps, args.warmup, args.graph)
+    others = {}
+    if args.other_precisions:
+        for pr in PREC:
+            if pr != args.precision:
+                r = run_gpu(wl, pr, max(args.steps // 2, 10), args.warmup, args.graph)
+                others[pr] = dict(mlups=round(r["mlups"], 1),
+                                  ms_per_step=round(r["ms_per_step"], 4),
+                                  lattice_gbs=round(r["lattice_gbs"], 1))
+    others[args.precision] = dict(mlups=round(main_res["mlups"], 1),
+                                  ms_per_step=round(main_res["ms_per_step"], 4),
+                                  lattice_gbs=round(main_res["lattice_gbs"], 1))
+    lat_ms = main_res["kernel_ms_per_step"]["lattice"]
+    achieved = main_res["lattice_gbs"]
+    traffic = traffic_for(args.precision)
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS,
+                unit="GB/s", frac=round(achieved / PEAK_HBM_GBS, 4),
+                traffic=traffic, kernel="k_lattice",
+                bytes_per_launch=main_res["bytes_alg"],
+                avg_launch_ms=round(lat_ms, 5))
+    cpu = cpu_baseline(wl, args.cpu_steps) if args.cpu_steps > 0 else None
+    p = wl.params
+    line = dict(
+        metric="coupled-step MLUPS (+ contact cells/s)",
+        value=round(main_res["mlups"], 1), unit="MLUPS", n_gpus=1,
+        steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(main_res["ms_per_step"], 4),
+        higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype=DTYPE[args.precision], data="synthetic",
+        config=dict(workload=f"{wl.name}: {wl.note}", lattice=[p.nx, p.ny, p.nz],
+                    particles=wl.scene.n, precision=args.precision,
+                    graph=bool(args.graph)),
+        contact_cells_per_s=round(main_res["contact_cells_per_s"], 1),
+        detected_pairs=main_res["pairs"], overlap_cells=main_res["overlap_cells"],
+        kernel_ms_per_step={k: round(v, 5) for k, v in
+                            main_res["kernel_ms_per_step"].items()},
+        precisions=others,
+        roofline=roof,
+        cpu_baseline=cpu,
+    )
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,200 @@
+/*
+ * hlbm.h -- C ABI of the MI355X (gfx950) library for the four-way coupled
+ * homogenized lattice Boltzmann method with a discrete contact model for
+ * convex particles (Marquardt, Hafen & Krause, arXiv 2401.10878).
+ *
+ * The library advances one time step of the paper's Algorithm 1 (a single
+ * sub-step) entirely on one GPU:
+ *   - D3Q19 BGK stream-collide (Sec. 3.1, eqs. (10)-(13)) with the
+ *     exact-difference velocity-shift coupling (Sec. 3.2, eqs. (14)-(15));
+ *   - per-node signed-distance evaluation of the particles, which gives
+ *     the coupling weight B and the particle velocity at each node
+ *     (Sec. 3.2), and the momentum-exchange force and torque on each
+ *     particle (eqs. (16)-(18));
+ *   - the node-parallel rough contact detection, bounding-box correction
+ *     and overlap integration of the discrete contact model (Sec. 3.3.1),
+ *     with the lower-id reference for periodic boundaries (Sec. 3.3.2),
+ *     and the Nassauer-Kuna contact forces (Sec. 2.3, eqs. (4)-(9));
+ *   - Newton-Euler particle motion (eqs. (2)-(3)) with gravity and the
+ *     zero-net-flow balance force (Sec. 5.1).
+ *
+ * Units: lattice units throughout (Delta x = Delta t = 1).  Nodes sit at
+ * integer coordinates 0 <= x < nx etc.  x and y are periodic; z is periodic
+ * or bounded by half-way bounce-back walls at z = -1/2 and z = nz - 1/2.
+ *
+ * Layout: host population arrays are FP64 [19][nz][ny][nx] (velocity index
+ * slowest), D3Q19 order: rest; +x,-x,+y,-y,+z,-z; (1,1,0),(-1,-1,0),
+ * (1,-1,0),(-1,1,0),(1,0,1),(-1,0,-1),(1,0,-1),(-1,0,1),(0,1,1),(0,-1,-1),
+ * (0,1,-1),(0,-1,1).  Per-particle vectors are [n][3], quaternions [n][4]
+ * in (w, x, y, z) order.  Per-node fields are [nz][ny][nx].
+ *
+ * Ownership: every pointer argument is a HOST pointer owned by the caller
+ * unless stated otherwise; read calls copy and synchronise before return.
+ * The context owns its device memory, except population buffers lent with
+ * hlbm_bind_populations, which it never frees.
+ *
+ * Errors: every call returns an hlbm_status; 0 is success.  After an error
+ * hlbm_last_error() describes it.  Device-side conditions (capacity
+ * overflow, non-finite or non-positive density) are raised at the next
+ * read or hlbm_sync call as HLBM_E_CAPACITY / HLBM_E_UNSTABLE.  No C++
+ * exception crosses the ABI.
+ */
+#ifndef HLBM_H
+#define HLBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HLBM_OK = 0,
+    HLBM_E_ARG = -1,        /* invalid argument or configuration */
+    HLBM_E_NOMEM = -2,      /* device or host allocation failed */
+    HLBM_E_DEVICE = -3,     /* HIP runtime error */
+    HLBM_E_CAPACITY = -4,   /* tile candidate list or pair table overflow */
+    HLBM_E_UNSTABLE = -5,   /* non-finite or non-positive density */
+    HLBM_E_STATE = -6       /* call out of order (e.g. step before init) */
+} hlbm_status;
+
+typedef enum {
+    HLBM_FP64 = 0,          /* populations stored and collided in FP64 */
+    HLBM_FP32 = 1,          /* populations stored and collided in FP32 */
+    HLBM_FP16S = 2          /* f - w stored as IEEE binary16, FP32 collision */
+} hlbm_precision;
+
+typedef enum { HLBM_SPHERE = 0, HLBM_CUBE = 1 } hlbm_shape;
+
+typedef struct {
+    int nx, ny, nz;             /* lattice nodes per axis */
+    int periodic_z;             /* 1 periodic, 0 walls at -1/2 and nz-1/2 */
+    double tau;                 /* BGK relaxation time, eq. (12); > 1/2 */
+    double wall_velocity[2][3]; /* bottom (0) and top (1) wall velocity */
+    double gravity[3];          /* gravitational acceleration on particles */
+    double fluid_accel[3];      /* uniform acceleration added to the fluid */
+    int balance;                /* add the zero-net-flow balance force */
+    double eps_b;               /* width of the B(d) band around the surface */
+    double enlarge;             /* enlargement in contact treatment (0.2) */
+    int n_c;                    /* contact resolution (8), 1..32 */
+    double young, poisson;      /* material, eq. (5) (same for walls) */
+    double restitution;         /* e of eq. (6) */
+    double mu_s, mu_k, u_k;     /* friction law, eqs. (7)-(9) */
+    int max_pairs;              /* capacity of the contact-pair table */
+    int tile_capacity;          /* particles per 4x4x4 tile, <= 64 */
+    int precision;              /* hlbm_precision */
+} hlbm_params;
+
+/* One contact record.  b >= 0: particle-particle with a < b; b = -1: the
+   bottom wall, b = -2: the top wall.  count / rlo / rhi come from the latest
+   rough detection (node images in the frame of particle a); lo / hi is the
+   box the next treatment starts from (the corrected box when carried = 1);
+   the remaining fields are the results of the latest treatment. */
+typedef struct {
+    int a, b;
+    int count;
+    int rlo[3], rhi[3];
+    int carried;
+    double lo[3], hi[3];
+    int established;
+    double damping;
+    int age;
+    int n_in;
+    double volume, centroid[3], normal[3], depth, fn, force_a[3], force_b[3];
+} hlbm_contact;
+
+typedef struct hlbm_ctx hlbm_ctx;
+
+/* Create a context on the current HIP device.  stream: a hipStream_t to run
+   on (for example the current torch stream), or NULL for a private stream.
+   Validates the parameters (lattice size, tau, capacities); allocates the
+   population buffers unless they are lent later.  *out is NULL on error. */
+hlbm_status hlbm_create(const hlbm_params *params, void *stream,
+                        hlbm_ctx **out);
+
+/* Lend two DEVICE population buffers of `bytes` each (19 * nx*ny*nz *
+   bytes-per-value of the precision: 8, 4 or 2).  Must be called before any
+   init call.  The context never frees them. */
+hlbm_status hlbm_bind_populations(hlbm_ctx *ctx, void *dev_a, void *dev_b,
+                                  size_t bytes);
+
+/* Upload n particles (host arrays).  size = radius (sphere) or edge (cube);
+   density = particle/fluid density ratio.  Positions on periodic axes are
+   wrapped into [0, n).  Periodic axes must exceed twice the particle reach
+   (circumradius + detection margin). */
+hlbm_status hlbm_init_particles(hlbm_ctx *ctx, int n, const int *shape,
+                                const double *size, const double *density,
+                                const double *X, const double *q,
+                                const double *U, const double *omega);
+
+/* Set f* = f^eq(rho, u) on every node, then couple the particles to the
+   fluid at their current state: node ownership, rough contact detection
+   (the initial contact list) and the momentum-exchange force. */
+hlbm_status hlbm_init_fluid_equilibrium(hlbm_ctx *ctx, double rho,
+                                        const double u[3]);
+
+/* Same, from a host FP64 population field [19][nz][ny][nx]. */
+hlbm_status hlbm_set_populations(hlbm_ctx *ctx, const double *f);
+
+/* Advance nsteps coupled time steps (asynchronous on the context stream).
+   Order per step (Algorithm 1, one sub-step): contact treatment, gravity and
+   Newton-Euler update, particle-to-fluid coupling with rough detection,
+   collide-and-stream with the fluid-to-particle momentum exchange. */
+hlbm_status hlbm_step(hlbm_ctx *ctx, int nsteps);
+
+/* Use (1) or stop using (0) a captured HIP graph for hlbm_step. */
+hlbm_status hlbm_use_graph(hlbm_ctx *ctx, int on);
+
+/* Per-kernel timing of the next steps: hlbm_step records HIP events on the
+   context stream around each of its six kernel launches (bookkeeping clear,
+   contact treatment, particle motion + tile binning, contact carry-over,
+   coupling map + rough detection, fused lattice pass) for up to max_steps
+   steps (graphs are bypassed meanwhile).  hlbm_timing_end synchronises and
+   returns the summed milliseconds per kernel in that order, kernel_ms[6],
+   and the number of timed steps. */
+hlbm_status hlbm_timing_begin(hlbm_ctx *ctx, int max_steps);
+hlbm_status hlbm_timing_end(hlbm_ctx *ctx, double *kernel_ms, int *nsteps);
+
+/* Wait for queued work; raise device-side error flags. */
+hlbm_status hlbm_sync(hlbm_ctx *ctx);
+
+/* Hydrodynamic and contact force/torque that moved the particles in the
+   last step ([n][3] each; any pointer may be NULL). */
+hlbm_status hlbm_read_forces(hlbm_ctx *ctx, double *Fh, double *Th,
+                             double *Fc, double *Tc);
+
+hlbm_status hlbm_read_particles(hlbm_ctx *ctx, double *X, double *q,
+                                double *U, double *omega);
+
+/* Current contact list, sorted by (a, b); *n_out = number of records (may
+   exceed capacity, in which case only `capacity` are written). */
+hlbm_status hlbm_read_contacts(hlbm_ctx *ctx, int capacity,
+                               hlbm_contact *out, int *n_out);
+
+/* Density and velocity moments of the stored post-collision field, and the
+   node owner (-1 = fluid) at the current particle state.  NULL skips. */
+hlbm_status hlbm_read_fields(hlbm_ctx *ctx, double *rho, double *u,
+                             int *owner);
+
+/* Post-collision populations as FP64 [19][nz][ny][nx] (FP16S: w_i + h_i). */
+hlbm_status hlbm_read_populations(hlbm_ctx *ctx, double *f);
+
+/* Latest detection: pairs with count > 0 and the sum of their counts
+   (overlap node count); totals accumulated over all steps so far. */
+hlbm_status hlbm_counters(hlbm_ctx *ctx, long long *pairs,
+                          long long *cells, long long *total_cells,
+                          long long *steps);
+
+/* The context's stream (hipStream_t) and precision. */
+void *hlbm_stream(const hlbm_ctx *ctx);
+
+/* The uniform fluid acceleration in use (fluid_accel + balance force). */
+hlbm_status hlbm_fluid_acceleration(const hlbm_ctx *ctx, double a[3]);
+
+const char *hlbm_last_error(const hlbm_ctx *ctx);
+void hlbm_destroy(hlbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,690 @@
+// C ABI of the library (declared in include/hlbm.h): context management,
+// validation on the host, the per-step launch sequence and read-out.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "context.h"
+
+using namespace hlbm;
+
+struct hlbm_ctx {
+  Ctx c;
+};
+
+namespace {
+
+hlbm_status fail(Ctx& c, hlbm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  c.err = buf;
+  return st;
+}
+
+#define HIPCHECK(call)                                                      \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return fail(c, HLBM_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t value_bytes(int prec) { return prec == HLBM_FP64 ? 8 : (prec == HLBM_FP32 ? 4 : 2); }
+
+int next_pow2(long long v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// reach beyond the body used for tile binning (must match k_particles)
+double margin_of(const Ctx& c) {
+  return fmax(0.5 * c.ph.eps + 1.4142135623730951, DETECT + c.ph.delta_c) + 0.25;
+}
+
+hlbm_status check_flags(Ctx& c) {
+  Counters h;
+  HIPCHECK(hipMemcpyAsync(&h, c.counters, sizeof h, hipMemcpyDeviceToHost, c.stream));
+  HIPCHECK(hipStreamSynchronize(c.stream));
+  if (h.tile_overflow)
+    return fail(c, HLBM_E_CAPACITY,
+                "tile candidate list overflow: more than tile_capacity=%d particles reach one 4x4x4 tile",
+                c.g.tile_cap);
+  if (h.pair_overflow)
+    return fail(c, HLBM_E_CAPACITY, "contact pair table full (max_pairs=%d)",
+                c.P.max_pairs);
+  if (h.unstable)
+    return fail(c, HLBM_E_UNSTABLE, "non-finite or non-positive density on the lattice");
+  return HLBM_OK;
+}
+
+hlbm_status ensure_populations(Ctx& c) {
+  if (c.fbuf[0]) return HLBM_OK;
+  const size_t bytes = (size_t)Q * (size_t)c.g.ncell * c.bytes_per_value;
+  for (int k = 0; k < 2; ++k) {
+    hipError_t e = hipMalloc(&c.fbuf[k], bytes);
+    if (e != hipSuccess)
+      return fail(c, HLBM_E_NOMEM, "population buffer of %zu bytes: %s", bytes,
+                  hipGetErrorString(e));
+  }
+  c.own_f = true;
+  return HLBM_OK;
+}
+
+void drop_graphs(Ctx& c) {
+  for (int k = 0; k < 2; ++k) {
+    if (c.graph_ready[k]) hipGraphExecDestroy(c.gexec[k]);
+    c.graph_ready[k] = false;
+  }
+}
+
+// Coupling and detection at the current particle state with the current
+// populations as f*: ownership map, initial contact list, and the
+// momentum-exchange force that moves the particles in the first step.
+hlbm_status prologue(Ctx& c) {
+  drop_graphs(c);
+  const int p = c.cur;
+  const size_t nb = sizeof(double) * 3 * (c.np > 0 ? c.np : 1);
+  HIPCHECK(launch_clear_step(c, c.tab[p]));
+  HIPCHECK(hipMemsetAsync(c.Fh, 0, nb, c.stream));
+  HIPCHECK(hipMemsetAsync(c.Th, 0, nb, c.stream));
+  HIPCHECK(hipMemsetAsync(c.tl.ovf, 0, 2 * nb, c.stream));
+  HIPCHECK(launch_particles(c, 0));
+  HIPCHECK(launch_detect(c, c.tab[p]));
+  HIPCHECK(launch_mea_only(c, c.fbuf[p]));
+  c.step = 0;
+  c.fluid_ready = true;
+  return check_flags(c);
+}
+
+// The launch sequence of one time step with parity p (buffers p -> 1-p).
+// ev (optional): NKERN + 1 events recorded around the launches.
+hipError_t enqueue_step(Ctx& c, int p, hipEvent_t* ev) {
+  hipError_t e;
+  auto mark = [&](int k) -> hipError_t {
+    return ev ? hipEventRecord(ev[k], c.stream) : hipSuccess;
+  };
+  if ((e = mark(0))) return e;
+  if ((e = launch_clear_step(c, c.tab[1 - p]))) return e;
+  if ((e = mark(1))) return e;
+  if ((e = launch_treat(c, c.tab[p]))) return e;
+  if ((e = mark(2))) return e;
+  if ((e = launch_particles(c, 1))) return e;
+  if ((e = mark(3))) return e;
+  if ((e = launch_keep(c, c.tab[p], c.tab[1 - p]))) return e;
+  if ((e = mark(4))) return e;
+  if ((e = launch_detect(c, c.tab[1 - p]))) return e;
+  if ((e = mark(5))) return e;
+  if ((e = launch_lattice(c, c.fbuf[p], c.fbuf[1 - p]))) return e;
+  return mark(6);
+}
+
+void free_timing(Ctx& c) {
+  if (c.tev) {
+    for (int i = 0; i < c.tcap * (NKERN + 1); ++i) hipEventDestroy(c.tev[i]);
+    delete[] c.tev;
+  }
+  c.tev = nullptr;
+  c.tcap = c.tused = 0;
+  c.timing = false;
+}
+
+void free_particles(Ctx& c) {
+  if (c.part_block) hipFree(c.part_block);
+  c.part_block = nullptr;
+  if (c.part_sums) hipFree(c.part_sums);
+  c.part_sums = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+hlbm_status hlbm_create(const hlbm_params* params, void* stream, hlbm_ctx** out) {
+  if (!out) return HLBM_E_ARG;
+  *out = nullptr;
+  if (!params) return HLBM_E_ARG;
+  hlbm_ctx* h = new (std::nothrow) hlbm_ctx();
+  if (!h) return HLBM_E_NOMEM;
+  Ctx& c = h->c;
+  c.P = *params;
+  const hlbm_params& P = *params;
+  auto bad = [&](const char* m) {
+    fprintf(stderr, "hlbm_create: %s\n", m);
+    delete h;
+    return HLBM_E_ARG;
+  };
+  if (P.nx < 1 || P.ny < 1 || P.nz < 1 || P.nx > 4096 || P.ny > 4096 || P.nz > 4096)
+    return bad("lattice size must be 1..4096 per axis");
+  const long long ncell = (long long)P.nx * P.ny * P.nz;
+  // population offsets i * ncell + node are 32-bit
+  if (ncell * Q > (1LL << 31) - 1) return bad("more than (2^31-1)/19 nodes");
+  if (!(P.tau > 0.5)) return bad("tau must exceed 1/2");
+  if (P.n_c < 1 || P.n_c > 32) return bad("n_c must be 1..32");
+  if (P.tile_capacity < 1 || P.tile_capacity > LCAP_MAX) return bad("tile_capacity must be 1..64");
+  if (P.max_pairs < 1 || P.max_pairs > (1 << 24)) return bad("max_pairs must be 1..2^24");
+  if (P.precision < 0 || P.precision > 2) return bad("precision must be 0, 1 or 2");
+  if (!(P.eps_b > 0.0) || !(P.enlarge >= 0.0)) return bad("eps_b > 0 and enlarge >= 0 required");
+  if (!(P.young > 0.0) || !(P.u_k > 0.0) || !(P.mu_s > 0.0))
+    return bad("young, u_k and mu_s must be positive");
+
+  c.precision = P.precision;
+  c.bytes_per_value = value_bytes(P.precision);
+  c.g.nx = P.nx; c.g.ny = P.ny; c.g.nz = P.nz;
+  c.g.periodic_z = P.periodic_z ? 1 : 0;
+  c.g.dtx = (P.nx + DX - 1) / DX;
+  c.g.dty = (P.ny + DY - 1) / DY;
+  c.g.dtz = (P.nz + DZ - 1) / DZ;
+  c.g.ltx = (P.nx + LX - 1) / LX;
+  c.g.lty = (P.ny + LY - 1) / LY;
+  c.g.ltz = (P.nz + LZ - 1) / LZ;
+  c.g.tile_cap = P.tile_capacity;
+  c.g.ncell = ncell;
+  c.ph.tau = P.tau;
+  c.ph.omega = 1.0 / P.tau;
+  for (int w = 0; w < 2; ++w)
+    for (int k = 0; k < 3; ++k) c.ph.wall_u[w][k] = P.wall_velocity[w][k];
+  for (int k = 0; k < 3; ++k) {
+    c.ph.gravity[k] = P.gravity[k];
+    c.ph.a_ext[k] = P.fluid_accel[k];
+  }
+  c.ph.eps = P.eps_b;
+  c.ph.delta_c = P.enlarge;
+  c.ph.n_c = P.n_c;
+  // eq. (5) with both bodies (and walls) of the same material
+  c.ph.estar = 1.0 / ((1.0 - P.poisson * P.poisson) / P.young +
+                      (1.0 - P.poisson * P.poisson) / P.young);
+  c.ph.restitution = P.restitution;
+  c.ph.mu_s = P.mu_s;
+  c.ph.mu_k = P.mu_k;
+  c.ph.u_k = P.u_k;
+
+  if (stream) {
+    c.stream = (hipStream_t)stream;
+    c.own_stream = false;
+  } else {
+    if (hipStreamCreate(&c.stream) != hipSuccess) {
+      delete h;
+      return HLBM_E_DEVICE;
+    }
+    c.own_stream = true;
+  }
+  const long long ndt = (long long)c.g.dtx * c.g.dty * c.g.dtz;
+  const long long nlt = (long long)c.g.ltx * c.g.lty * c.g.ltz;
+  const int cap = next_pow2(2LL * P.max_pairs);
+  const size_t tbytes = sizeof(int) * (size_t)(ndt + nlt) * (1 + P.tile_capacity) +
+                        sizeof(int) * (size_t)nlt * P.tile_capacity;
+  bool okm = hipMalloc(&c.owner, sizeof(int) * ncell) == hipSuccess &&
+             hipMalloc(&c.tile_block, tbytes) == hipSuccess &&
+             hipMalloc(&c.counters, sizeof(Counters)) == hipSuccess &&
+             hipMalloc(&c.scratch, sizeof(double) * ncell) == hipSuccess;
+  for (int k = 0; k < 2 && okm; ++k) {
+    c.tab[k].cap = cap;
+    okm = hipMalloc(&c.tab[k].keys, sizeof(uint64_t) * cap) == hipSuccess &&
+          hipMalloc(&c.tab[k].rec, sizeof(PairRec) * cap) == hipSuccess;
+  }
+  if (!okm) {
+    *out = h;
+    hlbm_destroy(h);
+    *out = nullptr;
+    return HLBM_E_NOMEM;
+  }
+  {
+    int* t = (int*)c.tile_block;
+    c.tl.dcount = t; t += ndt;
+    c.tl.dlist = t; t += ndt * P.tile_capacity;
+    c.tl.lcount = t; t += nlt;
+    c.tl.llist = t; t += nlt * P.tile_capacity;
+    c.tl.lent = t;
+  }
+  hipMemsetAsync(c.counters, 0, sizeof(Counters), c.stream);
+  hipMemsetAsync(c.owner, 0xff, sizeof(int) * ncell, c.stream);
+  for (int k = 0; k < 2; ++k) {
+    hipMemsetAsync(c.tab[k].keys, 0xff, sizeof(uint64_t) * cap, c.stream);
+    hipMemsetAsync(c.tab[k].rec, 0, sizeof(PairRec) * cap, c.stream);
+  }
+  if (hipStreamSynchronize(c.stream) != hipSuccess) {
+    hlbm_destroy(h);
+    return HLBM_E_DEVICE;
+  }
+  *out = h;
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_bind_populations(hlbm_ctx* h, void* a, void* b, size_t bytes) {
+  if (!h) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  const size_t need = (size_t)Q * (size_t)c.g.ncell * c.bytes_per_value;
+  if (!a || !b || a == b || bytes < need)
+    return fail(c, HLBM_E_ARG, "bind_populations: need two distinct buffers of %zu bytes", need);
+  if (c.fbuf[0] && c.own_f) {
+    hipFree(c.fbuf[0]);
+    hipFree(c.fbuf[1]);
+  }
+  c.fbuf[0] = a;
+  c.fbuf[1] = b;
+  c.own_f = false;
+  c.fluid_ready = false;
+  drop_graphs(c);
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const double* size,
+                                const double* density, const double* X, const double* q,
+                                const double* U, const double* omega) {
+  if (!h) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (n < 0 || (n > 0 && (!shape || !size || !density || !X || !q || !U || !omega)))
+    return fail(c, HLBM_E_ARG, "init_particles: bad arguments");
+  const double L[3] = {(double)c.g.nx, (double)c.g.ny, (double)c.g.nz};
+  const bool per[3] = {true, true, c.g.periodic_z != 0};
+  const double margin = margin_of(c);
+  std::vector<int> sh(n > 0 ? n : 1);
+  std::vector<double> sz(n), ds(n), vol(n), mass(n), inert(n), Xh(3 * n), qh(4 * n),
+      Uh(3 * n), Wh(3 * n);
+  for (int i = 0; i < n; ++i) {
+    if (shape[i] != 0 && shape[i] != 1)
+      return fail(c, HLBM_E_ARG, "particle %d: shape must be 0 (sphere) or 1 (cube)", i);
+    if (!(size[i] > 0.0) || !(density[i] > 0.0) || !isfinite(size[i]) || !isfinite(density[i]))
+      return fail(c, HLBM_E_ARG, "particle %d: size and density must be positive", i);
+    sh[i] = shape[i];
+    sz[i] = size[i];
+    ds[i] = density[i];
+    const double circ = shape[i] == 0 ? size[i] : 0.5 * size[i] * sqrt(3.0);
+    for (int k = 0; k < 3; ++k) {
+      if (per[k] && !(L[k] > 2.0 * (circ + margin)))
+        return fail(c, HLBM_E_ARG,
+                    "particle %d: periodic axis %d (%g nodes) must exceed twice the reach %g",
+                    i, k, L[k], circ + margin);
+      double x = X[3 * i + k];
+      if (!isfinite(x) || !isfinite(U[3 * i + k]) || !isfinite(omega[3 * i + k]))
+        return fail(c, HLBM_E_ARG, "particle %d: non-finite state", i);
+      if (per[k]) {
+        x = fmod(x, L[k]);
+        if (x < 0.0) x += L[k];
+        if (x >= L[k]) x -= L[k];
+      }
+      Xh[3 * i + k] = x;
+      Uh[3 * i + k] = U[3 * i + k];
+      Wh[3 * i + k] = omega[3 * i + k];
+    }
+    double nq = 0.0;
+    for (int k = 0; k < 4; ++k) nq += q[4 * i + k] * q[4 * i + k];
+    if (!(nq > 0.0) || !isfinite(nq))
+      return fail(c, HLBM_E_ARG, "particle %d: zero or non-finite quaternion", i);
+    for (int k = 0; k < 4; ++k) qh[4 * i + k] = q[4 * i + k];
+    if (fabs(nq - 1.0) > 1e-12)
+      for (int k = 0; k < 4; ++k) qh[4 * i + k] = q[4 * i + k] / sqrt(nq);
+    vol[i] = shape[i] == 0 ? 4.0 / 3.0 * PI * size[i] * size[i] * size[i]
+                           : size[i] * size[i] * size[i];
+    mass[i] = density[i] * vol[i];
+    inert[i] = shape[i] == 0 ? 0.4 * mass[i] * size[i] * size[i]
+                             : mass[i] * size[i] * size[i] / 6.0;
+  }
+  drop_graphs(c);
+  free_particles(c);
+  const size_t nn = n > 0 ? n : 1;
+  // layout of the one particle allocation (doubles, then ints)
+  // 5 scalars, X 3, q 4, U 3, W 3, R 9, Fh 3, Th 3, Fc 3, Tc 3
+  const size_t nd = nn * (5 + 3 + 4 + 3 + 3 + 9 + 3 + 3 + 3 + 3);
+  const size_t bytes = nd * sizeof(double) + nn * sizeof(int);
+  HIPCHECK(hipMalloc(&c.part_block, bytes));
+  HIPCHECK(hipMemsetAsync(c.part_block, 0, bytes, c.stream));
+  double* d = (double*)c.part_block;
+  auto take = [&](size_t k) { double* p = d; d += k * nn; return p; };
+  double* dsz = take(1); double* dds = take(1); double* dvol = take(1);
+  double* dmass = take(1); double* dinert = take(1);
+  c.part.X = take(3); c.part.q = take(4); c.part.U = take(3); c.part.W = take(3);
+  c.part.R = take(9);
+  c.Fh = take(3); c.Th = take(3);
+  c.Fc = take(3); c.Tc = take(3);
+  int* dsh = (int*)d;
+  c.part.n = n;
+  c.part.shape = dsh; c.part.size = dsz; c.part.dens = dds; c.part.vol = dvol;
+  c.part.mass = dmass; c.part.inert = dinert;
+  c.np = n;
+  // partial-sum slots: the lattice blocks one particle's reach box can touch
+  {
+    double emax = 0.0;
+    for (int i = 0; i < n; ++i)
+      emax = fmax(emax, sh[i] == 0 ? sz[i] : 0.5 * sz[i] * sqrt(3.0));
+    const double span = 2.0 * (emax + margin) + 3.0;
+    const int ts[3] = {LX, LY, LZ}, nt[3] = {c.g.ltx, c.g.lty, c.g.ltz};
+    long long me = 1;
+    for (int k = 0; k < 3; ++k) {
+      long long m = (long long)(span / ts[k]) + 2;
+      if (m > nt[k]) m = nt[k];
+      me *= m;
+    }
+    c.g.maxent = (int)me;
+    const size_t pb = sizeof(int) * nn + sizeof(double) * nn * 6 * (size_t)me +
+                      sizeof(double) * nn * 6;
+    HIPCHECK(hipMalloc(&c.part_sums, pb));
+    HIPCHECK(hipMemsetAsync(c.part_sums, 0, pb, c.stream));
+    double* pd = (double*)c.part_sums;
+    c.tl.part = pd;
+    c.tl.ovf = pd + nn * 6 * (size_t)me;
+    c.tl.nent = (int*)(c.tl.ovf + nn * 6);
+  }
+  if (n > 0) {
+    HIPCHECK(hipMemcpyAsync(dsh, sh.data(), sizeof(int) * n, hipMemcpyHostToDevice, c.stream));
+    HIPCHECK(hipMemcpyAsync(dsz, sz.data(), sizeof(double) * n, hipMemcpyHostToDevice, c.stream));
+    HIPCHECK(hipMemcpyAsync(dds, ds.data(), sizeof(double) * n, hipMemcpyHostToDevice, c.stream));
+    HIPCHECK(hipMemcpyAsync(dvol, vol.data(), sizeof(double) * n, hipMemcpyHostToDevice, c.stream));
+    HIPCHECK(hipMemcpyAsync(dmass, mass.data(), sizeof(double) * n, hipMemcpyHostToDevice, c.stream));
+    HIPCHECK(hipMemcpyAsync(dinert, inert.data(), sizeof(double) * n, hipMemcpyHostToDevice, c.stream));
+    HIPCHECK(hipMemcpyAsync(c.part.X, Xh.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c.stream));
+    HIPCHECK(hipMemcpyAsync(c.part.q, qh.data(), sizeof(double) * 4 * n, hipMemcpyHostToDevice, c.stream));
+    HIPCHECK(hipMemcpyAsync(c.part.U, Uh.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c.stream));
+    HIPCHECK(hipMemcpyAsync(c.part.W, Wh.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c.stream));
+  }
+  // zero-net-flow balance force (Sec. 5.1) on fully periodic boxes
+  for (int k = 0; k < 3; ++k) c.ph.a_ext[k] = c.P.fluid_accel[k];
+  if (c.P.balance && c.g.periodic_z) {
+    double tot[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < 3; ++k) tot[k] += (ds[i] - 1.0) * vol[i] * c.P.gravity[k];
+    for (int k = 0; k < 3; ++k) c.ph.a_ext[k] -= tot[k] / (double)c.g.ncell;
+  }
+  HIPCHECK(hipStreamSynchronize(c.stream));
+  c.particles_ready = true;
+  c.fluid_ready = false;
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_init_fluid_equilibrium(hlbm_ctx* h, double rho, const double u[3]) {
+  if (!h) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (!c.particles_ready)
+    return fail(c, HLBM_E_STATE, "init_particles must precede the fluid initialisation");
+  if (!(rho > 0.0) || !u) return fail(c, HLBM_E_ARG, "rho must be positive");
+  hlbm_status st = ensure_populations(c);
+  if (st) return st;
+  c.cur = 0;
+  HIPCHECK(launch_fill_equilibrium(c, c.fbuf[c.cur], rho, u));
+  return prologue(c);
+}
+
+hlbm_status hlbm_set_populations(hlbm_ctx* h, const double* f) {
+  if (!h) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (!c.particles_ready)
+    return fail(c, HLBM_E_STATE, "init_particles must precede the fluid initialisation");
+  if (!f) return fail(c, HLBM_E_ARG, "null population array");
+  hlbm_status st = ensure_populations(c);
+  if (st) return st;
+  c.cur = 0;
+  const size_t n = (size_t)c.g.ncell;
+  for (int i = 0; i < Q; ++i) {
+    HIPCHECK(hipMemcpyAsync(c.scratch, f + (size_t)i * n, sizeof(double) * n,
+                            hipMemcpyHostToDevice, c.stream));
+    HIPCHECK(launch_store_direction(c, c.fbuf[c.cur], i, c.scratch));
+  }
+  return prologue(c);
+}
+
+hlbm_status hlbm_step(hlbm_ctx* h, int nsteps) {
+  if (!h) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (!c.fluid_ready) return fail(c, HLBM_E_STATE, "initialise particles and fluid first");
+  if (nsteps < 0) return fail(c, HLBM_E_ARG, "nsteps must be >= 0");
+  for (int s = 0; s < nsteps; ++s) {
+    const int p = c.cur;
+    if (c.timing) {
+      if (c.tused >= c.tcap)
+        return fail(c, HLBM_E_CAPACITY, "timing window of %d steps is full", c.tcap);
+      HIPCHECK(enqueue_step(c, p, c.tev + (size_t)c.tused * (NKERN + 1)));
+      c.tused++;
+    } else if (c.use_graph) {
+      if (!c.graph_ready[p]) {
+        hipGraph_t gr;
+        HIPCHECK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_step(c, p, nullptr);
+        hipError_t e2 = hipStreamEndCapture(c.stream, &gr);
+        if (e != hipSuccess || e2 != hipSuccess)
+          return fail(c, HLBM_E_DEVICE, "graph capture: %s",
+                      hipGetErrorString(e != hipSuccess ? e : e2));
+        e = hipGraphInstantiate(&c.gexec[p], gr, nullptr, nullptr, 0);
+        hipGraphDestroy(gr);
+        if (e != hipSuccess)
+          return fail(c, HLBM_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+        c.graph_ready[p] = true;
+      }
+      HIPCHECK(hipGraphLaunch(c.gexec[p], c.stream));
+    } else {
+      HIPCHECK(enqueue_step(c, p, nullptr));
+    }
+    c.cur = 1 - p;
+    c.step++;
+  }
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_use_graph(hlbm_ctx* h, int on) {
+  if (!h) return HLBM_E_ARG;
+  h->c.use_graph = on != 0;
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_timing_begin(hlbm_ctx* h, int max_steps) {
+  if (!h) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (max_steps < 1 || max_steps > 100000)
+    return fail(c, HLBM_E_ARG, "timing window must be 1..100000 steps");
+  free_timing(c);
+  c.tev = new (std::nothrow) hipEvent_t[(size_t)max_steps * (NKERN + 1)];
+  if (!c.tev) return fail(c, HLBM_E_NOMEM, "timing events");
+  for (int i = 0; i < max_steps * (NKERN + 1); ++i) {
+    hipError_t e = hipEventCreate(&c.tev[i]);
+    if (e != hipSuccess) {
+      c.tcap = i / (NKERN + 1);
+      free_timing(c);
+      return fail(c, HLBM_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+    }
+  }
+  c.tcap = max_steps;
+  c.tused = 0;
+  c.timing = true;
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_timing_end(hlbm_ctx* h, double* kernel_ms, int* nsteps) {
+  if (!h || !kernel_ms || !nsteps) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (!c.timing) return fail(c, HLBM_E_STATE, "timing_begin was not called");
+  HIPCHECK(hipStreamSynchronize(c.stream));
+  for (int k = 0; k < NKERN; ++k) kernel_ms[k] = 0.0;
+  for (int s = 0; s < c.tused; ++s) {
+    hipEvent_t* ev = c.tev + (size_t)s * (NKERN + 1);
+    for (int k = 0; k < NKERN; ++k) {
+      float ms = 0.0f;
+      HIPCHECK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+      kernel_ms[k] += (double)ms;
+    }
+  }
+  *nsteps = c.tused;
+  free_timing(c);
+  return check_flags(c);
+}
+
+hlbm_status hlbm_sync(hlbm_ctx* h) {
+  if (!h) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  HIPCHECK(hipStreamSynchronize(c.stream));
+  return check_flags(c);
+}
+
+hlbm_status hlbm_read_forces(hlbm_ctx* h, double* Fh, double* Th, double* Fc, double* Tc) {
+  if (!h) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (!c.particles_ready) return fail(c, HLBM_E_STATE, "no particles");
+  const size_t b = sizeof(double) * 3 * c.np;
+  if (c.np > 0) {
+    if (Fh) HIPCHECK(hipMemcpyAsync(Fh, c.Fh, b, hipMemcpyDeviceToHost, c.stream));
+    if (Th) HIPCHECK(hipMemcpyAsync(Th, c.Th, b, hipMemcpyDeviceToHost, c.stream));
+    if (Fc) HIPCHECK(hipMemcpyAsync(Fc, c.Fc, b, hipMemcpyDeviceToHost, c.stream));
+    if (Tc) HIPCHECK(hipMemcpyAsync(Tc, c.Tc, b, hipMemcpyDeviceToHost, c.stream));
+  }
+  HIPCHECK(hipStreamSynchronize(c.stream));
+  return check_flags(c);
+}
+
+hlbm_status hlbm_read_particles(hlbm_ctx* h, double* X, double* q, double* U, double* W) {
+  if (!h) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (!c.particles_ready) return fail(c, HLBM_E_STATE, "no particles");
+  const size_t b = sizeof(double) * c.np;
+  if (c.np > 0) {
+    if (X) HIPCHECK(hipMemcpyAsync(X, c.part.X, 3 * b, hipMemcpyDeviceToHost, c.stream));
+    if (q) HIPCHECK(hipMemcpyAsync(q, c.part.q, 4 * b, hipMemcpyDeviceToHost, c.stream));
+    if (U) HIPCHECK(hipMemcpyAsync(U, c.part.U, 3 * b, hipMemcpyDeviceToHost, c.stream));
+    if (W) HIPCHECK(hipMemcpyAsync(W, c.part.W, 3 * b, hipMemcpyDeviceToHost, c.stream));
+  }
+  HIPCHECK(hipStreamSynchronize(c.stream));
+  return check_flags(c);
+}
+
+hlbm_status hlbm_read_contacts(hlbm_ctx* h, int capacity, hlbm_contact* out, int* n_out) {
+  if (!h || !n_out || capacity < 0 || (capacity > 0 && !out)) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (!c.fluid_ready) return fail(c, HLBM_E_STATE, "not initialised");
+  const PairTable& t = c.tab[c.cur];
+  std::vector<uint64_t> keys(t.cap);
+  std::vector<PairRec> rec(t.cap);
+  HIPCHECK(hipMemcpyAsync(keys.data(), t.keys, sizeof(uint64_t) * t.cap,
+                          hipMemcpyDeviceToHost, c.stream));
+  HIPCHECK(hipMemcpyAsync(rec.data(), t.rec, sizeof(PairRec) * t.cap,
+                          hipMemcpyDeviceToHost, c.stream));
+  HIPCHECK(hipStreamSynchronize(c.stream));
+  std::vector<std::pair<uint64_t, int>> order;
+  for (int s = 0; s < t.cap; ++s)
+    if (keys[s] != EMPTY_KEY) order.push_back({keys[s], s});
+  std::sort(order.begin(), order.end());
+  *n_out = (int)order.size();
+  const int m = std::min(capacity, (int)order.size());
+  for (int i = 0; i < m; ++i) {
+    const PairRec& r = rec[order[i].second];
+    hlbm_contact& o = out[i];
+    memset(&o, 0, sizeof o);
+    o.a = r.a;
+    o.b = r.b;
+    o.count = r.count;
+    for (int k = 0; k < 3; ++k) {
+      o.rlo[k] = r.count > 0 ? r.rlo[k] : 0;
+      o.rhi[k] = r.count > 0 ? r.rhi[k] : 0;
+      o.lo[k] = r.carried ? r.lo[k] : (double)r.rlo[k] - 0.5;
+      o.hi[k] = r.carried ? r.hi[k] : (double)r.rhi[k] + 0.5;
+      o.centroid[k] = r.centroid[k];
+      o.normal[k] = r.normal[k];
+      o.force_a[k] = r.force_a[k];
+      o.force_b[k] = -r.force_a[k];
+    }
+    o.carried = r.carried;
+    o.established = r.established;
+    o.damping = r.damping;
+    o.age = r.age;
+    o.n_in = r.n_in;
+    o.volume = r.volume;
+    o.depth = r.depth;
+    o.fn = r.fn;
+  }
+  return check_flags(c);
+}
+
+hlbm_status hlbm_read_fields(hlbm_ctx* h, double* rho, double* u, int* owner) {
+  if (!h) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (!c.fluid_ready) return fail(c, HLBM_E_STATE, "not initialised");
+  const size_t n = (size_t)c.g.ncell;
+  if (rho) {
+    HIPCHECK(launch_moment(c, c.fbuf[c.cur], -1, c.scratch));
+    HIPCHECK(hipMemcpyAsync(rho, c.scratch, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
+    HIPCHECK(hipStreamSynchronize(c.stream));
+  }
+  if (u) {
+    std::vector<double> tmp(n);
+    for (int k = 0; k < 3; ++k) {
+      HIPCHECK(launch_moment(c, c.fbuf[c.cur], k, c.scratch));
+      HIPCHECK(hipMemcpyAsync(tmp.data(), c.scratch, sizeof(double) * n,
+                              hipMemcpyDeviceToHost, c.stream));
+      HIPCHECK(hipStreamSynchronize(c.stream));
+      for (size_t i = 0; i < n; ++i) u[3 * i + k] = tmp[i];
+    }
+  }
+  if (owner)
+    HIPCHECK(hipMemcpyAsync(owner, c.owner, sizeof(int) * n, hipMemcpyDeviceToHost, c.stream));
+  HIPCHECK(hipStreamSynchronize(c.stream));
+  return check_flags(c);
+}
+
+hlbm_status hlbm_read_populations(hlbm_ctx* h, double* f) {
+  if (!h || !f) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (!c.fluid_ready) return fail(c, HLBM_E_STATE, "not initialised");
+  const size_t n = (size_t)c.g.ncell;
+  for (int i = 0; i < Q; ++i) {
+    HIPCHECK(launch_load_direction(c, c.fbuf[c.cur], i, c.scratch));
+    HIPCHECK(hipMemcpyAsync(f + (size_t)i * n, c.scratch, sizeof(double) * n,
+                            hipMemcpyDeviceToHost, c.stream));
+    HIPCHECK(hipStreamSynchronize(c.stream));
+  }
+  return check_flags(c);
+}
+
+hlbm_status hlbm_counters(hlbm_ctx* h, long long* pairs, long long* cells,
+                          long long* total_cells, long long* steps) {
+  if (!h) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  Counters k;
+  HIPCHECK(hipMemcpyAsync(&k, c.counters, sizeof k, hipMemcpyDeviceToHost, c.stream));
+  HIPCHECK(hipStreamSynchronize(c.stream));
+  if (pairs) *pairs = (long long)k.det_pairs;
+  if (cells) *cells = (long long)k.det_cells;
+  if (total_cells) *total_cells = (long long)k.total_cells;
+  if (steps) *steps = c.step;
+  return HLBM_OK;
+}
+
+void* hlbm_stream(const hlbm_ctx* h) { return h ? (void*)h->c.stream : nullptr; }
+
+hlbm_status hlbm_fluid_acceleration(const hlbm_ctx* h, double a[3]) {
+  if (!h || !a) return HLBM_E_ARG;
+  for (int k = 0; k < 3; ++k) a[k] = h->c.ph.a_ext[k];
+  return HLBM_OK;
+}
+
+const char* hlbm_last_error(const hlbm_ctx* h) {
+  return h ? h->c.err.c_str() : "null context";
+}
+
+void hlbm_destroy(hlbm_ctx* h) {
+  if (!h) return;
+  Ctx& c = h->c;
+  if (c.stream) hipStreamSynchronize(c.stream);
+  drop_graphs(c);
+  free_timing(c);
+  free_particles(c);
+  if (c.own_f) {
+    if (c.fbuf[0]) hipFree(c.fbuf[0]);
+    if (c.fbuf[1]) hipFree(c.fbuf[1]);
+  }
+  if (c.owner) hipFree(c.owner);
+  if (c.tile_block) hipFree(c.tile_block);
+  if (c.counters) hipFree(c.counters);
+  if (c.scratch) hipFree(c.scratch);
+  for (int k = 0; k < 2; ++k) {
+    if (c.tab[k].keys) hipFree(c.tab[k].keys);
+    if (c.tab[k].rec) hipFree(c.tab[k].rec);
+  }
+  if (c.own_stream && c.stream) hipStreamDestroy(c.stream);
+  delete h;
+}
+
+}  // extern "C"

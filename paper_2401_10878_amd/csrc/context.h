@@ -1,0 +1,148 @@
+// Host-side context of the library and the launch interface of each kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/hlbm.h"
+#include "device_math.h"
+
+namespace hlbm {
+
+// One contact-pair record of the open-addressing pair table.  count, rlo and
+// rhi are written with atomics by the rough detection; the rest is written
+// by the single wavefront that treats the record, or by the copy that
+// carries a kept contact into the next step's table.
+struct PairRec {
+  int a, b;
+  int count;
+  int rlo[3], rhi[3];
+  int carried, established, age, n_in, keep, pad;
+  double lo[3], hi[3];
+  double damping;
+  double volume, centroid[3], normal[3], depth, fn, force_a[3];
+};
+
+struct PairTable {
+  uint64_t* keys;   // [cap], EMPTY_KEY when free
+  PairRec* rec;     // [cap]
+  int cap;          // power of two
+};
+
+// Device counters and flags (one small block of device memory).
+struct Counters {
+  unsigned long long det_pairs;    // keys with count > 0 (latest detection)
+  unsigned long long det_cells;    // sum of counts (latest detection)
+  unsigned long long total_cells;  // sum over all detections
+  unsigned long long steps;
+  int tile_overflow;
+  int pair_overflow;
+  int unstable;
+  int pad;
+};
+
+// Scalar parameters handed to every kernel by value.
+struct Geom {
+  int nx, ny, nz;
+  int periodic_z;
+  int dtx, dty, dtz;      // detection tiles per axis (DX x DY x DZ nodes)
+  int ltx, lty, ltz;      // lattice blocks per axis (LX x LY x LZ nodes)
+  int tile_cap;           // particles per candidate list (both tilings)
+  int maxent;             // lattice blocks per particle (partial-sum slots)
+  long long ncell;
+};
+
+// Candidate lists of both tilings and the momentum-exchange partial sums.
+// dlist[t*cap + s]: particle ids reaching detection tile t.
+// llist[b*cap + s]: particle ids reaching lattice block b, lent[b*cap + s]:
+// index k of block b in that particle's own block enumeration;
+// part[(p*maxent + k)*6 + 0..5] = the (force, torque) the nodes of that
+// block contribute to particle p; nent[p] = blocks enumerated for p;
+// ovf[p*6 + ..] collects the rare contributions that do not fit the
+// per-lane slots.
+struct Tiles {
+  int* dcount;
+  int* dlist;
+  int* lcount;
+  int* llist;
+  int* lent;
+  int* nent;
+  double* part;
+  double* ovf;
+};
+
+struct Phys {
+  double tau, omega;      // relaxation time and 1/tau
+  double wall_u[2][3];
+  double gravity[3];
+  double a_ext[3];        // uniform fluid acceleration (incl. balance)
+  double eps, delta_c;
+  int n_c;
+  double estar;           // effective modulus, eq. (5)
+  double restitution, mu_s, mu_k, u_k;
+};
+
+constexpr int NKERN = 6;   // clear, treat, particles, keep, detect, lattice
+
+struct Ctx {
+  hlbm_params P;
+  Geom g;
+  Phys ph;
+  hipStream_t stream;
+  bool own_stream;
+  int precision;
+  size_t bytes_per_value;
+  // populations (two buffers, ping-pong); fbuf[cur] holds f* of the last step
+  void* fbuf[2];
+  bool own_f;
+  int cur;
+  // particles
+  int np;
+  Particles part;         // device pointers
+  void* part_block;       // one allocation for all particle arrays
+  double* Fh;             // [np][3] hydrodynamic force of the last step
+  double* Th;
+  double* Fc;             // contact force / torque of the last step
+  double* Tc;
+  // lattice-side maps
+  int* owner;             // [ncell]
+  Tiles tl;
+  void* tile_block;       // allocation holding count, list, ent
+  void* part_sums;        // allocation holding nent, part, ovf
+  // contacts
+  PairTable tab[2];
+  int tcur;               // tab[tcur] = current contact list
+  Counters* counters;     // device
+  double* scratch;        // [ncell] FP64 staging for host conversions
+  // state
+  bool particles_ready, fluid_ready;
+  long long step;
+  // per-kernel timing: NKERN+1 events per step, a pool for `tcap` steps
+  bool timing;
+  int tcap, tused;
+  hipEvent_t* tev;
+  // graphs: one per parity of (cur, fcur, tcur)
+  bool use_graph;
+  hipGraphExec_t gexec[2];
+  bool graph_ready[2];
+  std::string err;
+};
+
+// ---- launch wrappers (kernels live in the .hip files) --------------------
+hipError_t launch_clear_step(Ctx& c, PairTable next);
+hipError_t launch_particles(Ctx& c, int move);
+hipError_t launch_keep(Ctx& c, PairTable from, PairTable to);
+hipError_t launch_detect(Ctx& c, PairTable to);
+hipError_t launch_lattice(Ctx& c, const void* src, void* dst);
+hipError_t launch_mea_only(Ctx& c, const void* fstar);
+hipError_t launch_treat(Ctx& c, PairTable t);
+hipError_t launch_fill_equilibrium(Ctx& c, void* f, double rho,
+                                   const double u[3]);
+hipError_t launch_store_direction(Ctx& c, void* f, int i, const double* src);
+hipError_t launch_load_direction(Ctx& c, const void* f, int i, double* dst);
+// comp = -1: density, 0..2: velocity component of f* (FP64, into out[ncell])
+hipError_t launch_moment(Ctx& c, const void* f, int comp, double* out);
+
+}  // namespace hlbm

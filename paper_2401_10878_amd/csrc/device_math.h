@@ -1,0 +1,249 @@
+// Device-side building blocks shared by the gfx950 kernels: the D3Q19
+// velocity set, particle geometry (rotation, signed distances, coupling
+// weight) and small wavefront reductions.
+//
+// The signed distances and predicates that decide integer results (node
+// ownership, detection sets, inside-samples of the overlap integration) are
+// written as explicit left-to-right FP64 expressions and the library is
+// built with -ffp-contract=off, so every node and sample gets the value the
+// formula defines, independent of the launch shape.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hlbm {
+
+constexpr int Q = 19;
+// Two tilings of the lattice, each with a per-tile particle candidate list:
+//  - detection tiles of 4 x 4 x 4 nodes, one wavefront each (compact, so
+//    few particles reach a tile);
+//  - lattice blocks of 64 x 4 x 1 nodes, one workgroup of four wavefronts,
+//    each wavefront streaming one 64-node x-row (full-width coalesced rows).
+constexpr int DX = 4, DY = 4, DZ = 4;
+constexpr int LX = 64, LY = 4, LZ = 1;
+constexpr int LCAP_MAX = 64;    // lattice-block candidate capacity
+constexpr int WAVE = 64;
+constexpr double DETECT = 0.8660254037844386;   // sqrt(0.75), Sec. 3.3.1
+constexpr double PI = 3.141592653589793;
+constexpr uint64_t EMPTY_KEY = ~0ull;
+
+// D3Q19 (Sec. 3.1): rest, the six axis directions, the twelve edge
+// directions; each direction is followed by its opposite.
+__host__ __device__ constexpr int cx(int i) {
+  constexpr int t[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  return t[i];
+}
+__host__ __device__ constexpr int cy(int i) {
+  constexpr int t[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  return t[i];
+}
+__host__ __device__ constexpr int cz(int i) {
+  constexpr int t[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  return t[i];
+}
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__host__ __device__ constexpr double wgt(int i) {
+  return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// Particle record in device memory (structure of arrays, FP64).
+struct Particles {
+  int n;
+  const int* shape;     // 0 sphere, 1 cube
+  const double* size;   // radius or edge
+  const double* dens;   // density ratio s
+  const double* vol;    // volume
+  const double* mass;   // s * V
+  const double* inert;  // isotropic moment of inertia
+  double* X;            // [n][3]
+  double* q;            // [n][4]
+  double* U;            // [n][3]
+  double* W;            // [n][3] angular velocity
+  double* R;            // [n][9] rotation (body -> world), row-major
+};
+
+// Rotation matrix of q = (w, x, y, z).
+__device__ inline void quat_to_rot(const double* q, double* R) {
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0] = 1.0 - 2.0 * (y * y + z * z);
+  R[1] = 2.0 * (x * y - w * z);
+  R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z);
+  R[4] = 1.0 - 2.0 * (x * x + z * z);
+  R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y);
+  R[7] = 2.0 * (y * z + w * x);
+  R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// Minimal image of a coordinate difference on an axis of length L.
+__device__ inline double minimg(double v, double L, bool periodic) {
+  if (!periodic) return v;
+  if (v >= 0.5 * L) return v - L;
+  if (v < -0.5 * L) return v + L;
+  return v;
+}
+__device__ inline int image_shift(double v, double L, bool periodic) {
+  if (!periodic) return 0;
+  if (v >= 0.5 * L) return -1;
+  if (v < -0.5 * L) return 1;
+  return 0;
+}
+
+// Exact signed distance (negative inside) at world offset r from the centre.
+// sphere: |r| - radius.  cube (edge a): body offset p = R^T r,
+// q_k = |p_k| - a/2, d = |max(q, 0)| + min(max_k q_k, 0).
+__device__ inline double sdf(int shape, double size, const double* R,
+                             double r0, double r1, double r2) {
+  if (shape == 0) {
+    const double n2 = r0 * r0 + r1 * r1 + r2 * r2;
+    return sqrt(n2) - size;
+  }
+  const double h = 0.5 * size;
+  const double p0 = R[0] * r0 + R[3] * r1 + R[6] * r2;
+  const double p1 = R[1] * r0 + R[4] * r1 + R[7] * r2;
+  const double p2 = R[2] * r0 + R[5] * r1 + R[8] * r2;
+  const double q0 = fabs(p0) - h, q1 = fabs(p1) - h, q2 = fabs(p2) - h;
+  const double m0 = fmax(q0, 0.0), m1 = fmax(q1, 0.0), m2 = fmax(q2, 0.0);
+  const double outside = sqrt(m0 * m0 + m1 * m1 + m2 * m2);
+  const double inside = fmin(fmax(fmax(q0, q1), q2), 0.0);
+  return outside + inside;
+}
+
+// Signed distance with its world-frame gradient.  Inside a cube the
+// gradient is the normal of the nearest face (ties to the lowest axis);
+// at a sphere's centre it is zero.
+__device__ inline double sdf_grad(int shape, double size, const double* R,
+                                  const double* r, double* g) {
+  if (shape == 0) {
+    const double n2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const double n = sqrt(n2);
+    for (int k = 0; k < 3; ++k) g[k] = n > 0.0 ? r[k] / n : 0.0;
+    return n - size;
+  }
+  const double h = 0.5 * size;
+  double p[3], qd[3], m[3];
+  for (int k = 0; k < 3; ++k) {
+    p[k] = R[0 + k] * r[0] + R[3 + k] * r[1] + R[6 + k] * r[2];
+    qd[k] = fabs(p[k]) - h;
+    m[k] = fmax(qd[k], 0.0);
+  }
+  const double outside = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+  const double inside = fmin(fmax(fmax(qd[0], qd[1]), qd[2]), 0.0);
+  double gb[3] = {0.0, 0.0, 0.0};
+  if (outside > 0.0) {
+    for (int k = 0; k < 3; ++k) gb[k] = (p[k] < 0.0 ? -1.0 : 1.0) * m[k] / outside;
+  } else {
+    int km = 0;
+    if (qd[1] > qd[km]) km = 1;
+    if (qd[2] > qd[km]) km = 2;
+    gb[km] = p[km] < 0.0 ? -1.0 : 1.0;
+  }
+  for (int k = 0; k < 3; ++k)
+    g[k] = R[3 * k + 0] * gb[0] + R[3 * k + 1] * gb[1] + R[3 * k + 2] * gb[2];
+  return outside + inside;
+}
+
+// Coupling weight B(d): 1 for d <= -eps/2, 0 for d >= eps/2, cos^2 ramp.
+__device__ inline double weight(double d, double eps) {
+  if (d <= -0.5 * eps) return 1.0;
+  if (d >= 0.5 * eps) return 0.0;
+  const double c = cos(PI * (d + 0.5 * eps) / (2.0 * eps));
+  return c * c;
+}
+
+// ---- wavefront reductions (64 lanes) -------------------------------------
+// All-lane reductions built from DPP row rotations (row_ror 8, 4, 2, 1 within
+// each row of 16 lanes) and four readlanes, so no data goes through LDS and
+// the combination order is fixed.  Callers keep all 64 lanes active.
+template <int K>
+__device__ inline int ror_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x120 + K, 0xf, 0xf, false);
+}
+template <int K>
+__device__ inline double ror_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(ror_i<K>(hi), ror_i<K>(lo));
+}
+__device__ inline double lane_d(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ inline double wave_sum(double v) {
+  v += ror_d<8>(v);
+  v += ror_d<4>(v);
+  v += ror_d<2>(v);
+  v += ror_d<1>(v);
+  return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
+}
+__device__ inline double wave_min(double v) {
+  v = fmin(v, ror_d<8>(v));
+  v = fmin(v, ror_d<4>(v));
+  v = fmin(v, ror_d<2>(v));
+  v = fmin(v, ror_d<1>(v));
+  return fmin(fmin(lane_d(v, 0), lane_d(v, 16)), fmin(lane_d(v, 32), lane_d(v, 48)));
+}
+__device__ inline double wave_max(double v) {
+  v = fmax(v, ror_d<8>(v));
+  v = fmax(v, ror_d<4>(v));
+  v = fmax(v, ror_d<2>(v));
+  v = fmax(v, ror_d<1>(v));
+  return fmax(fmax(lane_d(v, 0), lane_d(v, 16)), fmax(lane_d(v, 32), lane_d(v, 48)));
+}
+__device__ inline int wave_sum_i(int v) {
+  v += ror_i<8>(v);
+  v += ror_i<4>(v);
+  v += ror_i<2>(v);
+  v += ror_i<1>(v);
+  return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+         (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
+}
+__device__ inline int wave_min_i(int v) {
+  v = min(v, ror_i<8>(v));
+  v = min(v, ror_i<4>(v));
+  v = min(v, ror_i<2>(v));
+  v = min(v, ror_i<1>(v));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+__device__ inline int wave_max_i(int v) {
+  v = max(v, ror_i<8>(v));
+  v = max(v, ror_i<4>(v));
+  v = max(v, ror_i<2>(v));
+  v = max(v, ror_i<1>(v));
+  return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+__device__ inline uint64_t wave_or_u64(uint64_t v) {
+  int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+  lo |= ror_i<8>(lo); hi |= ror_i<8>(hi);
+  lo |= ror_i<4>(lo); hi |= ror_i<4>(hi);
+  lo |= ror_i<2>(lo); hi |= ror_i<2>(hi);
+  lo |= ror_i<1>(lo); hi |= ror_i<1>(hi);
+  uint32_t l = 0, h = 0;
+  for (int r = 0; r < 64; r += 16) {
+    l |= (uint32_t)__builtin_amdgcn_readlane(lo, r);
+    h |= (uint32_t)__builtin_amdgcn_readlane(hi, r);
+  }
+  return ((uint64_t)h << 32) | l;
+}
+
+__device__ inline void atomic_add_f64(double* p, double v) {
+  unsafeAtomicAdd(p, v);
+}
+
+// Hash of a pair key (a << 32 | b + 2) for the open-addressing pair table.
+__host__ __device__ inline uint32_t pair_hash(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return (uint32_t)k;
+}
+__host__ __device__ inline uint64_t pair_key(int a, int b) {
+  return ((uint64_t)(uint32_t)a << 32) | (uint64_t)(uint32_t)(b + 2);
+}
+
+}  // namespace hlbm

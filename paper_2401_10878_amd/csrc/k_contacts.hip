@@ -1,0 +1,351 @@
+// Discrete contact treatment (Sec. 3.3.1, eqs. (4)-(9)) and the per-step
+// bookkeeping of the pair tables.
+//
+// One wavefront treats one contact record:
+//   box      the carried (corrected) box of an established contact, or the
+//            rough box [min - 1/2, max + 1/2] of the flagged node images;
+//            kept in the frame of the lower-id particle a (Sec. 3.3.2)
+//   correct  faces -x,+x,-y,+y,-z,+z in turn; N_c x N_c midpoint samples of
+//            phi = max(d'_a, d'_b) on the face (one per lane); the face
+//            moves inwards by the wave minimum of phi
+//   integrate N_c^3 midpoint samples of the box; inside = both enlarged
+//            distances negative; wave sums of count, position and gradient
+//            difference, wave maximum of -(d'_a + d'_b)
+//   force    normal force (4, 5, 6) and friction (7-9) at the centroid,
+//            committed to both particles with FP64 atomics.
+#include <float.h>
+
+#include "context.h"
+
+namespace hlbm {
+
+namespace {
+
+__global__ void k_clear_step(PairTable next, double* Fc, double* Tc, int np,
+                             int* dcount, long long ndt, int* lcount,
+                             long long nlt, Counters* ctr) {
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = tid; i < next.cap; i += stride) {
+    next.keys[i] = EMPTY_KEY;
+    PairRec r = {};
+    for (int k = 0; k < 3; ++k) {
+      r.rlo[k] = 0x7fffffff;
+      r.rhi[k] = (int)0x80000000;
+    }
+    next.rec[i] = r;
+  }
+  for (long long i = tid; i < ndt; i += stride) dcount[i] = 0;
+  for (long long i = tid; i < nlt; i += stride) lcount[i] = 0;
+  for (long long i = tid; i < 3LL * np; i += stride) {
+    Fc[i] = 0.0;
+    Tc[i] = 0.0;
+  }
+  if (tid == 0) {
+    ctr->det_pairs = 0;
+    ctr->det_cells = 0;
+  }
+}
+
+__global__ void k_keep(PairTable from, PairTable to, Counters* ctr) {
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= from.cap) return;
+  const uint64_t key = from.keys[s];
+  if (key == EMPTY_KEY) return;
+  const PairRec& r = from.rec[s];
+  if (!r.keep) return;
+  const uint32_t mask = (uint32_t)to.cap - 1u;
+  uint32_t h = pair_hash(key) & mask;
+  for (int probe = 0; probe < to.cap; ++probe) {
+    unsigned long long old = atomicCAS((unsigned long long*)&to.keys[h],
+                                       (unsigned long long)EMPTY_KEY,
+                                       (unsigned long long)key);
+    if (old == EMPTY_KEY || old == key) {
+      PairRec& d = to.rec[h];
+      d.a = r.a;
+      d.b = r.b;
+      d.carried = 1;
+      d.established = r.established;
+      d.age = r.age;
+      d.n_in = r.n_in;
+      d.keep = 0;
+      for (int k = 0; k < 3; ++k) {
+        d.lo[k] = r.lo[k];
+        d.hi[k] = r.hi[k];
+        d.centroid[k] = r.centroid[k];
+        d.normal[k] = r.normal[k];
+        d.force_a[k] = r.force_a[k];
+      }
+      d.damping = r.damping;
+      d.volume = r.volume;
+      d.depth = r.depth;
+      d.fn = r.fn;
+      return;
+    }
+    h = (h + 1u) & mask;
+  }
+  atomicOr(&ctr->pair_overflow, 1);
+}
+
+struct Body {
+  int shape;
+  double size, X[3], R[9];
+};
+
+__device__ inline double body_sdf(const Body& b, const double* y, double* g) {
+  const double r[3] = {y[0] - b.X[0], y[1] - b.X[1], y[2] - b.X[2]};
+  if (g) return sdf_grad(b.shape, b.size, b.R, r, g);
+  return sdf(b.shape, b.size, b.R, r[0], r[1], r[2]);
+}
+
+// enlarged distance of member b (particle, or wall -1 bottom / -2 top)
+__device__ inline double member_sdf(const Body& b, int bid, double delta,
+                                    double nz, const double* y, double* g) {
+  if (bid >= 0) return body_sdf(b, y, g) - delta;
+  if (bid == -1) {
+    if (g) { g[0] = 0.0; g[1] = 0.0; g[2] = 1.0; }
+    return y[2] + 0.5;
+  }
+  if (g) { g[0] = 0.0; g[1] = 0.0; g[2] = -1.0; }
+  return (nz - 0.5) - y[2];
+}
+
+__device__ inline void cross3(const double* a, const double* b, double* o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__global__ __launch_bounds__(256) void k_treat(PairTable t, Particles P, Geom g,
+                                               Phys ph, double* Fc, double* Tc) {
+  const int lane = threadIdx.x % WAVE;
+  const long long slot = (long long)blockIdx.x * 4 + threadIdx.x / WAVE;
+  if (slot >= t.cap) return;
+  if (t.keys[slot] == EMPTY_KEY) return;
+  PairRec* rec = &t.rec[slot];
+  const int a = __builtin_amdgcn_readfirstlane(rec->a);
+  const int b = __builtin_amdgcn_readfirstlane(rec->b);
+  const bool perz = g.periodic_z != 0;
+  const double L[3] = {(double)g.nx, (double)g.ny, (double)g.nz};
+  const bool per[3] = {true, true, perz};
+  const int nc = ph.n_c;
+  const double delta = ph.delta_c;
+
+  Body A, Bb;
+  A.shape = P.shape[a];
+  A.size = P.size[a];
+  for (int k = 0; k < 3; ++k) A.X[k] = P.X[3 * a + k];
+  for (int k = 0; k < 9; ++k) A.R[k] = P.R[9 * a + k];
+  Bb.shape = 0;
+  Bb.size = 0.0;
+  for (int k = 0; k < 3; ++k) Bb.X[k] = 0.0;
+  for (int k = 0; k < 9; ++k) Bb.R[k] = 0.0;
+  if (b >= 0) {
+    Bb.shape = P.shape[b];
+    Bb.size = P.size[b];
+    // the higher-id particle is moved next to the lower-id one
+    for (int k = 0; k < 3; ++k)
+      Bb.X[k] = A.X[k] + minimg(P.X[3 * b + k] - A.X[k], L[k], per[k]);
+    for (int k = 0; k < 9; ++k) Bb.R[k] = P.R[9 * b + k];
+  }
+
+  double lo[3], hi[3];
+  const bool carried = rec->carried != 0;
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = carried ? rec->lo[k] : (double)rec->rlo[k] - 0.5;
+    hi[k] = carried ? rec->hi[k] : (double)rec->rhi[k] + 0.5;
+    const double mid = 0.5 * (lo[k] + hi[k]);
+    const int sh = image_shift(mid - A.X[k], L[k], per[k]);
+    lo[k] += (double)(sh * (int)L[k]);
+    hi[k] += (double)(sh * (int)L[k]);
+  }
+
+  // ---- box correction, one pass -----------------------------------------
+  bool ok = true;
+  for (int face = 0; face < 6 && ok; ++face) {
+    for (int k = 0; k < 3; ++k)
+      if (!(hi[k] > lo[k])) ok = false;
+    if (!ok) break;
+    const int k = face / 2, plus = face % 2;
+    const int u = k == 0 ? 1 : 0, v = k == 2 ? 1 : 2;
+    const double hu = (hi[u] - lo[u]) / (double)nc;
+    const double hv = (hi[v] - lo[v]) / (double)nc;
+    double smin = DBL_MAX;
+    for (int idx = lane; idx < nc * nc; idx += WAVE) {
+      const int j = idx / nc, l = idx % nc;
+      double y[3];
+      y[k] = plus ? hi[k] : lo[k];
+      y[u] = lo[u] + ((double)j + 0.5) * hu;
+      y[v] = lo[v] + ((double)l + 0.5) * hv;
+      const double da = body_sdf(A, y, nullptr) - delta;
+      const double db = member_sdf(Bb, b, delta, L[2], y, nullptr);
+      smin = fmin(smin, fmax(da, db));
+    }
+    smin = wave_min(smin);
+    if (plus) hi[k] = hi[k] - smin;
+    else lo[k] = lo[k] + smin;
+  }
+  if (ok)
+    for (int k = 0; k < 3; ++k)
+      if (!(hi[k] > lo[k])) ok = false;
+
+  // ---- overlap integration ------------------------------------------------
+  int n_in = 0;
+  double sy[3] = {0.0, 0.0, 0.0}, gs[3] = {0.0, 0.0, 0.0};
+  double dmax = -DBL_MAX;
+  double h[3] = {0.0, 0.0, 0.0};
+  if (ok) {
+    for (int k = 0; k < 3; ++k) h[k] = (hi[k] - lo[k]) / (double)nc;
+    const int ns = nc * nc * nc;
+    for (int idx = lane; idx < ns; idx += WAVE) {
+      const int j = idx % nc, kk = (idx / nc) % nc, l = idx / (nc * nc);
+      double y[3], ga[3], gb[3];
+      y[0] = lo[0] + ((double)j + 0.5) * h[0];
+      y[1] = lo[1] + ((double)kk + 0.5) * h[1];
+      y[2] = lo[2] + ((double)l + 0.5) * h[2];
+      const double da = body_sdf(A, y, ga) - delta;
+      const double db = member_sdf(Bb, b, delta, L[2], y, gb);
+      if (fmax(da, db) < 0.0) {
+        n_in++;
+        dmax = fmax(dmax, -(da + db));
+        for (int m = 0; m < 3; ++m) {
+          sy[m] += y[m];
+          gs[m] += ga[m] - gb[m];
+        }
+      }
+    }
+    n_in = wave_sum_i(n_in);
+    for (int m = 0; m < 3; ++m) {
+      sy[m] = wave_sum(sy[m]);
+      gs[m] = wave_sum(gs[m]);
+    }
+    dmax = wave_max(dmax);
+  }
+  if (!ok || n_in == 0) {
+    if (lane == 0) {
+      rec->keep = 0;
+      rec->n_in = 0;
+      rec->volume = 0.0;
+    }
+    return;
+  }
+
+  // ---- results and forces (wave-uniform values) ----------------------------
+  const double V = (double)n_in * (h[0] * h[1] * h[2]);
+  double xc[3], nrm[3] = {0.0, 0.0, 0.0};
+  for (int m = 0; m < 3; ++m) xc[m] = sy[m] / (double)n_in;
+  const double gn = sqrt(gs[0] * gs[0] + gs[1] * gs[1] + gs[2] * gs[2]);
+  if (gn > 0.0) {
+    for (int m = 0; m < 3; ++m) nrm[m] = gs[m] / gn;
+  } else {
+    double dv[3];
+    if (b >= 0) {
+      for (int m = 0; m < 3; ++m) dv[m] = Bb.X[m] - A.X[m];
+    } else {
+      dv[0] = 0.0; dv[1] = 0.0; dv[2] = b == -1 ? -1.0 : 1.0;
+    }
+    const double dn = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    if (dn > 0.0)
+      for (int m = 0; m < 3; ++m) nrm[m] = dv[m] / dn;
+  }
+  const double depth = dmax;
+
+  double ra[3], t3[3], va[3], vb[3] = {0.0, 0.0, 0.0};
+  for (int m = 0; m < 3; ++m) ra[m] = xc[m] - A.X[m];
+  cross3(P.W + 3 * a, ra, t3);
+  for (int m = 0; m < 3; ++m) va[m] = P.U[3 * a + m] + t3[m];
+  double rb[3] = {0.0, 0.0, 0.0};
+  if (b >= 0) {
+    for (int m = 0; m < 3; ++m) rb[m] = xc[m] - Bb.X[m];
+    cross3(P.W + 3 * b, rb, t3);
+    for (int m = 0; m < 3; ++m) vb[m] = P.U[3 * b + m] + t3[m];
+  }
+  double v[3];
+  for (int m = 0; m < 3; ++m) v[m] = va[m] - vb[m];
+  const double dn = v[0] * nrm[0] + v[1] * nrm[1] + v[2] * nrm[2];
+  int established = rec->established;
+  double damping = rec->damping;
+  if (!established) {
+    const double e = ph.restitution;
+    damping = dn > 0.0 ? 1.5 * (1.0 - e) * (11.0 - e) / ((1.0 + 9.0 * e) * dn) : 0.0;
+    established = 1;
+  }
+  double fn = 4.0 / (3.0 * PI) * ph.estar * sqrt(V * depth) * (1.0 + damping * dn);
+  if (fn < 0.0) fn = 0.0;
+  double vt[3];
+  for (int m = 0; m < 3; ++m) vt[m] = v[m] - dn * nrm[m];
+  const double vtn = sqrt(vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2]);
+  double ft[3] = {0.0, 0.0, 0.0};
+  if (vtn > 0.0) {
+    const double aa = vtn / ph.u_k;
+    const double rr = ph.mu_k / ph.mu_s;
+    const double mus = ph.mu_s * (1.0 - 0.09 * (rr * rr * rr * rr));
+    const double a2 = aa * aa;
+    const double mu = (2.0 * mus - ph.mu_k) * a2 / (a2 * a2 + 1.0) + ph.mu_k -
+                      ph.mu_k / (a2 + 1.0);
+    for (int m = 0; m < 3; ++m) ft[m] = -(vt[m] / vtn) * mu * fn;
+  }
+  double Fa[3], Fb[3], Ta[3], Tb[3];
+  for (int m = 0; m < 3; ++m) {
+    Fa[m] = -fn * nrm[m] + ft[m];
+    Fb[m] = -Fa[m];
+  }
+  cross3(ra, Fa, Ta);
+  if (b >= 0) cross3(rb, Fb, Tb);
+  if (lane == 0) {
+    for (int m = 0; m < 3; ++m) {
+      atomic_add_f64(&Fc[3 * a + m], Fa[m]);
+      atomic_add_f64(&Tc[3 * a + m], Ta[m]);
+      if (b >= 0) {
+        atomic_add_f64(&Fc[3 * b + m], Fb[m]);
+        atomic_add_f64(&Tc[3 * b + m], Tb[m]);
+      }
+    }
+    rec->keep = 1;
+    rec->carried = 1;
+    rec->established = established;
+    rec->damping = damping;
+    rec->age = rec->age + 1;
+    rec->n_in = n_in;
+    rec->volume = V;
+    rec->depth = depth;
+    rec->fn = fn;
+    for (int m = 0; m < 3; ++m) {
+      rec->lo[m] = lo[m];
+      rec->hi[m] = hi[m];
+      rec->centroid[m] = xc[m];
+      rec->normal[m] = nrm[m];
+      rec->force_a[m] = Fa[m];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_clear_step(Ctx& c, PairTable next) {
+  const long long ndt = (long long)c.g.dtx * c.g.dty * c.g.dtz;
+  const long long nlt = (long long)c.g.ltx * c.g.lty * c.g.ltz;
+  long long work = next.cap;
+  if (ndt > work) work = ndt;
+  if (3LL * c.np > work) work = 3LL * c.np;
+  long long blocks = (work + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_clear_step, dim3((unsigned)blocks), dim3(256), 0,
+                     c.stream, next, c.Fc, c.Tc, c.np, c.tl.dcount, ndt,
+                     c.tl.lcount, nlt, c.counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_keep(Ctx& c, PairTable from, PairTable to) {
+  hipLaunchKernelGGL(k_keep, dim3((unsigned)((from.cap + 255) / 256)), dim3(256),
+                     0, c.stream, from, to, c.counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_treat(Ctx& c, PairTable t) {
+  hipLaunchKernelGGL(k_treat, dim3((unsigned)((t.cap + 3) / 4)), dim3(256), 0,
+                     c.stream, t, c.part, c.g, c.ph, c.Fc, c.Tc);
+  return hipGetLastError();
+}
+
+}  // namespace hlbm

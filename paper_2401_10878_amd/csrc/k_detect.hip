@@ -1,0 +1,151 @@
+// Particle-to-fluid coupling map and rough contact detection (Sec. 3.2,
+// Sec. 3.3.1-3.3.2), node-parallel.
+//
+// One wavefront per tile of TX x TY x TZ nodes.  The tile's candidate list is
+// wave-uniform, so each candidate's record is fetched once per wavefront
+// through scalar loads, and every lane evaluates that candidate's signed
+// distance at its node.  Per node:
+//   owner  = argmin over candidates with d < eps/2 of (d, id)
+//   K(x)   = candidates with d - delta_c < sqrt(0.75), plus the walls whose
+//            distance is below sqrt(0.75)
+// Pairs are aggregated over the wavefront with ballots and min/max shuffles
+// (count of flagged nodes, bounding box of their images in the frame of the
+// lower-id particle) and then committed with one set of atomics per pair
+// and tile into the open-addressing pair table.
+#include "context.h"
+
+namespace hlbm {
+
+namespace {
+
+__device__ int table_slot(PairTable t, uint64_t key, Counters* ctr) {
+  const uint32_t mask = (uint32_t)t.cap - 1u;
+  uint32_t h = pair_hash(key) & mask;
+  for (int probe = 0; probe < t.cap; ++probe) {
+    unsigned long long old = atomicCAS((unsigned long long*)&t.keys[h],
+                                       (unsigned long long)EMPTY_KEY,
+                                       (unsigned long long)key);
+    if (old == EMPTY_KEY || old == key) return (int)h;
+    h = (h + 1u) & mask;
+  }
+  atomicOr(&ctr->pair_overflow, 1);
+  return -1;
+}
+
+// Commit one pair seen by the lanes in `bal` with node images img.
+__device__ void commit_pair(PairTable t, Counters* ctr, int a, int b,
+                            uint64_t bal, bool pred, const int img[3]) {
+  const int cnt = __popcll(bal);
+  int lo[3], hi[3];
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = wave_min_i(pred ? img[k] : 0x7fffffff);
+    hi[k] = wave_max_i(pred ? img[k] : (int)0x80000000);
+  }
+  if (threadIdx.x % WAVE == 0) {
+    const int s = table_slot(t, pair_key(a, b), ctr);
+    if (s >= 0) {
+      PairRec* r = &t.rec[s];
+      r->a = a;
+      r->b = b;
+      const int old = atomicAdd(&r->count, cnt);
+      if (old == 0) atomicAdd(&ctr->det_pairs, 1ull);
+      for (int k = 0; k < 3; ++k) {
+        atomicMin(&r->rlo[k], lo[k]);
+        atomicMax(&r->rhi[k], hi[k]);
+      }
+      atomicAdd(&ctr->det_cells, (unsigned long long)cnt);
+      atomicAdd(&ctr->total_cells, (unsigned long long)cnt);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
+                                                Tiles tl, int* __restrict__ owner,
+                                                PairTable tab, Counters* ctr) {
+  const int lane = threadIdx.x % WAVE;
+  const long long ntiles = (long long)g.dtx * g.dty * g.dtz;
+  const long long tile = (long long)blockIdx.x * 4 + threadIdx.x / WAVE;
+  if (tile >= ntiles) return;                     // whole wavefront exits
+  const int tx = (int)(tile % g.dtx);
+  const int ty = (int)((tile / g.dtx) % g.dty);
+  const int tz = (int)(tile / ((long long)g.dtx * g.dty));
+  const int x = tx * DX + (lane % DX);
+  const int y = ty * DY + (lane / DX) % DY;
+  const int z = tz * DZ + lane / (DX * DY);
+  const bool valid = x < g.nx && y < g.ny && z < g.nz;
+  const bool perz = g.periodic_z != 0;
+  const double fx = (double)x, fy = (double)y, fz = (double)z;
+  const double Lx = (double)g.nx, Ly = (double)g.ny, Lz = (double)g.nz;
+
+  int cnt = tl.dcount[tile];
+  cnt = __builtin_amdgcn_readfirstlane(cnt < g.tile_cap ? cnt : g.tile_cap);
+  const int* list = tl.dlist + tile * g.tile_cap;
+
+  double bd = 1.0e300;
+  int bp = -1;
+  uint64_t mask = 0;
+  for (int c = 0; c < cnt; ++c) {
+    const int p = __builtin_amdgcn_readfirstlane(list[c]);
+    const double X0 = P.X[3 * p], X1 = P.X[3 * p + 1], X2 = P.X[3 * p + 2];
+    const double* R = P.R + 9 * p;
+    const double r0 = minimg(fx - X0, Lx, true);
+    const double r1 = minimg(fy - X1, Ly, true);
+    const double r2 = minimg(fz - X2, Lz, perz);
+    const double d = sdf(P.shape[p], P.size[p], R, r0, r1, r2);
+    if (valid && d < 0.5 * ph.eps && (d < bd || (d == bd && p < bp))) {
+      bd = d;
+      bp = p;
+    }
+    if (valid && d - ph.delta_c < DETECT) mask |= 1ull << c;
+  }
+  if (valid) owner[(long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z)] = bp;
+
+  const uint64_t orm = wave_or_u64(mask);
+  if (orm == 0) return;
+  const bool wbot = valid && !perz && (fz + 0.5 < DETECT);
+  const bool wtop = valid && !perz && ((Lz - 0.5) - fz < DETECT);
+  const bool anywall = __ballot(wbot || wtop) != 0;
+
+  for (int i = 0; i < cnt; ++i) {
+    if (!((orm >> i) & 1ull)) continue;
+    const int pi = __builtin_amdgcn_readfirstlane(list[i]);
+    const bool in_i = (mask >> i) & 1ull;
+    for (int j = i + 1; j < cnt; ++j) {
+      if (!((orm >> j) & 1ull)) continue;
+      const bool pred = in_i && ((mask >> j) & 1ull);
+      const uint64_t bal = __ballot(pred);
+      if (bal == 0) continue;
+      const int pj = __builtin_amdgcn_readfirstlane(list[j]);
+      const int a = pi < pj ? pi : pj, b = pi < pj ? pj : pi;
+      int img[3];
+      img[0] = x + g.nx * image_shift(fx - P.X[3 * a], Lx, true);
+      img[1] = y + g.ny * image_shift(fy - P.X[3 * a + 1], Ly, true);
+      img[2] = z + g.nz * image_shift(fz - P.X[3 * a + 2], Lz, perz);
+      commit_pair(tab, ctr, a, b, bal, pred, img);
+    }
+    if (anywall) {
+      int img[3];
+      img[0] = x + g.nx * image_shift(fx - P.X[3 * pi], Lx, true);
+      img[1] = y + g.ny * image_shift(fy - P.X[3 * pi + 1], Ly, true);
+      img[2] = z;
+      const bool pb = in_i && wbot;
+      const uint64_t bb = __ballot(pb);
+      if (bb) commit_pair(tab, ctr, pi, -1, bb, pb, img);
+      const bool pt = in_i && wtop;
+      const uint64_t bt = __ballot(pt);
+      if (bt) commit_pair(tab, ctr, pi, -2, bt, pt, img);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_detect(Ctx& c, PairTable to) {
+  const long long ntiles = (long long)c.g.dtx * c.g.dty * c.g.dtz;
+  const unsigned blocks = (unsigned)((ntiles + 3) / 4);
+  hipLaunchKernelGGL(k_detect, dim3(blocks), dim3(256), 0, c.stream, c.part,
+                     c.g, c.ph, c.tl, c.owner, to, c.counters);
+  return hipGetLastError();
+}
+
+}  // namespace hlbm

@@ -1,0 +1,220 @@
+// Particle motion (eqs. (2)-(3)) and tile binning for the node kernels.
+//
+// One wavefront per particle:
+//  1. (moving steps) gather the hydrodynamic force and torque of the last
+//     lattice pass: the sum of this particle's per-tile partial sums, in the
+//     fixed order of its tile enumeration (deterministic, no atomics);
+//  2. every lane evaluates the same FP64 Newton-Euler update (the result is
+//     wave-uniform) and lane 0 stores it;
+//  3. the lanes enumerate the tiles the particle's reach box touches and
+//     append (particle id, enumeration index) to each tile's candidate list.
+#include "context.h"
+
+namespace hlbm {
+
+namespace {
+
+// A set of at most two disjoint tile intervals on one axis.
+struct TileSpan {
+  int lo[2], hi[2], n;
+  __device__ int count() const {
+    int c = 0;
+    for (int k = 0; k < n; ++k) c += hi[k] - lo[k] + 1;
+    return c;
+  }
+  __device__ int at(int i) const {
+    const int len0 = hi[0] - lo[0] + 1;
+    return i < len0 ? lo[0] + i : lo[1] + (i - len0);
+  }
+};
+
+__device__ inline int wrapi(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+// Tiles (of ts nodes) touched by the node interval [floor(c-e), ceil(c+e)]
+// on an axis of n nodes and nt tiles; periodic axes wrap, bounded axes clip.
+__device__ TileSpan axis_tiles(double c, double e, int n, int nt, int ts,
+                               bool periodic) {
+  TileSpan s;
+  s.n = 0;
+  int lo = (int)floor(c - e), hi = (int)ceil(c + e);
+  if (periodic) {
+    if (hi - lo + 1 >= n) {
+      s.lo[0] = 0; s.hi[0] = nt - 1; s.n = 1;
+      return s;
+    }
+    const int a = wrapi(lo, n), b = wrapi(hi, n);
+    if (a <= b) {
+      s.lo[0] = a / ts; s.hi[0] = b / ts; s.n = 1;
+    } else {
+      const int t0 = a / ts, t1 = b / ts;
+      if (t1 >= t0) {
+        s.lo[0] = 0; s.hi[0] = nt - 1; s.n = 1;
+      } else {
+        s.lo[0] = 0; s.hi[0] = t1;
+        s.lo[1] = t0; s.hi[1] = nt - 1; s.n = 2;
+      }
+    }
+    return s;
+  }
+  if (lo < 0) lo = 0;
+  if (hi > n - 1) hi = n - 1;
+  if (lo > hi) return s;
+  s.lo[0] = lo / ts; s.hi[0] = hi / ts; s.n = 1;
+  return s;
+}
+
+__global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
+                                                  double* __restrict__ Fh,
+                                                  double* __restrict__ Th,
+                                                  const double* __restrict__ Fc,
+                                                  const double* __restrict__ Tc,
+                                                  int move, Tiles tl, Counters* ctr) {
+  const int ip = blockIdx.x;
+  if (ip >= P.n) return;
+  const int lane = threadIdx.x;
+  const bool perz = g.periodic_z != 0;
+  const double L[3] = {(double)g.nx, (double)g.ny, (double)g.nz};
+  const bool per[3] = {true, true, perz};
+
+  double X[3], U[3], W[3], q[4], R[9];
+  for (int k = 0; k < 3; ++k) {
+    X[k] = P.X[3 * ip + k];
+    U[k] = P.U[3 * ip + k];
+    W[k] = P.W[3 * ip + k];
+  }
+  for (int k = 0; k < 4; ++k) q[k] = P.q[4 * ip + k];
+
+  if (move) {
+    // 1. F_p = sum of the per-tile partials (eqs. (17)-(18))
+    const int ne = tl.nent[ip];
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int k = lane; k < ne; k += WAVE) {
+      const double* pp = tl.part + ((size_t)ip * g.maxent + k) * 6;
+      for (int m = 0; m < 6; ++m) v[m] += pp[m];
+    }
+    double F[3], T[3];
+    for (int m = 0; m < 3; ++m) {
+      F[m] = wave_sum(v[m]) + tl.ovf[6 * ip + m];
+      T[m] = wave_sum(v[3 + m]) + tl.ovf[6 * ip + 3 + m];
+    }
+    // 2. Newton-Euler, symplectic Euler with Delta t = 1 (eqs. (2)-(3));
+    // gravity minus buoyancy (rho_p - rho_f) V g with rho_f = 1 (Sec. 5.1).
+    const double V = P.vol[ip], m = P.mass[ip], I = P.inert[ip];
+    const double s = P.dens[ip];
+    for (int k = 0; k < 3; ++k) {
+      const double Fg = (s - 1.0) * V * ph.gravity[k];
+      const double Ft = F[k] + Fc[3 * ip + k] + Fg;
+      const double Tt = T[k] + Tc[3 * ip + k];
+      U[k] += Ft / m;
+      X[k] += U[k];
+      if (per[k]) {
+        if (X[k] >= L[k]) X[k] -= L[k];
+        else if (X[k] < 0.0) X[k] += L[k];
+      }
+      W[k] += Tt / I;
+    }
+    // orientation: exact rotation through |w| about w, q <- dq (x) q
+    const double th = sqrt(W[0] * W[0] + W[1] * W[1] + W[2] * W[2]);
+    if (th > 0.0) {
+      const double c = cos(0.5 * th), sn = sin(0.5 * th) / th;
+      const double d0 = c, d1 = sn * W[0], d2 = sn * W[1], d3 = sn * W[2];
+      double r[4];
+      r[0] = d0 * q[0] - (d1 * q[1] + d2 * q[2] + d3 * q[3]);
+      r[1] = d0 * q[1] + q[0] * d1 + (d2 * q[3] - d3 * q[2]);
+      r[2] = d0 * q[2] + q[0] * d2 + (d3 * q[1] - d1 * q[3]);
+      r[3] = d0 * q[3] + q[0] * d3 + (d1 * q[2] - d2 * q[1]);
+      const double nn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
+      for (int k = 0; k < 4; ++k) q[k] = r[k] / nn;
+    }
+    if (lane == 0) {
+      for (int k = 0; k < 3; ++k) {
+        Fh[3 * ip + k] = F[k];
+        Th[3 * ip + k] = T[k];
+      }
+      for (int k = 0; k < 6; ++k) tl.ovf[6 * ip + k] = 0.0;
+    }
+  }
+  quat_to_rot(q, R);
+  if (lane == 0) {
+    for (int k = 0; k < 3; ++k) {
+      P.X[3 * ip + k] = X[k];
+      P.U[3 * ip + k] = U[k];
+      P.W[3 * ip + k] = W[k];
+    }
+    for (int k = 0; k < 4; ++k) P.q[4 * ip + k] = q[k];
+    for (int k = 0; k < 9; ++k) P.R[9 * ip + k] = R[k];
+  }
+
+  // 3. Reach box: axis-aligned half extent of the body plus the largest
+  // distance at which a node can be owned by it (eps/2), receive a momentum
+  // exchange term through a link of a node it owns (eps/2 + sqrt 2), or be
+  // flagged by the rough detection (sqrt(0.75) + enlargement).
+  const double margin = fmax(0.5 * ph.eps + 1.4142135623730951, DETECT + ph.delta_c) + 0.25;
+  const int shape = P.shape[ip];
+  const double size = P.size[ip];
+  const int n3[3] = {g.nx, g.ny, g.nz};
+  double ext[3];
+  for (int k = 0; k < 3; ++k) {
+    ext[k] = size;
+    if (shape == 1)
+      ext[k] = 0.5 * size * (fabs(R[3 * k]) + fabs(R[3 * k + 1]) + fabs(R[3 * k + 2])) ;
+    ext[k] += margin;
+  }
+  // detection tiles
+  {
+    const int nt3[3] = {g.dtx, g.dty, g.dtz};
+    const int ts3[3] = {DX, DY, DZ};
+    TileSpan sp[3];
+    for (int k = 0; k < 3; ++k) sp[k] = axis_tiles(X[k], ext[k], n3[k], nt3[k], ts3[k], per[k]);
+    const int cxn = sp[0].count(), cyn = sp[1].count(), czn = sp[2].count();
+    const int total = cxn * cyn * czn;
+    for (int t = lane; t < total; t += WAVE) {
+      const int ix = t % cxn, iy = (t / cxn) % cyn, iz = t / (cxn * cyn);
+      const long long tile = sp[0].at(ix) + (long long)g.dtx * (sp[1].at(iy) + (long long)g.dty * sp[2].at(iz));
+      const int slot = atomicAdd(&tl.dcount[tile], 1);
+      if (slot < g.tile_cap) tl.dlist[tile * g.tile_cap + slot] = ip;
+      else atomicOr(&ctr->tile_overflow, 1);
+    }
+  }
+  // lattice blocks, with the particle's own enumeration index
+  {
+    const int nt3[3] = {g.ltx, g.lty, g.ltz};
+    const int ts3[3] = {LX, LY, LZ};
+    TileSpan sp[3];
+    for (int k = 0; k < 3; ++k) sp[k] = axis_tiles(X[k], ext[k], n3[k], nt3[k], ts3[k], per[k]);
+    const int cxn = sp[0].count(), cyn = sp[1].count(), czn = sp[2].count();
+    int total = cxn * cyn * czn;
+    if (total > g.maxent) {
+      if (lane == 0) atomicOr(&ctr->tile_overflow, 1);
+      total = g.maxent;
+    }
+    if (lane == 0) tl.nent[ip] = total;
+    for (int t = lane; t < total; t += WAVE) {
+      const int ix = t % cxn, iy = (t / cxn) % cyn, iz = t / (cxn * cyn);
+      const long long tile = sp[0].at(ix) + (long long)g.ltx * (sp[1].at(iy) + (long long)g.lty * sp[2].at(iz));
+      const int slot = atomicAdd(&tl.lcount[tile], 1);
+      if (slot < g.tile_cap) {
+        tl.llist[tile * g.tile_cap + slot] = ip;
+        tl.lent[tile * g.tile_cap + slot] = t;
+      } else {
+        atomicOr(&ctr->tile_overflow, 1);
+        double* pp = tl.part + ((size_t)ip * g.maxent + t) * 6;
+        for (int m = 0; m < 6; ++m) pp[m] = 0.0;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_particles(Ctx& c, int move) {
+  if (c.np == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_particles, dim3(c.np), dim3(64), 0, c.stream, c.part,
+                     c.g, c.ph, c.Fh, c.Th, c.Fc, c.Tc, move, c.tl, c.counters);
+  return hipGetLastError();
+}
+
+}  // namespace hlbm

@@ -1,0 +1,285 @@
+"""Python binding of libhlbm.so (C ABI in include/hlbm.h).
+
+Argument marshalling only: every step of the time step runs in the library's
+HIP kernels.  PyTorch supplies the device memory of the two population
+buffers and the HIP stream the library runs on.  The library must be built
+(`python -m paper_2401_10878_amd.build`); importing this module without it
+raises immediately, and there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+# HLBM_LIBRARY may point at another build of the same library (for A/B
+# timing of kernel variants); the default is the in-tree build.
+LIBPATH = os.environ.get("HLBM_LIBRARY") or os.path.join(HERE, "libhlbm.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "hlbm.h")
+
+Q = 19
+STATUS = {0: "OK", -1: "E_ARG", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_CAPACITY",
+          -5: "E_UNSTABLE", -6: "E_STATE"}
+BYTES = {0: 8, 1: 4, 2: 2}
+
+
+class HlbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hlbm {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("periodic_z", C.c_int), ("tau", C.c_double),
+                ("wall_velocity", (C.c_double * 3) * 2),
+                ("gravity", C.c_double * 3), ("fluid_accel", C.c_double * 3),
+                ("balance", C.c_int), ("eps_b", C.c_double),
+                ("enlarge", C.c_double), ("n_c", C.c_int),
+                ("young", C.c_double), ("poisson", C.c_double),
+                ("restitution", C.c_double), ("mu_s", C.c_double),
+                ("mu_k", C.c_double), ("u_k", C.c_double),
+                ("max_pairs", C.c_int), ("tile_capacity", C.c_int),
+                ("precision", C.c_int)]
+
+
+class Contact(C.Structure):
+    _fields_ = [("a", C.c_int), ("b", C.c_int), ("count", C.c_int),
+                ("rlo", C.c_int * 3), ("rhi", C.c_int * 3),
+                ("carried", C.c_int),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("established", C.c_int), ("damping", C.c_double),
+                ("age", C.c_int), ("n_in", C.c_int),
+                ("volume", C.c_double), ("centroid", C.c_double * 3),
+                ("normal", C.c_double * 3), ("depth", C.c_double),
+                ("fn", C.c_double), ("force_a", C.c_double * 3),
+                ("force_b", C.c_double * 3)]
+
+
+def header_functions() -> list:
+    """Names of the functions include/hlbm.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hlbm_[a-z_]+)\s*\(", txt)))
+
+
+_lib = None
+
+
+def load():
+    """Load libhlbm.so (no GPU call is made here)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise RuntimeError(
+            f"{LIBPATH} is missing: build it with python -m paper_2401_10878_amd.build")
+    L = C.CDLL(LIBPATH)
+    P, d, i, v = C.POINTER, C.c_double, C.c_int, C.c_void_p
+    L.hlbm_create.argtypes = [P(Params), v, P(v)]
+    L.hlbm_bind_populations.argtypes = [v, v, v, C.c_size_t]
+    L.hlbm_init_particles.argtypes = [v, i, P(i), P(d), P(d), P(d), P(d), P(d), P(d)]
+    L.hlbm_init_fluid_equilibrium.argtypes = [v, d, P(d)]
+    L.hlbm_set_populations.argtypes = [v, P(d)]
+    L.hlbm_step.argtypes = [v, i]
+    L.hlbm_use_graph.argtypes = [v, i]
+    L.hlbm_sync.argtypes = [v]
+    L.hlbm_timing_begin.argtypes = [v, i]
+    L.hlbm_timing_end.argtypes = [v, P(d), P(i)]
+    L.hlbm_read_forces.argtypes = [v, P(d), P(d), P(d), P(d)]
+    L.hlbm_read_particles.argtypes = [v, P(d), P(d), P(d), P(d)]
+    L.hlbm_read_contacts.argtypes = [v, i, P(Contact), P(i)]
+    L.hlbm_read_fields.argtypes = [v, P(d), P(d), P(i)]
+    L.hlbm_read_populations.argtypes = [v, P(d)]
+    L.hlbm_counters.argtypes = [v] + [P(C.c_longlong)] * 4
+    L.hlbm_stream.argtypes = [v]
+    L.hlbm_stream.restype = v
+    L.hlbm_fluid_acceleration.argtypes = [v, P(d)]
+    L.hlbm_last_error.argtypes = [v]
+    L.hlbm_last_error.restype = C.c_char_p
+    L.hlbm_destroy.argtypes = [v]
+    for name in header_functions():
+        f = getattr(L, name)
+        if name not in ("hlbm_stream", "hlbm_last_error", "hlbm_destroy"):
+            f.restype = C.c_int
+    L.hlbm_destroy.restype = None
+    _lib = L
+    return L
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+def make_params(p) -> Params:
+    o = Params()
+    for f in ("nx", "ny", "nz", "periodic_z", "tau", "balance", "eps_b",
+              "enlarge", "n_c", "young", "poisson", "restitution", "mu_s",
+              "mu_k", "u_k", "max_pairs", "tile_capacity", "precision"):
+        setattr(o, f, getattr(p, f))
+    for w in range(2):
+        for k in range(3):
+            o.wall_velocity[w][k] = p.wall_velocity[w][k]
+    for k in range(3):
+        o.gravity[k] = p.gravity[k]
+        o.fluid_accel[k] = p.fluid_accel[k]
+    return o
+
+
+class Simulation:
+    """One coupled HLBM + contact simulation on one GPU.
+
+    params: workloads.Params; scene: workloads.Scene.  The two population
+    buffers are torch device tensors lent to the library; the library runs on
+    a dedicated torch stream (default priority).
+    """
+
+    def __init__(self, params, scene, device="cuda:0", graph=False):
+        import torch
+        self.torch = torch
+        self.L = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("hlbm needs a GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        self.params = params
+        self.ncell = params.nx * params.ny * params.nz
+        self.np = scene.n
+        self.stream = torch.cuda.Stream(self.device)
+        self.P = make_params(params)
+        h = C.c_void_p()
+        self._check(self.L.hlbm_create(C.byref(self.P),
+                                       C.c_void_p(self.stream.cuda_stream),
+                                       C.byref(h)), None)
+        self.h = h
+        nbytes = Q * self.ncell * BYTES[params.precision]
+        self.fa = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.fb = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        self._check(self.L.hlbm_bind_populations(
+            self.h, C.c_void_p(self.fa.data_ptr()), C.c_void_p(self.fb.data_ptr()),
+            nbytes))
+        sh = np.ascontiguousarray(scene.shape, np.int32)
+        arrs = [np.ascontiguousarray(a, np.float64) for a in
+                (scene.size, scene.density, scene.X, scene.q, scene.U, scene.omega)]
+        self._check(self.L.hlbm_init_particles(self.h, self.np, _ip(sh),
+                                               *[_dp(a) for a in arrs]))
+        if graph:
+            self._check(self.L.hlbm_use_graph(self.h, 1))
+
+    # ---- lifecycle ------------------------------------------------------
+    def _check(self, rc, h=...):
+        if rc != 0:
+            hh = self.h if h is ... else h
+            msg = self.L.hlbm_last_error(hh).decode() if hh else ""
+            raise HlbmError(rc, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.hlbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- initial conditions and stepping --------------------------------
+    def init_equilibrium(self, rho=1.0, u=(0.0, 0.0, 0.0)):
+        uu = np.asarray(u, np.float64)
+        self._check(self.L.hlbm_init_fluid_equilibrium(self.h, rho, _dp(uu)))
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, np.float64)
+        assert f.size == Q * self.ncell
+        self._check(self.L.hlbm_set_populations(self.h, _dp(f)))
+
+    def step(self, n=1):
+        self._check(self.L.hlbm_step(self.h, n))
+
+    def use_graph(self, on=True):
+        self._check(self.L.hlbm_use_graph(self.h, 1 if on else 0))
+
+    KERNELS = ("clear", "treat", "particles", "keep", "detect", "lattice")
+
+    def timing_begin(self, max_steps):
+        self._check(self.L.hlbm_timing_begin(self.h, max_steps))
+
+    def timing_end(self):
+        ms = np.zeros(6)
+        n = C.c_int()
+        self._check(self.L.hlbm_timing_end(self.h, _dp(ms), C.byref(n)))
+        return dict(zip(self.KERNELS, ms.tolist())), n.value
+
+    def sync(self):
+        self._check(self.L.hlbm_sync(self.h))
+
+    # ---- read-out ---------------------------------------------------------
+    def shape3(self):
+        p = self.params
+        return (p.nz, p.ny, p.nx)
+
+    def forces(self):
+        n = max(self.np, 1)
+        a = [np.zeros((n, 3)) for _ in range(4)]
+        self._check(self.L.hlbm_read_forces(self.h, *[_dp(x) for x in a]))
+        k = self.np
+        return dict(Fh=a[0][:k], Th=a[1][:k], Fc=a[2][:k], Tc=a[3][:k])
+
+    def particles(self):
+        n = max(self.np, 1)
+        X, q, U, w = (np.zeros((n, 3)), np.zeros((n, 4)), np.zeros((n, 3)),
+                      np.zeros((n, 3)))
+        self._check(self.L.hlbm_read_particles(self.h, _dp(X), _dp(q), _dp(U), _dp(w)))
+        k = self.np
+        return dict(X=X[:k], q=q[:k], U=U[:k], omega=w[:k])
+
+    def contacts(self):
+        n = C.c_int()
+        self._check(self.L.hlbm_read_contacts(self.h, 0, None, C.byref(n)))
+        arr = (Contact * max(n.value, 1))()
+        self._check(self.L.hlbm_read_contacts(self.h, n.value, arr, C.byref(n)))
+        out = []
+        for c in arr[:n.value]:
+            out.append(dict(a=c.a, b=c.b, count=c.count, rlo=tuple(c.rlo),
+                            rhi=tuple(c.rhi), carried=c.carried, lo=tuple(c.lo),
+                            hi=tuple(c.hi), established=c.established,
+                            damping=c.damping, age=c.age, n_in=c.n_in,
+                            volume=c.volume, centroid=tuple(c.centroid),
+                            normal=tuple(c.normal), depth=c.depth, fn=c.fn,
+                            force_a=tuple(c.force_a), force_b=tuple(c.force_b)))
+        return out
+
+    def fields(self, rho=True, u=True, owner=True):
+        s = self.shape3()
+        r = np.zeros(s) if rho else None
+        uu = np.zeros(s + (3,)) if u else None
+        o = np.zeros(s, np.int32) if owner else None
+        self._check(self.L.hlbm_read_fields(
+            self.h, _dp(r) if rho else None, _dp(uu) if u else None,
+            _ip(o) if owner else None))
+        return dict(rho=r, u=uu, owner=o)
+
+    def populations(self):
+        f = np.zeros((Q,) + self.shape3())
+        self._check(self.L.hlbm_read_populations(self.h, _dp(f)))
+        return f
+
+    def counters(self):
+        v = [C.c_longlong() for _ in range(4)]
+        self._check(self.L.hlbm_counters(self.h, *[C.byref(x) for x in v]))
+        return dict(pairs=v[0].value, cells=v[1].value, total_cells=v[2].value,
+                    steps=v[3].value)
+
+    def fluid_acceleration(self):
+        a = np.zeros(3)
+        self._check(self.L.hlbm_fluid_acceleration(self.h, _dp(a)))
+        return a
