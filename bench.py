@@ -102,6 +102,21 @@ def cpu_baseline(wl, steps):
     return res
 
 
+def copy_calibration(nbytes=1 << 30, reps=5):
+    """A plain streaming copy of known size (an elementwise kernel that reads
+    nbytes and writes nbytes), profiled beside the lattice kernel to scale the
+    HBM byte counters (FETCH_SIZE, WRITE_SIZE)."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_bytes_read=nbytes, copy_bytes_written=nbytes,
+                          launches=reps)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,13 +128,18 @@ def main():
                     help="replay the step as a captured HIP graph")
     ap.add_argument("--other-precisions", type=int, default=1,
                     help="also time the other two storage precisions")
-    ap.add_argument("--cpu-steps", type=int, default=4,
+    ap.add_argument("--cpu-steps", type=int, default=10,
                     help="oracle steps timed for the CPU baseline (0 = skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU "
               "path (see DESIGN.md for how it would shard).", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     from paper_2401_10878_amd import workloads as W
     wl = W.WORKLOADS[args.workload]()

@@ -366,6 +366,19 @@ __device__ inline Nbr neighbours(const Geom& g, int x, int y, int z) {
   return nb;
 }
 
+// Lattice directions packed as 2-bit fields (c + 1) per direction, so that a
+// runtime direction index is decoded with shifts instead of a table lookup.
+template <typename A>
+constexpr uint64_t pack_dirs(A a) {
+  uint64_t v = 0;
+  for (int j = 0; j < Q; ++j) v |= (uint64_t)(a(j) + 1) << (2 * j);
+  return v;
+}
+constexpr uint64_t CXP = pack_dirs([](int j) { return cx(j); });
+constexpr uint64_t CYP = pack_dirs([](int j) { return cy(j); });
+constexpr uint64_t CZP = pack_dirs([](int j) { return cz(j); });
+__device__ inline int cdir(uint64_t pk, int j) { return (int)((pk >> (2 * j)) & 3u) - 1; }
+
 // Momentum exchange of the compacted nodes of a lattice block: entry `slot`
 // (one per thread, slot < total) holds the node's post-collision populations
 // and its link masks.  For each particle that receives terms from the node
@@ -394,7 +407,7 @@ __device__ void mea_compacted(C (*fl)[256], int (*meta)[7], int slot, int total,
     rem = (unsigned)meta[slot][6];
   }
   const bool perz = g.periodic_z != 0;
-  const Nbr nb = neighbours(g, x, y, z);
+  const bool wall_m = !perz && z == 0, wall_p = !perz && z == g.nz - 1;
   // post-collision population of the entry: stored value h_j, full f_j*
   auto hval = [&](int j) -> C { return fl[j][slot]; };
   auto fval = [&](int j) -> double { return full_f<S>(fl[j][slot], j); };
@@ -415,12 +428,12 @@ __device__ void mea_compacted(C (*fl)[256], int (*meta)[7], int slot, int total,
                             Uq[2] + (w[0] * r[1] - w[1] * r[0])};
       double Sc[3], Tcc[3];
       link_group_sums<Store<S>::shifted>(hval, msk, own, up, w, Sc, Tcc);
-      if (own && (nb.wall_m || nb.wall_p)) {
+      if (own && (wall_m || wall_p)) {
         // links that bounce back from a wall return to y as f_opp(j)(y) of
         // the next step: term (c_j + u_p(y)) f_opp(j)(y)
 #pragma unroll
         for (int j = 1; j < Q; ++j) {
-          const int bw = nb.beyond(cz(j));
+          const int bw = cz(j) < 0 ? (wall_m ? 1 : 0) : (cz(j) > 0 ? (wall_p ? 2 : 0) : 0);
           if (!bw) continue;
           const double* uw = ph.wall_u[bw - 1];
           const double cuw = cx(j) * uw[0] + cy(j) * uw[1] + cz(j) * uw[2];
@@ -446,14 +459,13 @@ __device__ void mea_compacted(C (*fl)[256], int (*meta)[7], int slot, int total,
     msk2 = 0;
     if (q < 0 && rem) {
       // owner of the first remaining link, and all remaining links it owns
+      // (links beyond a wall never carry an owner, so z wraps only when
+      // periodic)
       auto link_owner = [&](int j) -> int {
-        int dx = 0, dy = 0, dz = 0;
-#pragma unroll
-        for (int jj = 1; jj < Q; ++jj)
-          if (jj == j) { dx = cx(jj); dy = cy(jj); dz = cz(jj); }
-        const int xj = dx < 0 ? nb.xs[0] : (dx > 0 ? nb.xs[2] : nb.xs[1]);
-        const int yj = dy < 0 ? nb.ys[0] : (dy > 0 ? nb.ys[2] : nb.ys[1]);
-        const int zj = dz < 0 ? nb.zs[0] : (dz > 0 ? nb.zs[2] : nb.zs[1]);
+        int xj = x + cdir(CXP, j), yj = y + cdir(CYP, j), zj = z + cdir(CZP, j);
+        xj = xj < 0 ? xj + g.nx : (xj >= g.nx ? xj - g.nx : xj);
+        yj = yj < 0 ? yj + g.ny : (yj >= g.ny ? yj - g.ny : yj);
+        zj = zj < 0 ? zj + g.nz : (zj >= g.nz ? zj - g.nz : zj);
         return owner[xj + g.nx * (yj + g.ny * zj)];
       };
       q = link_owner(__ffs(rem) - 1);
@@ -466,8 +478,11 @@ __device__ void mea_compacted(C (*fl)[256], int (*meta)[7], int slot, int total,
   }
 }
 
+// Four wavefronts per SIMD (the LDS footprint of the FP32 / binary16 forms
+// allows four blocks per CU); the register allocation is held to 128 VGPRs
+// for that, without spills.  The FP64 form is limited to two by its LDS.
 template <typename S>
-__global__ __launch_bounds__(256) void k_lattice(const S* __restrict__ src,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_lattice(const S* __restrict__ src,
                                                  S* __restrict__ dst,
                                                  const int* __restrict__ owner,
                                                  Particles P, Geom g, Phys ph,
