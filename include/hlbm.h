@@ -191,6 +191,43 @@ void *hlbm_stream(const hlbm_ctx *ctx);
 /* The uniform fluid acceleration in use (fluid_accel + balance force). */
 hlbm_status hlbm_fluid_acceleration(const hlbm_ctx *ctx, double a[3]);
 
+/* ---- Adjoint (reverse-mode gradient) of K coupled steps -----------------
+   Differentiates the time step of Sec. 4.4 (Algorithm 1): streaming and the
+   BGK + velocity-shift collision (eqs. (10)-(15)), the coupling weight and
+   particle velocity of each node (Sec. 3.2), the momentum exchange
+   (eqs. (16)-(18)) and the Newton-Euler update (eqs. (2)-(3)).  The owner
+   of every node and the contact forces (eqs. (4)-(9)) of the recorded
+   forward run are held fixed: the discrete decisions of the forward pass are
+   not differentiated.  FP64 form and fully periodic boxes only (E_ARG
+   otherwise).
+
+   hlbm_adjoint_record: from the current state, runs `ksteps` steps and keeps
+   a device snapshot of the whole state every `ckpt_every` steps (plus the
+   end state); the context then stands at the end of the window, as after
+   hlbm_step(ksteps).  Memory: ceil(ksteps / ckpt_every) + 1 snapshots of
+   about 19 x 8 B per node each.
+
+   hlbm_adjoint_gradient: for J = sum_p dJ_dU[p] . U_p (the particle
+   velocities at the end of the window; dJ_dU is 3n, host), recomputes each
+   segment from its checkpoint (keeping ckpt_every + 1 population fields on
+   the device) and sweeps it in reverse.  Outputs (host, any may be NULL):
+     dJ_ds[n]         derivative by each particle's density ratio s_p (mass,
+                      inertia, gravity-buoyancy, and the balance acceleration
+                      of a balanced box);
+     dJ_dtheta0[3n]   derivative by a world-frame rotation of each particle's
+                      initial orientation, q -> exp(theta/2) (x) q;
+     dJ_dq0[4n]       the same as a quaternion gradient tangent to |q| = 1,
+                      2 (0, dJ_dtheta0) (x) q;
+     dJ_dX0, dJ_dU0, dJ_domega0 [3n]  derivatives by the initial position,
+                      velocity and angular velocity.
+   The context is left at the end of the recorded window.  Reductions use
+   FP64 atomics, so results can differ from run to run in the last bits. */
+hlbm_status hlbm_adjoint_record(hlbm_ctx *ctx, int ksteps, int ckpt_every);
+hlbm_status hlbm_adjoint_gradient(hlbm_ctx *ctx, const double *dJ_dU,
+                                  double *dJ_ds, double *dJ_dtheta0,
+                                  double *dJ_dq0, double *dJ_dX0,
+                                  double *dJ_dU0, double *dJ_domega0);
+
 const char *hlbm_last_error(const hlbm_ctx *ctx);
 void hlbm_destroy(hlbm_ctx *ctx);
 

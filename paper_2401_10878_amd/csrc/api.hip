@@ -136,11 +136,77 @@ void free_timing(Ctx& c) {
   c.timing = false;
 }
 
+void free_snapshot(Snapshot& s) {
+  void* p[] = {s.f, s.part, s.tiles, s.psums, s.keys[0], s.keys[1], s.rec[0],
+               s.rec[1], s.owner, s.ctr};
+  for (void* q : p)
+    if (q) hipFree(q);
+  s = Snapshot();
+}
+
+void free_adjoint(Ctx& c) {
+  Adjoint& a = c.adj;
+  if (c.stream) hipStreamSynchronize(c.stream);
+  for (int k = 0; k < a.nseg; ++k) free_snapshot(a.ck[k]);
+  delete[] a.ck;
+  free_snapshot(a.end);
+  void* p[] = {a.fst, a.ost, a.pst, a.frc, a.gbar, a.hbar, a.pbar, a.sbar, a.work};
+  for (void* q : p)
+    if (q) hipFree(q);
+  a = Adjoint();
+}
+
 void free_particles(Ctx& c) {
+  free_adjoint(c);
   if (c.part_block) hipFree(c.part_block);
   c.part_block = nullptr;
   if (c.part_sums) hipFree(c.part_sums);
   c.part_sums = nullptr;
+}
+
+// ---- state snapshots (device-to-device copies on the context stream) ------
+size_t pop_bytes(const Ctx& c) { return (size_t)Q * (size_t)c.g.ncell * c.bytes_per_value; }
+
+hipError_t snapshot_alloc(Ctx& c, Snapshot& s) {
+  hipError_t e;
+  const size_t cap = (size_t)c.tab[0].cap;
+  if ((e = hipMalloc(&s.f, pop_bytes(c)))) return e;
+  if ((e = hipMalloc(&s.part, c.part_bytes))) return e;
+  if ((e = hipMalloc(&s.tiles, c.tile_bytes))) return e;
+  if ((e = hipMalloc(&s.psums, c.psum_bytes))) return e;
+  for (int k = 0; k < 2; ++k) {
+    if ((e = hipMalloc(&s.keys[k], sizeof(uint64_t) * cap))) return e;
+    if ((e = hipMalloc(&s.rec[k], sizeof(PairRec) * cap))) return e;
+  }
+  if ((e = hipMalloc(&s.owner, sizeof(int) * (size_t)c.g.ncell))) return e;
+  return hipMalloc(&s.ctr, sizeof(Counters));
+}
+
+// dir = 0: context -> snapshot, 1: snapshot -> context
+hipError_t snapshot_copy(Ctx& c, Snapshot& s, int dir) {
+  hipError_t e;
+  const size_t cap = (size_t)c.tab[0].cap;
+  auto cp = [&](void* snap, void* live, size_t n) {
+    return dir == 0 ? hipMemcpyAsync(snap, live, n, hipMemcpyDeviceToDevice, c.stream)
+                    : hipMemcpyAsync(live, snap, n, hipMemcpyDeviceToDevice, c.stream);
+  };
+  if (dir == 0) {
+    s.cur = c.cur;
+    s.step = c.step;
+  } else {
+    c.cur = s.cur;
+    c.step = s.step;
+  }
+  if ((e = cp(s.f, c.fbuf[c.cur], pop_bytes(c)))) return e;
+  if ((e = cp(s.part, c.part_block, c.part_bytes))) return e;
+  if ((e = cp(s.tiles, c.tile_block, c.tile_bytes))) return e;
+  if ((e = cp(s.psums, c.part_sums, c.psum_bytes))) return e;
+  for (int k = 0; k < 2; ++k) {
+    if ((e = cp(s.keys[k], c.tab[k].keys, sizeof(uint64_t) * cap))) return e;
+    if ((e = cp(s.rec[k], c.tab[k].rec, sizeof(PairRec) * cap))) return e;
+  }
+  if ((e = cp(s.owner, c.owner, sizeof(int) * (size_t)c.g.ncell))) return e;
+  return cp(s.ctr, c.counters, sizeof(Counters));
 }
 
 }  // namespace
@@ -221,6 +287,7 @@ hlbm_status hlbm_create(const hlbm_params* params, void* stream, hlbm_ctx** out)
   const int cap = next_pow2(2LL * P.max_pairs);
   const size_t tbytes = sizeof(int) * (size_t)(ndt + nlt) * (1 + P.tile_capacity) +
                         sizeof(int) * (size_t)nlt * P.tile_capacity;
+  c.tile_bytes = tbytes;
   bool okm = hipMalloc(&c.owner, sizeof(int) * ncell) == hipSuccess &&
              hipMalloc(&c.tile_block, tbytes) == hipSuccess &&
              hipMalloc(&c.counters, sizeof(Counters)) == hipSuccess &&
@@ -335,6 +402,7 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
   // 5 scalars, X 3, q 4, U 3, W 3, R 9, Fh 3, Th 3, Fc 3, Tc 3
   const size_t nd = nn * (5 + 3 + 4 + 3 + 3 + 9 + 3 + 3 + 3 + 3);
   const size_t bytes = nd * sizeof(double) + nn * sizeof(int);
+  c.part_bytes = bytes;
   HIPCHECK(hipMalloc(&c.part_block, bytes));
   HIPCHECK(hipMemsetAsync(c.part_block, 0, bytes, c.stream));
   double* d = (double*)c.part_block;
@@ -366,6 +434,7 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
     c.g.maxent = (int)me;
     const size_t pb = sizeof(int) * nn + sizeof(double) * nn * 6 * (size_t)me +
                       sizeof(double) * nn * 6;
+    c.psum_bytes = pb;
     HIPCHECK(hipMalloc(&c.part_sums, pb));
     HIPCHECK(hipMemsetAsync(c.part_sums, 0, pb, c.stream));
     double* pd = (double*)c.part_sums;
@@ -660,6 +729,141 @@ hlbm_status hlbm_fluid_acceleration(const hlbm_ctx* h, double a[3]) {
   return HLBM_OK;
 }
 
+hlbm_status hlbm_adjoint_record(hlbm_ctx* h, int ksteps, int ckpt_every) {
+  if (!h) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (!c.fluid_ready) return fail(c, HLBM_E_STATE, "initialise particles and fluid first");
+  if (c.precision != HLBM_FP64)
+    return fail(c, HLBM_E_ARG, "the adjoint runs on the FP64 form only");
+  if (!c.g.periodic_z) return fail(c, HLBM_E_ARG, "the adjoint needs a fully periodic box");
+  if (c.timing) return fail(c, HLBM_E_STATE, "finish the timing window first");
+  if (ksteps < 1 || ckpt_every < 1)
+    return fail(c, HLBM_E_ARG, "ksteps and ckpt_every must be >= 1");
+  free_adjoint(c);
+  Adjoint& a = c.adj;
+  a.K = ksteps;
+  a.L = ckpt_every < ksteps ? ckpt_every : ksteps;
+  a.nseg = (a.K + a.L - 1) / a.L;
+  a.ck = new (std::nothrow) Snapshot[a.nseg];
+  if (!a.ck) return fail(c, HLBM_E_NOMEM, "checkpoint table");
+  for (int k = 0; k < a.nseg; ++k)
+    if (snapshot_alloc(c, a.ck[k]) != hipSuccess) {
+      free_adjoint(c);
+      return fail(c, HLBM_E_NOMEM, "checkpoint %d of %d", k, a.nseg);
+    }
+  if (snapshot_alloc(c, a.end) != hipSuccess) {
+    free_adjoint(c);
+    return fail(c, HLBM_E_NOMEM, "end-state snapshot");
+  }
+  for (int seg = 0; seg < a.nseg; ++seg) {
+    HIPCHECK(snapshot_copy(c, a.ck[seg], 0));
+    const int n = std::min(a.L, a.K - seg * a.L);
+    for (int s = 0; s < n; ++s) {
+      HIPCHECK(enqueue_step(c, c.cur, nullptr));
+      c.cur = 1 - c.cur;
+      c.step++;
+    }
+  }
+  HIPCHECK(snapshot_copy(c, a.end, 0));
+  hlbm_status st = check_flags(c);
+  if (st) return st;
+  a.recorded = true;
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_adjoint_gradient(hlbm_ctx* h, const double* dJ_dU, double* dJ_ds,
+                                  double* dJ_dtheta0, double* dJ_dq0,
+                                  double* dJ_dX0, double* dJ_dU0,
+                                  double* dJ_domega0) {
+  if (!h) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  Adjoint& a = c.adj;
+  if (!a.recorded) return fail(c, HLBM_E_STATE, "no recorded forward window");
+  if (!dJ_dU) return fail(c, HLBM_E_ARG, "null seed");
+  const int np = c.np;
+  const size_t npp = np > 0 ? np : 1;
+  const long long n = c.g.ncell;
+  const int PR = adjoint_record_doubles(), PB = adjoint_slots();
+  if (!a.fst) {
+    bool ok = hipMalloc(&a.fst, sizeof(double) * (size_t)(a.L + 1) * Q * n) == hipSuccess &&
+              hipMalloc(&a.ost, sizeof(int) * (size_t)(a.L + 1) * n) == hipSuccess &&
+              hipMalloc(&a.pst, sizeof(double) * (size_t)(a.L + 1) * npp * PR) == hipSuccess &&
+              hipMalloc(&a.frc, sizeof(double) * (size_t)a.L * npp * 12) == hipSuccess &&
+              hipMalloc(&a.gbar, sizeof(double) * (size_t)Q * n) == hipSuccess &&
+              hipMalloc(&a.hbar, sizeof(double) * (size_t)Q * n) == hipSuccess &&
+              hipMalloc(&a.pbar, sizeof(double) * npp * PB) == hipSuccess &&
+              hipMalloc(&a.sbar, sizeof(double) * npp) == hipSuccess &&
+              hipMalloc(&a.work, sizeof(double) * adjoint_work_doubles(c)) == hipSuccess;
+    if (!ok) return fail(c, HLBM_E_NOMEM, "adjoint work arrays (segment of %d steps)", a.L);
+  }
+  // seed: J = sum_p dJ_dU[p] . U_p(K)
+  std::vector<double> pb(npp * PB, 0.0);
+  for (int p = 0; p < np; ++p)
+    for (int k = 0; k < 3; ++k) pb[(size_t)PB * p + 6 + k] = dJ_dU[3 * p + k];
+  HIPCHECK(hipMemcpyAsync(a.pbar, pb.data(), sizeof(double) * npp * PB,
+                          hipMemcpyHostToDevice, c.stream));
+  HIPCHECK(launch_fill_zero(c, a.sbar, (long long)npp));
+  HIPCHECK(launch_fill_zero(c, a.gbar, (long long)Q * n));
+  const size_t fs = (size_t)Q * n;
+  for (int seg = a.nseg - 1; seg >= 0; --seg) {
+    HIPCHECK(snapshot_copy(c, a.ck[seg], 1));
+    const int L = std::min(a.L, a.K - seg * a.L);
+    // recompute the segment, recording what the reverse steps read
+    for (int k = 0; k <= L; ++k) {
+      if (k < L)
+        HIPCHECK(hipMemcpyAsync(a.fst + (size_t)k * fs, c.fbuf[c.cur],
+                                sizeof(double) * fs, hipMemcpyDeviceToDevice, c.stream));
+      HIPCHECK(hipMemcpyAsync(a.ost + (size_t)k * n, c.owner, sizeof(int) * n,
+                              hipMemcpyDeviceToDevice, c.stream));
+      HIPCHECK(launch_rec_particles(c, a.pst + (size_t)k * npp * PR));
+      if (k == L) break;
+      HIPCHECK(enqueue_step(c, c.cur, nullptr));
+      c.cur = 1 - c.cur;
+      c.step++;
+      HIPCHECK(launch_rec_forces(c, a.frc + (size_t)k * npp * 12));
+    }
+    for (int k = L - 1; k >= 0; --k)
+      HIPCHECK(launch_adjoint_step(c, a.gbar, a.hbar, a.fst + (size_t)k * fs,
+                                   a.ost + (size_t)k * n, a.ost + (size_t)(k + 1) * n,
+                                   a.pst + (size_t)k * npp * PR,
+                                   a.pst + (size_t)(k + 1) * npp * PR,
+                                   a.frc + (size_t)k * npp * 12, a.pbar, a.sbar, a.work));
+  }
+  // initial orientations, from the particle block of checkpoint 0
+  std::vector<double> q0(4 * npp);
+  const size_t qoff = (size_t)((char*)c.part.q - (char*)c.part_block);
+  HIPCHECK(hipMemcpyAsync(q0.data(), (char*)a.ck[0].part + qoff, sizeof(double) * 4 * npp,
+                          hipMemcpyDeviceToHost, c.stream));
+  std::vector<double> sb(npp);
+  HIPCHECK(hipMemcpyAsync(pb.data(), a.pbar, sizeof(double) * npp * PB,
+                          hipMemcpyDeviceToHost, c.stream));
+  HIPCHECK(hipMemcpyAsync(sb.data(), a.sbar, sizeof(double) * npp, hipMemcpyDeviceToHost,
+                          c.stream));
+  HIPCHECK(snapshot_copy(c, a.end, 1));
+  HIPCHECK(hipStreamSynchronize(c.stream));
+  for (int p = 0; p < np; ++p) {
+    const double* v = &pb[(size_t)PB * p];
+    if (dJ_ds) dJ_ds[p] = sb[p];
+    for (int k = 0; k < 3; ++k) {
+      if (dJ_dX0) dJ_dX0[3 * p + k] = v[k];
+      if (dJ_dtheta0) dJ_dtheta0[3 * p + k] = v[3 + k];
+      if (dJ_dU0) dJ_dU0[3 * p + k] = v[6 + k];
+      if (dJ_domega0) dJ_domega0[3 * p + k] = v[9 + k];
+    }
+    if (dJ_dq0) {
+      // gradient in quaternion space, tangent to the unit sphere:
+      // 2 (0, theta_bar) (x) q
+      const double* q = &q0[4 * p];
+      const double t[3] = {v[3], v[4], v[5]};
+      dJ_dq0[4 * p + 0] = -2.0 * (t[0] * q[1] + t[1] * q[2] + t[2] * q[3]);
+      dJ_dq0[4 * p + 1] = 2.0 * (q[0] * t[0] + (t[1] * q[3] - t[2] * q[2]));
+      dJ_dq0[4 * p + 2] = 2.0 * (q[0] * t[1] + (t[2] * q[1] - t[0] * q[3]));
+      dJ_dq0[4 * p + 3] = 2.0 * (q[0] * t[2] + (t[0] * q[2] - t[1] * q[1]));
+    }
+  }
+  return check_flags(c);
+}
+
 const char* hlbm_last_error(const hlbm_ctx* h) {
   return h ? h->c.err.c_str() : "null context";
 }
@@ -671,6 +875,7 @@ void hlbm_destroy(hlbm_ctx* h) {
   drop_graphs(c);
   free_timing(c);
   free_particles(c);
+  free_adjoint(c);
   if (c.own_f) {
     if (c.fbuf[0]) hipFree(c.fbuf[0]);
     if (c.fbuf[1]) hipFree(c.fbuf[1]);

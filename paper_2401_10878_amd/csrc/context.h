@@ -86,6 +86,39 @@ struct Phys {
 
 constexpr int NKERN = 6;   // clear, treat, particles, keep, detect, lattice
 
+// Device copy of the whole step state (populations f*, particle block,
+// candidate lists and partial sums, both pair tables, owner map, counters).
+struct Snapshot {
+  void* f = nullptr;
+  void* part = nullptr;
+  void* tiles = nullptr;
+  void* psums = nullptr;
+  uint64_t* keys[2] = {nullptr, nullptr};
+  PairRec* rec[2] = {nullptr, nullptr};
+  int* owner = nullptr;
+  Counters* ctr = nullptr;
+  int cur = 0;
+  long long step = 0;
+};
+
+// Recorded forward window of the adjoint and its work arrays.
+struct Adjoint {
+  bool recorded = false;
+  int K = 0, L = 0;                  // steps, steps per checkpoint
+  Snapshot* ck = nullptr;            // checkpoint at the start of each segment
+  int nseg = 0;
+  Snapshot end;                      // state after the K steps
+  double* fst = nullptr;             // (L + 1) x Q x ncell: f* at each step of a segment
+  int* ost = nullptr;                // (L + 1) x ncell: owner maps
+  double* pst = nullptr;             // (L + 1) x np x 22: particle states
+  double* frc = nullptr;             // L x np x 12: forces of each step
+  double* gbar = nullptr;            // dJ/df* (Q x ncell)
+  double* hbar = nullptr;            // dJ/df  (Q x ncell)
+  double* pbar = nullptr;            // np x 12 particle adjoints
+  double* sbar = nullptr;            // np: dJ/ds
+  double* work = nullptr;
+};
+
 struct Ctx {
   hlbm_params P;
   Geom g;
@@ -123,6 +156,9 @@ struct Ctx {
   bool timing;
   int tcap, tused;
   hipEvent_t* tev;
+  // sizes of the state blocks (for snapshots)
+  size_t part_bytes = 0, tile_bytes = 0, psum_bytes = 0;
+  Adjoint adj;
   // graphs: one per parity of (cur, fcur, tcur)
   bool use_graph;
   hipGraphExec_t gexec[2];
@@ -144,5 +180,17 @@ hipError_t launch_store_direction(Ctx& c, void* f, int i, const double* src);
 hipError_t launch_load_direction(Ctx& c, const void* f, int i, double* dst);
 // comp = -1: density, 0..2: velocity component of f* (FP64, into out[ncell])
 hipError_t launch_moment(Ctx& c, const void* f, int comp, double* out);
+// adjoint (k_adjoint.hip)
+int adjoint_record_doubles();
+int adjoint_slots();
+size_t adjoint_work_doubles(const Ctx& c);
+hipError_t launch_rec_particles(Ctx& c, double* out);
+hipError_t launch_rec_forces(Ctx& c, double* out);
+hipError_t launch_fill_zero(Ctx& c, double* p, long long n);
+hipError_t launch_adjoint_step(Ctx& c, double* gbar, double* hbar,
+                               const double* fprev, const int* owner_prev,
+                               const int* owner_t, const double* prec_prev,
+                               const double* prec_t, const double* frc,
+                               double* pbar, double* sbar, double* work);
 
 }  // namespace hlbm

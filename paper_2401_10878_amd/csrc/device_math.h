@@ -106,9 +106,25 @@ __device__ inline double sdf(int shape, double size, const double* R,
   const double p2 = R[2] * r0 + R[5] * r1 + R[8] * r2;
   const double q0 = fabs(p0) - h, q1 = fabs(p1) - h, q2 = fabs(p2) - h;
   const double m0 = fmax(q0, 0.0), m1 = fmax(q1, 0.0), m2 = fmax(q2, 0.0);
-  const double outside = sqrt(m0 * m0 + m1 * m1 + m2 * m2);
+  const double s2 = m0 * m0 + m1 * m1 + m2 * m2;
+  const double outside = s2 > 0.0 ? sqrt(s2) : 0.0;
   const double inside = fmin(fmax(fmax(q0, q1), q2), 0.0);
   return outside + inside;
+}
+
+// The same signed distance in FP32 arithmetic (inputs rounded to FP32), for
+// conservative screening against thresholds: its error is below
+// 1e-6 (|r|_1 + size) plus a few units in the last place.
+__device__ inline float sdf32(int shape, float size, const double* R, float r0,
+                              float r1, float r2) {
+  if (shape == 0) return sqrtf(r0 * r0 + r1 * r1 + r2 * r2) - size;
+  const float h = 0.5f * size;
+  const float p0 = (float)R[0] * r0 + (float)R[3] * r1 + (float)R[6] * r2;
+  const float p1 = (float)R[1] * r0 + (float)R[4] * r1 + (float)R[7] * r2;
+  const float p2 = (float)R[2] * r0 + (float)R[5] * r1 + (float)R[8] * r2;
+  const float q0 = fabsf(p0) - h, q1 = fabsf(p1) - h, q2 = fabsf(p2) - h;
+  const float m0 = fmaxf(q0, 0.0f), m1 = fmaxf(q1, 0.0f), m2 = fmaxf(q2, 0.0f);
+  return sqrtf(m0 * m0 + m1 * m1 + m2 * m2) + fminf(fmaxf(fmaxf(q0, q1), q2), 0.0f);
 }
 
 // Signed distance with its world-frame gradient.  Inside a cube the
@@ -153,6 +169,13 @@ __device__ inline double weight(double d, double eps) {
   return c * c;
 }
 
+__device__ inline float weight32(float d, float eps) {
+  if (d <= -0.5f * eps) return 1.0f;
+  if (d >= 0.5f * eps) return 0.0f;
+  const float c = cosf((float)PI * (d + 0.5f * eps) / (2.0f * eps));
+  return c * c;
+}
+
 // ---- wavefront reductions (64 lanes) -------------------------------------
 // All-lane reductions built from DPP row rotations (row_ror 8, 4, 2, 1 within
 // each row of 16 lanes) and four readlanes, so no data goes through LDS and
@@ -177,6 +200,57 @@ __device__ inline double wave_sum(double v) {
   v += ror_d<1>(v);
   return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
 }
+// DPP move of an FP64 value within each row of 16 lanes.
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false));
+}
+// Value of lane (l ^ 16) and of lane (l ^ 32).
+__device__ inline double xor16_d(double v) {
+  return __hiloint2double(__builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401f),
+                          __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401f));
+}
+__device__ inline double xor32_d(double v) {
+  const int a = ((threadIdx.x & 63) ^ 32) << 2;
+  return __hiloint2double(__builtin_amdgcn_ds_bpermute(a, __double2hiint(v)),
+                          __builtin_amdgcn_ds_bpermute(a, __double2loint(v)));
+}
+// Reduce-scatter of six wavefront sums: the sum over all 64 lanes of v[k]
+// ends in lanes 2k and 2k + 1 (k < 6).  Each level pairs lanes that differ
+// in one bit of their index within the row (row_mirror, row_half_mirror,
+// quad_perm 3210, quad_perm 1032); the lane keeps the half of its current
+// values that its bit selects and adds the partner's copy of that half, so
+// the work halves at every level.  Rows are then combined through lanes
+// l ^ 16 and l ^ 32.  Fixed order, all 64 lanes active.
+__device__ inline double wave_sum6_scatter(const double* v) {
+  const int i = threadIdx.x & 15;
+  const bool b3 = (i & 8) != 0, b2 = (i & 4) != 0, b1 = (i & 2) != 0;
+  // slots 0..7 (6, 7 are zero): keep 0..3 (b3 = 0) or 4..7 (b3 = 1)
+  const double s0 = b3 ? v[0] : v[4], s1 = b3 ? v[1] : v[5];
+  const double s2 = b3 ? v[2] : 0.0, s3 = b3 ? v[3] : 0.0;
+  double k0 = b3 ? v[4] : v[0], k1 = b3 ? v[5] : v[1];
+  double k2 = b3 ? 0.0 : v[2], k3 = b3 ? 0.0 : v[3];
+  k0 += dpp_d<0x140>(s0);
+  k1 += dpp_d<0x140>(s1);
+  k2 += dpp_d<0x140>(s2);
+  k3 += dpp_d<0x140>(s3);
+  // keep local 0, 1 (b2 = 0) or 2, 3 (b2 = 1)
+  const double t0 = b2 ? k0 : k2, t1 = b2 ? k1 : k3;
+  double m0 = b2 ? k2 : k0, m1 = b2 ? k3 : k1;
+  m0 += dpp_d<0x141>(t0);
+  m1 += dpp_d<0x141>(t1);
+  // keep local 0 (b1 = 0) or 1 (b1 = 1)
+  const double t = b1 ? m0 : m1;
+  double n = b1 ? m1 : m0;
+  n += dpp_d<0x1b>(t);
+  n += dpp_d<0xb1>(n);
+  n += xor16_d(n);
+  n += xor32_d(n);
+  return n;
+}
+
 __device__ inline double wave_min(double v) {
   v = fmin(v, ror_d<8>(v));
   v = fmin(v, ror_d<4>(v));

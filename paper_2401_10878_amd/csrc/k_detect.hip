@@ -80,23 +80,66 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
   int cnt = tl.dcount[tile];
   cnt = __builtin_amdgcn_readfirstlane(cnt < g.tile_cap ? cnt : g.tile_cap);
   const int* list = tl.dlist + tile * g.tile_cap;
+  const double own_t = 0.5 * ph.eps;              // owner:     d < eps/2
+  const double det_t = DETECT + ph.delta_c;       // detection: d < sqrt(0.75) + delta_c
 
-  double bd = 1.0e300;
-  int bp = -1;
+  // Pass 1, FP32: classify each candidate against both thresholds with a
+  // bound on the FP32 error; a lane is settled when every candidate is
+  // clearly on one side of both thresholds and at most one can own it.
+  int bp = -1, nown = 0;
+  bool unsure = false;
   uint64_t mask = 0;
   for (int c = 0; c < cnt; ++c) {
     const int p = __builtin_amdgcn_readfirstlane(list[c]);
     const double X0 = P.X[3 * p], X1 = P.X[3 * p + 1], X2 = P.X[3 * p + 2];
-    const double* R = P.R + 9 * p;
     const double r0 = minimg(fx - X0, Lx, true);
     const double r1 = minimg(fy - X1, Ly, true);
     const double r2 = minimg(fz - X2, Lz, perz);
-    const double d = sdf(P.shape[p], P.size[p], R, r0, r1, r2);
-    if (valid && d < 0.5 * ph.eps && (d < bd || (d == bd && p < bp))) {
-      bd = d;
+    const float d = sdf32(P.shape[p], (float)P.size[p], P.R + 9 * p, (float)r0,
+                          (float)r1, (float)r2);
+    const double tol = 1e-3 + 1e-5 * (fabs(r0) + fabs(r1) + fabs(r2) + P.size[p]);
+    const double dd = (double)d;
+    if (dd < own_t + tol) {
+      ++nown;
       bp = p;
+      if (dd > own_t - tol) unsure = true;
     }
-    if (valid && d - ph.delta_c < DETECT) mask |= 1ull << c;
+    if (dd < det_t + tol) {
+      mask |= 1ull << c;
+      if (dd > det_t - tol) unsure = true;
+    }
+  }
+  if (!valid) {
+    bp = -1;
+    mask = 0;
+  }
+  // Pass 2, FP64, for the lanes pass 1 did not settle: the exact signed
+  // distances decide the owner (smallest (d, id)) and the detection set.
+  const bool exact = valid && (unsure || nown > 1);
+  if (__ballot(exact)) {
+    double bd = 1.0e300;
+    int ep = -1;
+    uint64_t em = 0;
+    for (int c = 0; c < cnt; ++c) {
+      const int p = __builtin_amdgcn_readfirstlane(list[c]);
+      if (exact) {
+        const double X0 = P.X[3 * p], X1 = P.X[3 * p + 1], X2 = P.X[3 * p + 2];
+        const double* R = P.R + 9 * p;
+        const double r0 = minimg(fx - X0, Lx, true);
+        const double r1 = minimg(fy - X1, Ly, true);
+        const double r2 = minimg(fz - X2, Lz, perz);
+        const double d = sdf(P.shape[p], P.size[p], R, r0, r1, r2);
+        if (d < own_t && (d < bd || (d == bd && p < ep))) {
+          bd = d;
+          ep = p;
+        }
+        if (d - ph.delta_c < DETECT) em |= 1ull << c;
+      }
+    }
+    if (exact) {
+      bp = ep;
+      mask = em;
+    }
   }
   if (valid) owner[(long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z)] = bp;
 

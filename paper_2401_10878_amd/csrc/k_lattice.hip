@@ -179,16 +179,18 @@ __device__ void commit_group(int q, const double* s, const double* t, int lid,
     const bool take = pend && q == pick;
     double v[6];
     for (int k = 0; k < 3; ++k) {
-      v[k] = wave_sum(take ? s[k] : 0.0);
-      v[3 + k] = wave_sum(take ? t[k] : 0.0);
+      v[k] = take ? s[k] : 0.0;
+      v[3 + k] = take ? t[k] : 0.0;
     }
+    const double sum = wave_sum6_scatter(v);   // component lane/2 in even lanes < 12
     const uint64_t hit = __ballot(lid == pick);
-    if (lane == 0) {
+    if (lane < 12 && (lane & 1) == 0) {
+      const int k = lane >> 1;
       if (hit) {
         const int c = __ffsll((long long)hit) - 1;
-        for (int k = 0; k < 6; ++k) row[c][k] -= v[k];
+        row[c][k] -= sum;
       } else {
-        for (int k = 0; k < 6; ++k) atomic_add_f64(&ovf[6 * pick + k], -v[k]);
+        atomic_add_f64(&ovf[6 * pick + k], -sum);
       }
     }
     if (take) pend = false;
@@ -561,26 +563,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const C inv = (C)1 / rho;
   const C u0 = J0 * inv, u1 = J1 * inv, u2 = J2 * inv;
 
-  // coupling (FP64 geometry): B and u_p of the owner
-  double upy[3] = {0.0, 0.0, 0.0};
-  double B = 0.0;
+  // coupling: B and u_p of the owner, in FP64 for FP64 storage and in FP32
+  // otherwise (the owner itself was decided in FP64)
+  C upy[3] = {(C)0, (C)0, (C)0};
+  C B = (C)0;
   if (o >= 0) {
     const double* Xo = P.X + 3 * o;
-    const double r0 = minimg((double)x - Xo[0], (double)g.nx, true);
-    const double r1 = minimg((double)y - Xo[1], (double)g.ny, true);
-    const double r2 = minimg((double)z - Xo[2], (double)g.nz, perz);
-    const double d = sdf(P.shape[o], P.size[o], P.R + 9 * o, r0, r1, r2);
-    B = weight(d, ph.eps);
+    const C r0 = (C)minimg((double)x - Xo[0], (double)g.nx, true);
+    const C r1 = (C)minimg((double)y - Xo[1], (double)g.ny, true);
+    const C r2 = (C)minimg((double)z - Xo[2], (double)g.nz, perz);
+    C d;
+    if constexpr (Store<S>::shifted) {
+      d = sdf32(P.shape[o], (float)P.size[o], P.R + 9 * o, r0, r1, r2);
+      B = weight32(d, (float)ph.eps);
+    } else {
+      d = sdf(P.shape[o], P.size[o], P.R + 9 * o, r0, r1, r2);
+      B = weight(d, ph.eps);
+    }
     const double* Uo = P.U + 3 * o;
     const double* Wo = P.W + 3 * o;
-    upy[0] = Uo[0] + (Wo[1] * r2 - Wo[2] * r1);
-    upy[1] = Uo[1] + (Wo[2] * r0 - Wo[0] * r2);
-    upy[2] = Uo[2] + (Wo[0] * r1 - Wo[1] * r0);
+    const C w0 = (C)Wo[0], w1 = (C)Wo[1], w2 = (C)Wo[2];
+    upy[0] = (C)Uo[0] + (w1 * r2 - w2 * r1);
+    upy[1] = (C)Uo[1] + (w2 * r0 - w0 * r2);
+    upy[2] = (C)Uo[2] + (w0 * r1 - w1 * r0);
   }
-  const C Bc = (C)B;
-  const C du0 = Bc * ((C)upy[0] - u0) + (C)ph.a_ext[0];
-  const C du1 = Bc * ((C)upy[1] - u1) + (C)ph.a_ext[1];
-  const C du2 = Bc * ((C)upy[2] - u2) + (C)ph.a_ext[2];
+  const C du0 = B * (upy[0] - u0) + (C)ph.a_ext[0];
+  const C du1 = B * (upy[1] - u1) + (C)ph.a_ext[1];
+  const C du2 = B * (upy[2] - u2) + (C)ph.a_ext[2];
   const C v0 = u0 + du0, v1 = u1 + du1, v2 = u2 + du2;
   const C uu = u0 * u0 + u1 * u1 + u2 * u2;
   const C vv = v0 * v0 + v1 * v1 + v2 * v2;

@@ -98,6 +98,8 @@ def load():
     L.hlbm_stream.argtypes = [v]
     L.hlbm_stream.restype = v
     L.hlbm_fluid_acceleration.argtypes = [v, P(d)]
+    L.hlbm_adjoint_record.argtypes = [v, i, i]
+    L.hlbm_adjoint_gradient.argtypes = [v] + [P(d)] * 7
     L.hlbm_last_error.argtypes = [v]
     L.hlbm_last_error.restype = C.c_char_p
     L.hlbm_destroy.argtypes = [v]
@@ -283,3 +285,67 @@ class Simulation:
         a = np.zeros(3)
         self._check(self.L.hlbm_fluid_acceleration(self.h, _dp(a)))
         return a
+
+    # ---- adjoint ------------------------------------------------------------
+    def adjoint_record(self, ksteps, ckpt_every):
+        """Run ksteps steps keeping checkpoints every ckpt_every steps."""
+        self._check(self.L.hlbm_adjoint_record(self.h, ksteps, ckpt_every))
+
+    def adjoint_gradient(self, dJ_dU):
+        """Gradients of J = sum_p dJ_dU[p] . U_p(end of window)."""
+        n = max(self.np, 1)
+        seed = np.zeros((n, 3))
+        seed[:self.np] = np.asarray(dJ_dU, np.float64).reshape(self.np, 3)
+        out = dict(s=np.zeros(n), theta0=np.zeros((n, 3)), q0=np.zeros((n, 4)),
+                   X0=np.zeros((n, 3)), U0=np.zeros((n, 3)), omega0=np.zeros((n, 3)))
+        self._check(self.L.hlbm_adjoint_gradient(
+            self.h, _dp(seed), _dp(out["s"]), _dp(out["theta0"]), _dp(out["q0"]),
+            _dp(out["X0"]), _dp(out["U0"]), _dp(out["omega0"])))
+        return {k: v[:self.np] for k, v in out.items()}
+
+
+def _settling_function():
+    import torch
+
+    class MeanSettlingVelocity(torch.autograd.Function):
+        """J = mean over particles of the vertical velocity U_z after ksteps
+        coupled steps from fluid at rest, as a function of the particles'
+        density ratios (n) and initial quaternions (n x 4).  The backward pass
+        is the library's adjoint (owners and contact forces of the forward run
+        held fixed); the quaternion gradient is tangent to |q| = 1."""
+
+        @staticmethod
+        def forward(ctx, density, q0, params, scene, ksteps, ckpt_every):
+            sc = scene.copy()
+            sc.density = density.detach().cpu().double().numpy().copy()
+            sc.q = q0.detach().cpu().double().numpy().copy()
+            sim = Simulation(params.replace(precision=0), sc)
+            sim.init_equilibrium()
+            sim.adjoint_record(int(ksteps), int(ckpt_every))
+            U = sim.particles()["U"]
+            ctx.sim = sim
+            ctx.n = sc.n
+            return torch.tensor(U[:, 2].mean(), dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, grad):
+            g = float(grad)
+            seed = np.zeros((ctx.n, 3))
+            seed[:, 2] = g / ctx.n
+            r = ctx.sim.adjoint_gradient(seed)
+            ctx.sim.close()
+            return (torch.from_numpy(r["s"]), torch.from_numpy(r["q0"]),
+                    None, None, None, None)
+
+    return MeanSettlingVelocity
+
+
+_MSV = None
+
+
+def mean_settling_velocity(density, q0, params, scene, ksteps, ckpt_every=50):
+    """Differentiable J(density, q0); see MeanSettlingVelocity."""
+    global _MSV
+    if _MSV is None:
+        _MSV = _settling_function()
+    return _MSV.apply(density, q0, params, scene, ksteps, ckpt_every)

@@ -40,3 +40,9 @@ def O():
 def W():
     from paper_2401_10878_amd import workloads
     return workloads
+
+
+@pytest.fixture(scope="session")
+def H():
+    from paper_2401_10878_amd import hlbm
+    return hlbm

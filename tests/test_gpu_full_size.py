@@ -1,0 +1,107 @@
+"""GPU parity at the full sizes of the dense settling boxes, in the launch
+configuration the benchmark times (one context, stream execution, the same
+workload records).
+
+256^3 periodic box with 1834 cubes of edge 14 (phi 0.30, Ar 1000) and the
+same centres with spheres of the volume-equivalent diameter (Ar 2000).  The
+FP64 oracle runs the whole lattice (a few steps take seconds on the host's
+cores), so every output is compared, not a sample:
+  * at the initial state (identical in every precision): the owner of every
+    node, the detected pair set, per-pair overlap node counts and image boxes
+    bit for bit;
+  * after each step: hydrodynamic and contact forces and torques, particle
+    state, and the final population field, within the precision's tolerance
+    (forces relative to max(|F_oracle|, (s - 1) V |g|)).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from test_gpu_parity import TOL, compare_contacts, force_err, rel_field
+
+pytestmark = pytest.mark.gpu
+
+NSTEPS = 3
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_run(O, wl):
+    """Initial integer outputs, per-step forces and particles, final field."""
+    o = O.OracleSim(wl.params.replace(precision=0), wl.scene)
+    o.init_equilibrium()
+    ref = dict(owner0=o.fields()["owner"], contacts0=o.contacts(),
+               counters0=o.counters(), steps=[])
+    for _ in range(NSTEPS):
+        o.step(1)
+        ref["steps"].append(dict(forces=o.forces(), particles=o.particles(),
+                                 contacts=o.contacts(), counters=o.counters()))
+    ref["pop"] = o.populations()
+    o.close()
+    return ref
+
+
+@pytest.fixture(scope="module")
+def dense_cubes(O, W):
+    wl = W.c3_dense_cubes()
+    _say("oracle: dense cube box", wl.note)
+    return wl, _oracle_run(O, wl)
+
+
+@pytest.fixture(scope="module")
+def dense_spheres(O, W):
+    wl = W.c4_dense_spheres()
+    _say("oracle: dense sphere box", wl.note)
+    return wl, _oracle_run(O, wl)
+
+
+def _check(H, wl, ref, prec):
+    p = wl.params.replace(precision=prec)
+    tol = TOL[prec]
+    g = H.Simulation(p, wl.scene)
+    g.init_equilibrium()
+    assert np.array_equal(g.fields()["owner"], ref["owner0"])
+    compare_contacts(ref["contacts0"], g.contacts(), 0.0)
+    c = g.counters()
+    assert (c["pairs"], c["cells"]) == ref["counters0"]
+    V = np.where(wl.scene.shape == 1, wl.scene.size ** 3,
+                 4.0 / 3.0 * np.pi * wl.scene.size ** 3)
+    Fref = ((wl.scene.density - 1) * V).max() * abs(p.gravity[2])
+    Tref = Fref * wl.scene.size.max()
+    for k in range(NSTEPS):
+        g.step(1)
+        s = ref["steps"][k]
+        eo, eg = s["forces"], g.forces()
+        ferr = max(force_err(eg["Fh"], eo["Fh"], Fref),
+                   force_err(eg["Fc"], eo["Fc"], Fref))
+        terr = max(force_err(eg["Th"], eo["Th"], Tref),
+                   force_err(eg["Tc"], eo["Tc"], Tref))
+        po, pg = s["particles"], g.particles()
+        xerr = np.abs(pg["X"] - po["X"]).max()
+        _say(f"  precision {prec} step {k + 1}: force {ferr:.2e} torque {terr:.2e} X {xerr:.2e}")
+        assert ferr <= tol and terr <= tol
+        assert xerr <= tol * max(p.nx, p.ny, p.nz)
+        if prec == 0:
+            oc, gc = s["contacts"], g.contacts()
+            assert [(a["a"], a["b"], a["count"]) for a in oc] == \
+                   [(b["a"], b["b"], b["count"]) for b in gc]
+    perr = rel_field(g.populations(), ref["pop"])
+    _say(f"  precision {prec}: population error {perr:.2e}")
+    assert perr <= tol
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_dense_cube_box_full_size(dense_cubes, H, prec):
+    wl, ref = dense_cubes
+    _check(H, wl, ref, prec)
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_dense_sphere_box_full_size(dense_spheres, H, prec):
+    wl, ref = dense_spheres
+    _check(H, wl, ref, prec)

@@ -22,12 +22,6 @@ def _say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def H():
-    from paper_2401_10878_amd import hlbm
-    return hlbm
-
-
 def _pair(O, H, params, scene, f0=None):
     o = O.OracleSim(params, scene)
     g = H.Simulation(params, scene)
