@@ -66,6 +66,7 @@ def run_gpu(wl, prec, steps, warmup, graph):
     t1 = time.perf_counter()
     kms, n = sim.timing_end()
     c1 = sim.counters()
+    final = dict(U=sim.particles()["U"], Fh=sim.forces()["Fh"])
     ncell = p.nx * p.ny * p.nz
     wall = t1 - t0
     out = dict(
@@ -73,7 +74,7 @@ def run_gpu(wl, prec, steps, warmup, graph):
         ms_per_step=wall * 1e3 / steps,
         contact_cells_per_s=(c1["total_cells"] - c0["total_cells"]) / wall,
         kernel_ms_per_step={k: v / n for k, v in kms.items()},
-        pairs=c1["pairs"], overlap_cells=c1["cells"],
+        pairs=c1["pairs"], overlap_cells=c1["cells"], final=final,
     )
     lat_s = kms["lattice"] / n / 1e3
     bytes_alg = 2 * 19 * VALUE_BYTES[PREC[prec]] * ncell
@@ -83,6 +84,44 @@ def run_gpu(wl, prec, steps, warmup, graph):
     del sim
     torch.cuda.empty_cache()
     return out
+
+
+def graph_ms_per_step(wl, prec, steps, warmup):
+    """Wall time per step when the step is replayed as a captured HIP graph."""
+    import torch
+    from paper_2401_10878_amd import hlbm
+    sim = hlbm.Simulation(wl.params.replace(precision=PREC[prec]), wl.scene,
+                          device="cuda:0", graph=True)
+    sim.init_equilibrium()
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return (t1 - t0) * 1e3 / steps
+
+
+def error_vs_fp64(wl, res, ref):
+    """Errors of a precision form against the FP64 run of the same steps:
+    mean settling velocity, hydrodynamic force (relative to
+    max(|F|, (s - 1) V |g|)) and particle velocity."""
+    import numpy as np
+    sc, g = wl.scene, abs(wl.params.gravity[2])
+    V = np.where(sc.shape == 1, sc.size ** 3, 4.0 / 3.0 * np.pi * sc.size ** 3)
+    Fref = ((sc.density - 1.0) * V).max() * g
+    U, U64 = res["final"]["U"], ref["final"]["U"]
+    F, F64 = res["final"]["Fh"], ref["final"]["Fh"]
+    uz, uz64 = U[:, 2].mean(), U64[:, 2].mean()
+    return dict(
+        mean_settling_velocity_rel=float(abs(uz - uz64) / abs(uz64)),
+        force_rel=float((np.abs(F - F64) / np.maximum(np.abs(F64), Fref)).max()),
+        velocity_rel=float(np.abs(U - U64).max() / np.abs(U64).max()))
 
 
 def cpu_baseline(wl, steps):
@@ -144,17 +183,22 @@ def main():
     from paper_2401_10878_amd import workloads as W
     wl = W.WORKLOADS[args.workload]()
     main_res = run_gpu(wl, args.precision, args.steps, args.warmup, args.graph)
-    others = {}
+    runs = {args.precision: main_res}
     if args.other_precisions:
         for pr in PREC:
             if pr != args.precision:
-                r = run_gpu(wl, pr, max(args.steps // 2, 10), args.warmup, args.graph)
-                others[pr] = dict(mlups=round(r["mlups"], 1),
-                                  ms_per_step=round(r["ms_per_step"], 4),
-                                  lattice_gbs=round(r["lattice_gbs"], 1))
-    others[args.precision] = dict(mlups=round(main_res["mlups"], 1),
-                                  ms_per_step=round(main_res["ms_per_step"], 4),
-                                  lattice_gbs=round(main_res["lattice_gbs"], 1))
+                runs[pr] = run_gpu(wl, pr, args.steps, args.warmup, args.graph)
+    others = {}
+    for pr, r in runs.items():
+        others[pr] = dict(mlups=round(r["mlups"], 1),
+                          ms_per_step=round(r["ms_per_step"], 4),
+                          lattice_gbs=round(r["lattice_gbs"], 1))
+        if "fp64" in runs and pr != "fp64":
+            others[pr]["error_vs_fp64"] = {
+                k: float(f"{v:.3e}") for k, v in
+                error_vs_fp64(wl, r, runs["fp64"]).items()}
+    graph_ms = None if args.graph else graph_ms_per_step(
+        wl, args.precision, args.steps, args.warmup)
     lat_ms = main_res["kernel_ms_per_step"]["lattice"]
     achieved = main_res["lattice_gbs"]
     traffic = traffic_for(args.precision)
@@ -179,6 +223,7 @@ def main():
         detected_pairs=main_res["pairs"], overlap_cells=main_res["overlap_cells"],
         kernel_ms_per_step={k: round(v, 5) for k, v in
                             main_res["kernel_ms_per_step"].items()},
+        graph_ms_per_step=None if graph_ms is None else round(graph_ms, 4),
         precisions=others,
         roofline=roof,
         cpu_baseline=cpu,

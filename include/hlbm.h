@@ -191,6 +191,18 @@ void *hlbm_stream(const hlbm_ctx *ctx);
 /* The uniform fluid acceleration in use (fluid_accel + balance force). */
 hlbm_status hlbm_fluid_acceleration(const hlbm_ctx *ctx, double a[3]);
 
+/* Checkpoint and resume.  hlbm_get_state copies the whole step state
+   (populations in their storage precision, particle records, candidate
+   lists and momentum-exchange partial sums, both contact tables, owner map,
+   counters, step count) into a caller-owned host buffer; with blob = NULL it
+   only sets *bytes to the size needed.  hlbm_set_state restores such a blob
+   into a context created with the same parameters and initialised with the
+   same particle set (count and shapes); the next hlbm_step continues exactly
+   where the saved context stood.  E_ARG for a blob of another
+   configuration. */
+hlbm_status hlbm_get_state(hlbm_ctx *ctx, void *blob, size_t *bytes);
+hlbm_status hlbm_set_state(hlbm_ctx *ctx, const void *blob, size_t bytes);
+
 /* ---- Adjoint (reverse-mode gradient) of K coupled steps -----------------
    Differentiates the time step of Sec. 4.4 (Algorithm 1): streaming and the
    BGK + velocity-shift collision (eqs. (10)-(15)), the coupling weight and

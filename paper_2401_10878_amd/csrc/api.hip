@@ -60,6 +60,8 @@ hlbm_status check_flags(Ctx& c) {
   if (h.pair_overflow)
     return fail(c, HLBM_E_CAPACITY, "contact pair table full (max_pairs=%d)",
                 c.P.max_pairs);
+  if (h.contact_overflow)
+    return fail(c, HLBM_E_CAPACITY, "more than %d contacts on one particle in one step", MAXC);
   if (h.unstable)
     return fail(c, HLBM_E_UNSTABLE, "non-finite or non-positive density on the lattice");
   return HLBM_OK;
@@ -400,7 +402,8 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
   const size_t nn = n > 0 ? n : 1;
   // layout of the one particle allocation (doubles, then ints)
   // 5 scalars, X 3, q 4, U 3, W 3, R 9, Fh 3, Th 3, Fc 3, Tc 3
-  const size_t nd = nn * (5 + 3 + 4 + 3 + 3 + 9 + 3 + 3 + 3 + 3);
+  // (plus 6 doubles' room for the 12 FP32 screening values)
+  const size_t nd = nn * (5 + 3 + 4 + 3 + 3 + 9 + 3 + 3 + 3 + 3 + 6);
   const size_t bytes = nd * sizeof(double) + nn * sizeof(int);
   c.part_bytes = bytes;
   HIPCHECK(hipMalloc(&c.part_block, bytes));
@@ -411,6 +414,7 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
   double* dmass = take(1); double* dinert = take(1);
   c.part.X = take(3); c.part.q = take(4); c.part.U = take(3); c.part.W = take(3);
   c.part.R = take(9);
+  c.part.XR32 = (float*)take(6);
   c.Fh = take(3); c.Th = take(3);
   c.Fc = take(3); c.Tc = take(3);
   int* dsh = (int*)d;
@@ -432,15 +436,21 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
       me *= m;
     }
     c.g.maxent = (int)me;
-    const size_t pb = sizeof(int) * nn + sizeof(double) * nn * 6 * (size_t)me +
-                      sizeof(double) * nn * 6;
+    // doubles: part (nn x me x 6), ovf (nn x 6), cval (nn x MAXC x 6);
+    // ints: nent (nn), ccount (nn), ckey (nn x MAXC)
+    const size_t nd = nn * 6 * (size_t)me + nn * 6 + nn * MAXC * 6;
+    const size_t ni = nn + nn + nn * MAXC;
+    const size_t pb = sizeof(double) * nd + sizeof(int) * ni;
     c.psum_bytes = pb;
     HIPCHECK(hipMalloc(&c.part_sums, pb));
     HIPCHECK(hipMemsetAsync(c.part_sums, 0, pb, c.stream));
     double* pd = (double*)c.part_sums;
     c.tl.part = pd;
     c.tl.ovf = pd + nn * 6 * (size_t)me;
-    c.tl.nent = (int*)(c.tl.ovf + nn * 6);
+    c.tl.cval = c.tl.ovf + nn * 6;
+    c.tl.nent = (int*)(c.tl.cval + nn * MAXC * 6);
+    c.tl.ccount = c.tl.nent + nn;
+    c.tl.ckey = c.tl.ccount + nn;
   }
   if (n > 0) {
     HIPCHECK(hipMemcpyAsync(dsh, sh.data(), sizeof(int) * n, hipMemcpyHostToDevice, c.stream));
@@ -690,6 +700,9 @@ hlbm_status hlbm_read_fields(hlbm_ctx* h, double* rho, double* u, int* owner) {
   if (owner)
     HIPCHECK(hipMemcpyAsync(owner, c.owner, sizeof(int) * n, hipMemcpyDeviceToHost, c.stream));
   HIPCHECK(hipStreamSynchronize(c.stream));
+  // every negative code of the device map reads as "no owner"
+  if (owner)
+    for (size_t i = 0; i < n; ++i) owner[i] = owner[i] < 0 ? -1 : owner[i];
   return check_flags(c);
 }
 
@@ -727,6 +740,118 @@ hlbm_status hlbm_fluid_acceleration(const hlbm_ctx* h, double a[3]) {
   if (!h || !a) return HLBM_E_ARG;
   for (int k = 0; k < 3; ++k) a[k] = h->c.ph.a_ext[k];
   return HLBM_OK;
+}
+
+// ---- host state blob: header, then the device blocks in a fixed order ----
+namespace {
+struct StateHeader {
+  char magic[8];
+  int version, precision, nx, ny, nz, np, cur, cap;
+  long long step;
+  unsigned long long f_bytes, part_bytes, tile_bytes, psum_bytes, tab_bytes,
+      owner_bytes;
+};
+const char kMagic[8] = {'H', 'L', 'B', 'M', 'S', 'T', 'A', '1'};
+
+unsigned long long state_bytes(const Ctx& c) {
+  const size_t cap = (size_t)c.tab[0].cap;
+  return sizeof(StateHeader) + pop_bytes(c) + c.part_bytes + c.tile_bytes +
+         c.psum_bytes + 2 * cap * (sizeof(uint64_t) + sizeof(PairRec)) +
+         sizeof(int) * (size_t)c.g.ncell + sizeof(Counters);
+}
+}  // namespace
+
+hlbm_status hlbm_get_state(hlbm_ctx* h, void* blob, size_t* bytes) {
+  if (!h || !bytes) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (!c.fluid_ready) return fail(c, HLBM_E_STATE, "initialise particles and fluid first");
+  const unsigned long long need = state_bytes(c);
+  if (!blob) {
+    *bytes = (size_t)need;
+    return HLBM_OK;
+  }
+  if (*bytes < need) return fail(c, HLBM_E_ARG, "state blob needs %llu bytes", need);
+  const size_t cap = (size_t)c.tab[0].cap;
+  StateHeader hd;
+  memset(&hd, 0, sizeof hd);
+  memcpy(hd.magic, kMagic, 8);
+  hd.version = 1;
+  hd.precision = c.precision;
+  hd.nx = c.g.nx; hd.ny = c.g.ny; hd.nz = c.g.nz;
+  hd.np = c.np;
+  hd.cur = c.cur;
+  hd.cap = (int)cap;
+  hd.step = c.step;
+  hd.f_bytes = pop_bytes(c);
+  hd.part_bytes = c.part_bytes;
+  hd.tile_bytes = c.tile_bytes;
+  hd.psum_bytes = c.psum_bytes;
+  hd.tab_bytes = cap * (sizeof(uint64_t) + sizeof(PairRec));
+  hd.owner_bytes = sizeof(int) * (size_t)c.g.ncell;
+  char* o = (char*)blob;
+  memcpy(o, &hd, sizeof hd);
+  o += sizeof hd;
+  auto get = [&](const void* dev, size_t n) {
+    hipError_t e = hipMemcpyAsync(o, dev, n, hipMemcpyDeviceToHost, c.stream);
+    o += n;
+    return e;
+  };
+  HIPCHECK(get(c.fbuf[c.cur], pop_bytes(c)));
+  HIPCHECK(get(c.part_block, c.part_bytes));
+  HIPCHECK(get(c.tile_block, c.tile_bytes));
+  HIPCHECK(get(c.part_sums, c.psum_bytes));
+  for (int k = 0; k < 2; ++k) {
+    HIPCHECK(get(c.tab[k].keys, sizeof(uint64_t) * cap));
+    HIPCHECK(get(c.tab[k].rec, sizeof(PairRec) * cap));
+  }
+  HIPCHECK(get(c.owner, sizeof(int) * (size_t)c.g.ncell));
+  HIPCHECK(get(c.counters, sizeof(Counters)));
+  HIPCHECK(hipStreamSynchronize(c.stream));
+  *bytes = (size_t)need;
+  return HLBM_OK;
+}
+
+hlbm_status hlbm_set_state(hlbm_ctx* h, const void* blob, size_t bytes) {
+  if (!h || !blob) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (!c.particles_ready)
+    return fail(c, HLBM_E_STATE, "initialise the particles (same count and shapes) first");
+  StateHeader hd;
+  if (bytes < sizeof hd) return fail(c, HLBM_E_ARG, "state blob too short");
+  memcpy(&hd, blob, sizeof hd);
+  const size_t cap = (size_t)c.tab[0].cap;
+  if (memcmp(hd.magic, kMagic, 8) != 0 || hd.version != 1)
+    return fail(c, HLBM_E_ARG, "not a state blob of this library");
+  if (hd.precision != c.precision || hd.nx != c.g.nx || hd.ny != c.g.ny || hd.nz != c.g.nz ||
+      hd.np != c.np || hd.cap != (int)cap || hd.part_bytes != c.part_bytes ||
+      hd.tile_bytes != c.tile_bytes || hd.psum_bytes != c.psum_bytes)
+    return fail(c, HLBM_E_ARG, "state blob was written by a different configuration");
+  if (bytes < state_bytes(c)) return fail(c, HLBM_E_ARG, "state blob truncated");
+  hlbm_status st = ensure_populations(c);
+  if (st) return st;
+  drop_graphs(c);
+  c.cur = hd.cur;
+  c.step = hd.step;
+  const char* o = (const char*)blob + sizeof hd;
+  auto put = [&](void* dev, size_t n) {
+    hipError_t e = hipMemcpyAsync(dev, o, n, hipMemcpyHostToDevice, c.stream);
+    o += n;
+    return e;
+  };
+  HIPCHECK(put(c.fbuf[c.cur], pop_bytes(c)));
+  HIPCHECK(put(c.part_block, c.part_bytes));
+  HIPCHECK(put(c.tile_block, c.tile_bytes));
+  HIPCHECK(put(c.part_sums, c.psum_bytes));
+  for (int k = 0; k < 2; ++k) {
+    HIPCHECK(put(c.tab[k].keys, sizeof(uint64_t) * cap));
+    HIPCHECK(put(c.tab[k].rec, sizeof(PairRec) * cap));
+  }
+  HIPCHECK(put(c.owner, sizeof(int) * (size_t)c.g.ncell));
+  HIPCHECK(put(c.counters, sizeof(Counters)));
+  HIPCHECK(hipStreamSynchronize(c.stream));
+  free_adjoint(c);
+  c.fluid_ready = true;
+  return check_flags(c);
 }
 
 hlbm_status hlbm_adjoint_record(hlbm_ctx* h, int ksteps, int ckpt_every) {

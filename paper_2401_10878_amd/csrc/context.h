@@ -40,7 +40,7 @@ struct Counters {
   int tile_overflow;
   int pair_overflow;
   int unstable;
-  int pad;
+  int contact_overflow;   // more than MAXC contacts on one particle
 };
 
 // Scalar parameters handed to every kernel by value.
@@ -71,6 +71,12 @@ struct Tiles {
   int* nent;
   double* part;
   double* ovf;
+  // contact forces of the step, per particle: ccount[p] entries, each with
+  // the partner id ckey[p*MAXC + k] (walls -1, -2) and (force, torque)
+  // cval[(p*MAXC + k)*6 + 0..5]; summed in partner order by k_particles
+  int* ccount;
+  int* ckey;
+  double* cval;
 };
 
 struct Phys {

@@ -23,6 +23,10 @@ constexpr int Q = 19;
 constexpr int DX = 4, DY = 4, DZ = 4;
 constexpr int LX = 64, LY = 4, LZ = 1;
 constexpr int LCAP_MAX = 64;    // lattice-block candidate capacity
+constexpr int MAXC = 32;        // contacts per particle in one step
+// owner-map code of a node with no owner but a link neighbour that may have
+// one (every negative code means "no owner")
+constexpr int NEAR_NONE = -2;
 constexpr int WAVE = 64;
 constexpr double DETECT = 0.8660254037844386;   // sqrt(0.75), Sec. 3.3.1
 constexpr double PI = 3.141592653589793;
@@ -61,6 +65,7 @@ struct Particles {
   double* U;            // [n][3]
   double* W;            // [n][3] angular velocity
   double* R;            // [n][9] rotation (body -> world), row-major
+  float* XR32;          // [n][12] X (3) and R (9) rounded to FP32, for screening
 };
 
 // Rotation matrix of q = (w, x, y, z).
@@ -82,6 +87,12 @@ __device__ inline double minimg(double v, double L, bool periodic) {
   if (!periodic) return v;
   if (v >= 0.5 * L) return v - L;
   if (v < -0.5 * L) return v + L;
+  return v;
+}
+__device__ inline float minimg_f(float v, float L, bool periodic) {
+  if (!periodic) return v;
+  if (v >= 0.5f * L) return v - L;
+  if (v < -0.5f * L) return v + L;
   return v;
 }
 __device__ inline int image_shift(double v, double L, bool periodic) {
@@ -122,6 +133,19 @@ __device__ inline float sdf32(int shape, float size, const double* R, float r0,
   const float p0 = (float)R[0] * r0 + (float)R[3] * r1 + (float)R[6] * r2;
   const float p1 = (float)R[1] * r0 + (float)R[4] * r1 + (float)R[7] * r2;
   const float p2 = (float)R[2] * r0 + (float)R[5] * r1 + (float)R[8] * r2;
+  const float q0 = fabsf(p0) - h, q1 = fabsf(p1) - h, q2 = fabsf(p2) - h;
+  const float m0 = fmaxf(q0, 0.0f), m1 = fmaxf(q1, 0.0f), m2 = fmaxf(q2, 0.0f);
+  return sqrtf(m0 * m0 + m1 * m1 + m2 * m2) + fminf(fmaxf(fmaxf(q0, q1), q2), 0.0f);
+}
+
+// As sdf32, with the rotation already in FP32.
+__device__ inline float sdf32_r(int shape, float size, const float* R, float r0,
+                                float r1, float r2) {
+  if (shape == 0) return sqrtf(r0 * r0 + r1 * r1 + r2 * r2) - size;
+  const float h = 0.5f * size;
+  const float p0 = R[0] * r0 + R[3] * r1 + R[6] * r2;
+  const float p1 = R[1] * r0 + R[4] * r1 + R[7] * r2;
+  const float p2 = R[2] * r0 + R[5] * r1 + R[8] * r2;
   const float q0 = fabsf(p0) - h, q1 = fabsf(p1) - h, q2 = fabsf(p2) - h;
   const float m0 = fmaxf(q0, 0.0f), m1 = fmaxf(q1, 0.0f), m2 = fmaxf(q2, 0.0f);
   return sqrtf(m0 * m0 + m1 * m1 + m2 * m2) + fminf(fmaxf(fmaxf(q0, q1), q2), 0.0f);

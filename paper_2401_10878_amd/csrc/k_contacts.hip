@@ -12,7 +12,9 @@
 //            distances negative; wave sums of count, position and gradient
 //            difference, wave maximum of -(d'_a + d'_b)
 //   force    normal force (4, 5, 6) and friction (7-9) at the centroid,
-//            committed to both particles with FP64 atomics.
+//            appended to both particles' contact slots; k_particles sums a
+//            particle's slots in the order of the partner id, so the
+//            result does not depend on the order the pairs ran in.
 #include <float.h>
 
 #include "context.h"
@@ -23,7 +25,7 @@ namespace {
 
 __global__ void k_clear_step(PairTable next, double* Fc, double* Tc, int np,
                              int* dcount, long long ndt, int* lcount,
-                             long long nlt, Counters* ctr) {
+                             long long nlt, int* ccount, Counters* ctr) {
   const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = tid; i < next.cap; i += stride) {
@@ -41,6 +43,7 @@ __global__ void k_clear_step(PairTable next, double* Fc, double* Tc, int np,
     Fc[i] = 0.0;
     Tc[i] = 0.0;
   }
+  for (long long i = tid; i < np; i += stride) ccount[i] = 0;
   if (tid == 0) {
     ctr->det_pairs = 0;
     ctr->det_cells = 0;
@@ -116,8 +119,24 @@ __device__ inline void cross3(const double* a, const double* b, double* o) {
   o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+// Append (force, torque) on particle p from its partner `other` to p's slots.
+__device__ void add_contact(Tiles tl, Counters* ctr, int p, int other,
+                            const double* F, const double* T) {
+  const int k = atomicAdd(&tl.ccount[p], 1);
+  if (k >= MAXC) {
+    atomicOr(&ctr->contact_overflow, 1);
+    return;
+  }
+  const size_t e = (size_t)p * MAXC + k;
+  tl.ckey[e] = other;
+  for (int m = 0; m < 3; ++m) {
+    tl.cval[6 * e + m] = F[m];
+    tl.cval[6 * e + 3 + m] = T[m];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_treat(PairTable t, Particles P, Geom g,
-                                               Phys ph, double* Fc, double* Tc) {
+                                               Phys ph, Tiles tl, Counters* ctr) {
   const int lane = threadIdx.x % WAVE;
   const long long slot = (long long)blockIdx.x * 4 + threadIdx.x / WAVE;
   if (slot >= t.cap) return;
@@ -293,14 +312,8 @@ __global__ __launch_bounds__(256) void k_treat(PairTable t, Particles P, Geom g,
   cross3(ra, Fa, Ta);
   if (b >= 0) cross3(rb, Fb, Tb);
   if (lane == 0) {
-    for (int m = 0; m < 3; ++m) {
-      atomic_add_f64(&Fc[3 * a + m], Fa[m]);
-      atomic_add_f64(&Tc[3 * a + m], Ta[m]);
-      if (b >= 0) {
-        atomic_add_f64(&Fc[3 * b + m], Fb[m]);
-        atomic_add_f64(&Tc[3 * b + m], Tb[m]);
-      }
-    }
+    add_contact(tl, ctr, a, b, Fa, Ta);
+    if (b >= 0) add_contact(tl, ctr, b, a, Fb, Tb);
     rec->keep = 1;
     rec->carried = 1;
     rec->established = established;
@@ -332,7 +345,7 @@ hipError_t launch_clear_step(Ctx& c, PairTable next) {
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_clear_step, dim3((unsigned)blocks), dim3(256), 0,
                      c.stream, next, c.Fc, c.Tc, c.np, c.tl.dcount, ndt,
-                     c.tl.lcount, nlt, c.counters);
+                     c.tl.lcount, nlt, c.tl.ccount, c.counters);
   return hipGetLastError();
 }
 
@@ -344,7 +357,7 @@ hipError_t launch_keep(Ctx& c, PairTable from, PairTable to) {
 
 hipError_t launch_treat(Ctx& c, PairTable t) {
   hipLaunchKernelGGL(k_treat, dim3((unsigned)((t.cap + 3) / 4)), dim3(256), 0,
-                     c.stream, t, c.part, c.g, c.ph, c.Fc, c.Tc);
+                     c.stream, t, c.part, c.g, c.ph, c.tl, c.counters);
   return hipGetLastError();
 }
 

@@ -77,9 +77,19 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
   const double fx = (double)x, fy = (double)y, fz = (double)z;
   const double Lx = (double)g.nx, Ly = (double)g.ny, Lz = (double)g.nz;
 
-  int cnt = tl.dcount[tile];
-  cnt = __builtin_amdgcn_readfirstlane(cnt < g.tile_cap ? cnt : g.tile_cap);
+  // The tile's count and candidate ids in one round trip (lane c reads slot
+  // c of the list whatever the count); the loops take candidate c's id with
+  // readlane and its FP32 screening record (centre, rotation) through
+  // scalar loads.
   const int* list = tl.dlist + tile * g.tile_cap;
+  const int cnt_raw = tl.dcount[tile];
+  const int my_id = lane < g.tile_cap ? list[lane] : 0;
+  int cnt = __builtin_amdgcn_readfirstlane(cnt_raw);
+  cnt = cnt < g.tile_cap ? cnt : g.tile_cap;
+  const bool have = lane < cnt;
+  const int pid = have ? my_id : 0;
+  const float fxf = (float)x, fyf = (float)y, fzf = (float)z;
+  const float Lxf = (float)g.nx, Lyf = (float)g.ny, Lzf = (float)g.nz;
   const double own_t = 0.5 * ph.eps;              // owner:     d < eps/2
   const double det_t = DETECT + ph.delta_c;       // detection: d < sqrt(0.75) + delta_c
 
@@ -87,26 +97,30 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
   // bound on the FP32 error; a lane is settled when every candidate is
   // clearly on one side of both thresholds and at most one can own it.
   int bp = -1, nown = 0;
-  bool unsure = false;
+  bool unsure = false, near = false;
   uint64_t mask = 0;
   for (int c = 0; c < cnt; ++c) {
-    const int p = __builtin_amdgcn_readfirstlane(list[c]);
-    const double X0 = P.X[3 * p], X1 = P.X[3 * p + 1], X2 = P.X[3 * p + 2];
-    const double r0 = minimg(fx - X0, Lx, true);
-    const double r1 = minimg(fy - X1, Ly, true);
-    const double r2 = minimg(fz - X2, Lz, perz);
-    const float d = sdf32(P.shape[p], (float)P.size[p], P.R + 9 * p, (float)r0,
-                          (float)r1, (float)r2);
-    const double tol = 1e-3 + 1e-5 * (fabs(r0) + fabs(r1) + fabs(r2) + P.size[p]);
-    const double dd = (double)d;
-    if (dd < own_t + tol) {
+    const int p = __builtin_amdgcn_readlane(pid, c);
+    const float* xr = P.XR32 + 12 * p;      // uniform: scalar loads
+    const int shape = P.shape[p];
+    const float size = (float)P.size[p];
+    const float f0 = minimg_f(fxf - xr[0], Lxf, true);
+    const float f1 = minimg_f(fyf - xr[1], Lyf, true);
+    const float f2 = minimg_f(fzf - xr[2], Lzf, perz);
+    const float d = sdf32_r(shape, size, xr + 3, f0, f1, f2);
+    const float tol = 1e-3f + 1e-5f * (fabsf(f0) + fabsf(f1) + fabsf(f2) + size);
+    const float ot = (float)own_t, dt = (float)det_t;
+    // a link neighbour (at most sqrt 2 away) can be owned by p only if
+    // d < eps/2 + sqrt 2 here (signed distances are 1-Lipschitz)
+    if (d < ot + 1.4142135f + tol) near = true;
+    if (d < ot + tol) {
       ++nown;
       bp = p;
-      if (dd > own_t - tol) unsure = true;
+      if (d > ot - tol) unsure = true;
     }
-    if (dd < det_t + tol) {
+    if (d < dt + tol) {
       mask |= 1ull << c;
-      if (dd > det_t - tol) unsure = true;
+      if (d > dt - tol) unsure = true;
     }
   }
   if (!valid) {
@@ -121,7 +135,7 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
     int ep = -1;
     uint64_t em = 0;
     for (int c = 0; c < cnt; ++c) {
-      const int p = __builtin_amdgcn_readfirstlane(list[c]);
+      const int p = __builtin_amdgcn_readlane(pid, c);
       if (exact) {
         const double X0 = P.X[3 * p], X1 = P.X[3 * p + 1], X2 = P.X[3 * p + 2];
         const double* R = P.R + 9 * p;
@@ -141,7 +155,11 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
       mask = em;
     }
   }
-  if (valid) owner[(long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z)] = bp;
+  // owner map: the owner, or NEAR_NONE for an unowned node with a possibly
+  // owned link neighbour, or -1 (no owner anywhere within one link)
+  if (valid)
+    owner[(long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z)] =
+        bp >= 0 ? bp : (near ? NEAR_NONE : -1);
 
   const uint64_t orm = wave_or_u64(mask);
   if (orm == 0) return;
@@ -151,14 +169,14 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
 
   for (int i = 0; i < cnt; ++i) {
     if (!((orm >> i) & 1ull)) continue;
-    const int pi = __builtin_amdgcn_readfirstlane(list[i]);
+    const int pi = __builtin_amdgcn_readlane(pid, i);
     const bool in_i = (mask >> i) & 1ull;
     for (int j = i + 1; j < cnt; ++j) {
       if (!((orm >> j) & 1ull)) continue;
       const bool pred = in_i && ((mask >> j) & 1ull);
       const uint64_t bal = __ballot(pred);
       if (bal == 0) continue;
-      const int pj = __builtin_amdgcn_readfirstlane(list[j]);
+      const int pj = __builtin_amdgcn_readlane(pid, j);
       const int a = pi < pj ? pi : pj, b = pi < pj ? pj : pi;
       int img[3];
       img[0] = x + g.nx * image_shift(fx - P.X[3 * a], Lx, true);

@@ -387,7 +387,7 @@ __device__ inline int cdir(uint64_t pk, int j) { return (int)((pk >> (2 * j)) & 
 // the per-node force and torque (link_group_sums) are committed per
 // wavefront.  Threads without an entry take part in the reductions only.
 template <typename S, typename C>
-__device__ void mea_compacted(C (*fl)[256], int (*meta)[7], int slot, int total,
+__device__ void mea_compacted(C (*fl)[256], int (*meta)[2], int slot, int total,
                               const BlockNode& nd, const Particles& P,
                               const Geom& g, const Phys& ph,
                               const int* __restrict__ owner, int lid,
@@ -402,11 +402,29 @@ __device__ void mea_compacted(C (*fl)[256], int (*meta)[7], int slot, int total,
     x = nd.x - (int)(threadIdx.x % WAVE) + (t % WAVE);
     y = nd.y - nd.wave + t / WAVE;
     o = meta[slot][1];
-    q = meta[slot][2];
-    q2 = meta[slot][3];
-    msk = (unsigned)meta[slot][4];
-    msk2 = (unsigned)meta[slot][5];
-    rem = (unsigned)meta[slot][6];
+    // owners of the 18 link neighbours (none beyond a wall).  Links whose
+    // far node is owned: by the primary particle (the node's owner, else
+    // the owner of its first owned neighbour), by a secondary particle, or
+    // by others (rare, found again below)
+    const Nbr nb = neighbours(g, x, y, z);
+    int on[Q];
+#pragma unroll
+    for (int j = 1; j < Q; ++j)
+      on[j] = nb.beyond(cz(j)) ? -1 : owner[nb.off(cx(j), cy(j), cz(j))];
+    q = o >= 0 ? o : -1;
+#pragma unroll
+    for (int j = 1; j < Q; ++j)
+      if (q < 0 && on[j] >= 0) q = on[j];
+#pragma unroll
+    for (int j = 1; j < Q; ++j)
+      if (q2 < 0 && on[j] >= 0 && on[j] != q) q2 = on[j];
+#pragma unroll
+    for (int j = 1; j < Q; ++j) {
+      if (on[j] < 0) continue;
+      if (on[j] == q) msk |= 1u << j;
+      else if (on[j] == q2) msk2 |= 1u << j;
+      else rem |= 1u << j;
+    }
   }
   const bool perz = g.periodic_z != 0;
   const bool wall_m = !perz && z == 0, wall_p = !perz && z == g.nz - 1;
@@ -492,7 +510,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   using C = typename Store<S>::C;
   __shared__ double red[4][LCAP_MAX][6];
   __shared__ C fl[Q][256];
-  __shared__ int meta[256][7];
+  __shared__ int meta[256][2];
   __shared__ int wcount[4];
   const BlockNode nd = block_node(g);
   const int x = nd.x, y = nd.y, z = nd.z;
@@ -505,11 +523,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 
   C f[Q];
   int o = -1;
-  // links j whose far node y + c_j is owned: by the primary particle Pp of
-  // the node (its owner, else the owner of its first owned neighbour), by a
-  // secondary particle Qp, or by a third one (rare)
-  int Pp = -1, Qp = -1;
-  unsigned mP = 0, mQ = 0, mR = 0;
   if (valid) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -523,24 +536,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       }
     }
     o = owner[self];
-    int on[Q];
-#pragma unroll
-    for (int j = 1; j < Q; ++j)
-      on[j] = nb.beyond(cz(j)) ? -1 : owner[nb.off(cx(j), cy(j), cz(j))];
-    Pp = o;
-#pragma unroll
-    for (int j = 1; j < Q; ++j)
-      if (Pp < 0 && on[j] >= 0) Pp = on[j];
-#pragma unroll
-    for (int j = 1; j < Q; ++j)
-      if (Qp < 0 && on[j] >= 0 && on[j] != Pp) Qp = on[j];
-#pragma unroll
-    for (int j = 1; j < Q; ++j) {
-      if (on[j] < 0) continue;
-      if (on[j] == Pp) mP |= 1u << j;
-      else if (on[j] == Qp) mQ |= 1u << j;
-      else mR |= 1u << j;
-    }
   } else {
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[i] = Store<S>::shifted ? (C)0 : (C)wgt(i);
@@ -597,13 +592,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   // equilibrium minus the storage shift: w_i [Ds + rho (3cu + 4.5cu^2 - 1.5u.u)]
   // with Ds = rho - 1 (= D) when shifted, rho otherwise
   const C Ds = Store<S>::shifted ? D : rho;
+  // f*_i = e2_i + keep (f_i - e1_i) = keep f_i + (e2_i - keep e1_i), and for
+  // the opposite pair (i, opp(i)), c . u changes sign, so
+  //   e2 - keep e1 = w_i [A + 4.5 rho ((c.v)^2 - keep (c.u)^2)]   (even)
+  //                 +/- 3 w_i rho (c.v - keep c.u)                  (odd)
+  // with A = (1 - keep) Ds - 1.5 rho (v.v - keep u.u).
+  const C A = ((C)1 - keep) * Ds - (C)1.5 * rho * (vv - keep * uu);
+  f[0] = keep * f[0] + (C)wgt(0) * A;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 1; i < Q; i += 2) {
     const C cu = (C)cx(i) * u0 + (C)cy(i) * u1 + (C)cz(i) * u2;
     const C cv = (C)cx(i) * v0 + (C)cy(i) * v1 + (C)cz(i) * v2;
-    const C e1 = (C)wgt(i) * (Ds + rho * ((C)3 * cu + (C)4.5 * cu * cu - (C)1.5 * uu));
-    const C e2 = (C)wgt(i) * (Ds + rho * ((C)3 * cv + (C)4.5 * cv * cv - (C)1.5 * vv));
-    f[i] = e2 + keep * (f[i] - e1);
+    const C wi = (C)wgt(i);
+    const C even = wi * (A + (C)4.5 * rho * (cv * cv - keep * (cu * cu)));
+    const C odd = (C)3 * wi * rho * (cv - keep * cu);
+    f[i] = keep * f[i] + (even + odd);
+    f[i + 1] = keep * f[i + 1] + (even - odd);
   }
   if (valid) {
 #pragma unroll
@@ -611,10 +615,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   }
 
   // ---- momentum exchange of the next step --------------------------------
-  // Compact the block's nodes that send terms to some particle (Pp >= 0)
-  // into LDS, then let the four wavefronts work through that list only.
+  // Compact the block's nodes that may send terms to some particle (owned,
+  // or with a possibly owned link neighbour) into LDS, then let the four
+  // wavefronts work through that list only.
   const int lane = threadIdx.x % WAVE;
-  const bool need = valid && Pp >= 0;
+  const bool need = valid && o != -1;
   const uint64_t nb_mask = __ballot(need);
   if (lane == 0) wcount[nd.wave] = __popcll(nb_mask);
   __syncthreads();
@@ -629,11 +634,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     for (int j = 1; j < Q; ++j) fl[j][slot] = f[j];
     meta[slot][0] = (int)threadIdx.x;
     meta[slot][1] = o;
-    meta[slot][2] = Pp;
-    meta[slot][3] = Qp;
-    meta[slot][4] = (int)mP;
-    meta[slot][5] = (int)mQ;
-    meta[slot][6] = (int)mR;
   }
   int cnt = tl.lcount[tile];
   cnt = __builtin_amdgcn_readfirstlane(cnt < g.tile_cap ? cnt : g.tile_cap);

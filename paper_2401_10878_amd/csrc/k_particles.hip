@@ -18,9 +18,7 @@ namespace {
 struct TileSpan {
   int lo[2], hi[2], n;
   __device__ int count() const {
-    int c = 0;
-    for (int k = 0; k < n; ++k) c += hi[k] - lo[k] + 1;
-    return c;
+    return (n > 0 ? hi[0] - lo[0] + 1 : 0) + (n > 1 ? hi[1] - lo[1] + 1 : 0);
   }
   __device__ int at(int i) const {
     const int len0 = hi[0] - lo[0] + 1;
@@ -69,8 +67,8 @@ __device__ TileSpan axis_tiles(double c, double e, int n, int nt, int ts,
 __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
                                                   double* __restrict__ Fh,
                                                   double* __restrict__ Th,
-                                                  const double* __restrict__ Fc,
-                                                  const double* __restrict__ Tc,
+                                                  double* __restrict__ Fc,
+                                                  double* __restrict__ Tc,
                                                   int move, Tiles tl, Counters* ctr) {
   const int ip = blockIdx.x;
   if (ip >= P.n) return;
@@ -100,14 +98,33 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
       F[m] = wave_sum(v[m]) + tl.ovf[6 * ip + m];
       T[m] = wave_sum(v[3 + m]) + tl.ovf[6 * ip + 3 + m];
     }
+    // contact force and torque: the particle's slots summed in the order
+    // of the partner id (lane k holds slot k; partners are distinct)
+    double Fcp[3] = {0.0, 0.0, 0.0}, Tcp[3] = {0.0, 0.0, 0.0};
+    {
+      int nc = tl.ccount[ip];
+      nc = nc < MAXC ? nc : MAXC;
+      const size_t e0 = (size_t)ip * MAXC;
+      const int key = lane < nc ? tl.ckey[e0 + lane] : 0x7fffffff;
+      int rank = 0;
+      for (int j = 0; j < nc; ++j) rank += __builtin_amdgcn_readlane(key, j) < key ? 1 : 0;
+      for (int r = 0; r < nc; ++r) {
+        const int j = __ffsll((long long)__ballot(lane < nc && rank == r)) - 1;
+        const double* cv = tl.cval + 6 * (e0 + j);
+        for (int m = 0; m < 3; ++m) {
+          Fcp[m] += cv[m];
+          Tcp[m] += cv[3 + m];
+        }
+      }
+    }
     // 2. Newton-Euler, symplectic Euler with Delta t = 1 (eqs. (2)-(3));
     // gravity minus buoyancy (rho_p - rho_f) V g with rho_f = 1 (Sec. 5.1).
     const double V = P.vol[ip], m = P.mass[ip], I = P.inert[ip];
     const double s = P.dens[ip];
     for (int k = 0; k < 3; ++k) {
       const double Fg = (s - 1.0) * V * ph.gravity[k];
-      const double Ft = F[k] + Fc[3 * ip + k] + Fg;
-      const double Tt = T[k] + Tc[3 * ip + k];
+      const double Ft = F[k] + Fcp[k] + Fg;
+      const double Tt = T[k] + Tcp[k];
       U[k] += Ft / m;
       X[k] += U[k];
       if (per[k]) {
@@ -133,6 +150,8 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
       for (int k = 0; k < 3; ++k) {
         Fh[3 * ip + k] = F[k];
         Th[3 * ip + k] = T[k];
+        Fc[3 * ip + k] = Fcp[k];
+        Tc[3 * ip + k] = Tcp[k];
       }
       for (int k = 0; k < 6; ++k) tl.ovf[6 * ip + k] = 0.0;
     }
@@ -146,6 +165,8 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
     }
     for (int k = 0; k < 4; ++k) P.q[4 * ip + k] = q[k];
     for (int k = 0; k < 9; ++k) P.R[9 * ip + k] = R[k];
+    for (int k = 0; k < 3; ++k) P.XR32[12 * ip + k] = (float)X[k];
+    for (int k = 0; k < 9; ++k) P.XR32[12 * ip + 3 + k] = (float)R[k];
   }
 
   // 3. Reach box: axis-aligned half extent of the body plus the largest
@@ -171,9 +192,21 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
     for (int k = 0; k < 3; ++k) sp[k] = axis_tiles(X[k], ext[k], n3[k], nt3[k], ts3[k], per[k]);
     const int cxn = sp[0].count(), cyn = sp[1].count(), czn = sp[2].count();
     const int total = cxn * cyn * czn;
+    // A tile whose centre lies farther from the body than the widest test of
+    // the node pass (a possibly owned link neighbour, eps/2 + sqrt 2, or
+    // detection, sqrt(0.75) + delta_c) plus the tile's radius has no node
+    // inside either bound (signed distances are 1-Lipschitz): skip it.
+    const double reach = fmax(0.5 * ph.eps + 1.4142135623730951, DETECT + ph.delta_c) +
+                         0.5 * sqrt((double)(DX - 1) * (DX - 1) + (DY - 1) * (DY - 1) +
+                                    (DZ - 1) * (DZ - 1)) + 0.01;
     for (int t = lane; t < total; t += WAVE) {
       const int ix = t % cxn, iy = (t / cxn) % cyn, iz = t / (cxn * cyn);
-      const long long tile = sp[0].at(ix) + (long long)g.dtx * (sp[1].at(iy) + (long long)g.dty * sp[2].at(iz));
+      const int tx = sp[0].at(ix), ty = sp[1].at(iy), tz = sp[2].at(iz);
+      const double rc[3] = {minimg(tx * DX + 0.5 * (DX - 1) - X[0], L[0], true),
+                            minimg(ty * DY + 0.5 * (DY - 1) - X[1], L[1], true),
+                            minimg(tz * DZ + 0.5 * (DZ - 1) - X[2], L[2], per[2])};
+      if (sdf(shape, size, R, rc[0], rc[1], rc[2]) > reach) continue;
+      const long long tile = tx + (long long)g.dtx * (ty + (long long)g.dty * tz);
       const int slot = atomicAdd(&tl.dcount[tile], 1);
       if (slot < g.tile_cap) tl.dlist[tile * g.tile_cap + slot] = ip;
       else atomicOr(&ctr->tile_overflow, 1);

@@ -98,6 +98,8 @@ def load():
     L.hlbm_stream.argtypes = [v]
     L.hlbm_stream.restype = v
     L.hlbm_fluid_acceleration.argtypes = [v, P(d)]
+    L.hlbm_get_state.argtypes = [v, v, P(C.c_size_t)]
+    L.hlbm_set_state.argtypes = [v, v, C.c_size_t]
     L.hlbm_adjoint_record.argtypes = [v, i, i]
     L.hlbm_adjoint_gradient.argtypes = [v] + [P(d)] * 7
     L.hlbm_last_error.argtypes = [v]
@@ -285,6 +287,18 @@ class Simulation:
         a = np.zeros(3)
         self._check(self.L.hlbm_fluid_acceleration(self.h, _dp(a)))
         return a
+
+    # ---- checkpoint / resume ------------------------------------------------
+    def get_state(self) -> bytes:
+        n = C.c_size_t()
+        self._check(self.L.hlbm_get_state(self.h, None, C.byref(n)))
+        buf = (C.c_char * n.value)()
+        self._check(self.L.hlbm_get_state(self.h, buf, C.byref(n)))
+        return bytes(buf)
+
+    def set_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        self._check(self.L.hlbm_set_state(self.h, buf, len(blob)))
 
     # ---- adjoint ------------------------------------------------------------
     def adjoint_record(self, ksteps, ckpt_every):

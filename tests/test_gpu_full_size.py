@@ -105,3 +105,25 @@ def test_dense_cube_box_full_size(dense_cubes, H, prec):
 def test_dense_sphere_box_full_size(dense_spheres, H, prec):
     wl, ref = dense_spheres
     _check(H, wl, ref, prec)
+
+
+def test_dense_cube_box_bitwise_reproducible(W, H):
+    """Two runs of the benchmark workload (FP32, 30 steps with contacts)
+    give identical bits: every reduction on the path has a fixed order."""
+    wl = W.c3_dense_cubes()
+    out = []
+    for _ in range(2):
+        g = H.Simulation(wl.params, wl.scene)
+        g.init_equilibrium()
+        g.step(30)
+        e = g.forces()
+        out.append((g.particles(), e, g.populations()[:, ::7, ::5, ::3].copy(),
+                    [(c["a"], c["b"], c["count"], c["fn"]) for c in g.contacts()]))
+        g.close()
+    (pa, ea, fa, ca), (pb, eb, fb, cb) = out
+    assert len(ca) > 0 and ca == cb
+    for k in pa:
+        assert np.array_equal(pa[k], pb[k]), k
+    for k in ea:
+        assert np.array_equal(ea[k], eb[k]), k
+    assert np.array_equal(fa, fb)

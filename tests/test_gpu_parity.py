@@ -253,3 +253,34 @@ def test_walled_settling_workload_parity(O, W, H):
         assert [(c["a"], c["b"], c["count"]) for c in oc] == \
                [(c["a"], c["b"], c["count"]) for c in gc]
     assert rel_field(g.populations(), o.populations()) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_state_checkpoint_resume(W, H, prec):
+    """A state saved to the host and restored into a fresh context continues
+    bit for bit like the original."""
+    sc = W.random_small_scene(31, (22, 26, 19), 6, size_range=(1.6, 2.8),
+                              gap=-0.6, speed=0.01, spin=0.004)
+    p = W.Params(nx=22, ny=26, nz=19, tau=0.7, gravity=(0.0, 0.0, -2e-4),
+                 balance=1, young=0.4, u_k=3e-4, max_pairs=256,
+                 tile_capacity=16, precision=prec)
+    a = H.Simulation(p, sc)
+    a.init_equilibrium(u=(0.002, 0.0, -0.001))
+    a.step(5)
+    blob = a.get_state()
+    a.step(7)
+    b = H.Simulation(p, sc)
+    b.set_state(blob)
+    b.step(7)
+    assert np.array_equal(a.populations(), b.populations())
+    pa, pb = a.particles(), b.particles()
+    for k in pa:
+        assert np.array_equal(pa[k], pb[k]), k
+    assert [(c["a"], c["b"], c["count"], c["volume"]) for c in a.contacts()] == \
+           [(c["a"], c["b"], c["count"], c["volume"]) for c in b.contacts()]
+    assert a.counters()["steps"] == b.counters()["steps"]
+    # a blob of another configuration is refused
+    other = H.Simulation(p.replace(nx=23), sc)
+    with pytest.raises(H.HlbmError) as e:
+        other.set_state(blob)
+    assert e.value.code == -1
