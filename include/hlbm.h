@@ -83,6 +83,10 @@ typedef struct {
     int max_pairs;              /* capacity of the contact-pair table */
     int tile_capacity;          /* particles per 4x4x4 tile, <= 64 */
     int precision;              /* hlbm_precision */
+    int n_sub;                  /* contact sub-steps per time step, 1..64
+                                   (Sec. 4.4, Algorithm 1): contact forces,
+                                   motion over 1/n_sub and detection repeat
+                                   with the hydrodynamic force held fixed */
 } hlbm_params;
 
 /* One contact record.  b >= 0: particle-particle with a < b; b = -1: the

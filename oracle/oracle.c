@@ -972,11 +972,12 @@ static int treat_contacts(orc_sim *S)
 }
 
 /* ======================================================================
- * Particle motion, eqs. (2)-(3): symplectic Euler with Delta t = 1; gravity
- * minus buoyancy F_g = (rho_p - rho_f) V g (Sec. 5.1) with rho_f = 1;
- * orientation advanced by the exact rotation through |w| about w.
+ * Particle motion, eqs. (2)-(3): symplectic Euler over a sub-step of length
+ * dt (1 without sub-steps); gravity minus buoyancy F_g = (rho_p - rho_f) V g
+ * (Sec. 5.1) with rho_f = 1; orientation advanced by the exact rotation
+ * through |w| dt about w.
  * ====================================================================== */
-static void move_particles(orc_sim *S)
+static void move_particles(orc_sim *S, double dt)
 {
     const orc_params *P = &S->P;
     int dims[3] = {P->nx, P->ny, P->nz};
@@ -990,18 +991,18 @@ static void move_particles(orc_sim *S)
             double Fg = (pp->dens - 1.0) * V * P->gravity[k];
             double F = S->Fh[3 * ip + k] + S->Fc[3 * ip + k] + Fg;
             double T = S->Th[3 * ip + k] + S->Tc[3 * ip + k];
-            pp->U[k] += F / m;
-            pp->X[k] += pp->U[k];
+            pp->U[k] += F / m * dt;
+            pp->X[k] += pp->U[k] * dt;
             if (per[k]) {
                 if (pp->X[k] >= (double)dims[k]) pp->X[k] -= (double)dims[k];
                 else if (pp->X[k] < 0.0) pp->X[k] += (double)dims[k];
             }
-            pp->w[k] += T / I;
+            pp->w[k] += T / I * dt;
         }
         double th = sqrt(pp->w[0] * pp->w[0] + pp->w[1] * pp->w[1] +
-                         pp->w[2] * pp->w[2]);
+                         pp->w[2] * pp->w[2]) * dt;
         if (th > 0.0) {
-            double c = cos(0.5 * th), s = sin(0.5 * th) / th;
+            double c = cos(0.5 * th), s = sin(0.5 * th) / th * dt;
             double dq[4] = {c, s * pp->w[0], s * pp->w[1], s * pp->w[2]};
             const double *q = pp->q;
             double r[4];
@@ -1053,11 +1054,13 @@ static void collide(orc_sim *S)
 }
 
 /* ======================================================================
- * Time step (Algorithm 1, one sub-step): couple fluid to particles, treat
- * contacts, apply gravity and move particles, couple particles to fluid with
- * contact detection, collide.  The stored state between steps is the
- * post-collision field f*, so each step begins with the streaming half of
- * the previous "collide and stream".
+ * Time step (Sec. 4.4, Algorithm 1): couple fluid to particles; then, in
+ * each of n_sub sub-steps of length 1/n_sub with the hydrodynamic force and
+ * torque held constant, treat contacts, apply gravity and move particles,
+ * couple particles to fluid with contact detection; finally collide.  The
+ * stored state between steps is the post-collision field f*, so each step
+ * begins with the streaming half of the previous "collide and stream".  The
+ * contact forces reported are those of the last sub-step.
  * ====================================================================== */
 static int prologue(orc_sim *S)
 {
@@ -1092,13 +1095,16 @@ int orc_step(orc_sim *S, int nsteps)
     for (int it = 0; it < nsteps; ++it) {
         stream(S);
         momentum_exchange(S);
-        int nkeep = treat_contacts(S);
-        move_particles(S);
-        if (couple_and_detect_nodes(S) != 0) {
-            set_err(S, "detection set overflow (more than ORC_MAXK particles at a node)");
-            return -1;
+        const int nsub = S->P.n_sub > 1 ? S->P.n_sub : 1;
+        for (int sub = 0; sub < nsub; ++sub) {
+            int nkeep = treat_contacts(S);
+            move_particles(S, 1.0 / (double)nsub);
+            if (couple_and_detect_nodes(S) != 0) {
+                set_err(S, "detection set overflow (more than ORC_MAXK particles at a node)");
+                return -1;
+            }
+            detect_and_merge(S, nkeep);
         }
-        detect_and_merge(S, nkeep);
         collide(S);
         S->step++;
     }

@@ -39,6 +39,7 @@ typedef struct {
     double delta_c;          /* enlargement during contact treatment */
     int n_c;                 /* contact resolution */
     double young, poisson, restitution, mu_s, mu_k, u_k;
+    int n_sub;               /* contact sub-steps per time step (>= 1) */
 } orc_params;
 
 typedef struct {

@@ -28,7 +28,8 @@ class OrcParams(C.Structure):
                 ("delta_c", C.c_double), ("n_c", C.c_int),
                 ("young", C.c_double), ("poisson", C.c_double),
                 ("restitution", C.c_double), ("mu_s", C.c_double),
-                ("mu_k", C.c_double), ("u_k", C.c_double)]
+                ("mu_k", C.c_double), ("u_k", C.c_double),
+                ("n_sub", C.c_int)]
 
 
 class OrcParticle(C.Structure):
@@ -131,6 +132,7 @@ def make_params(p) -> OrcParams:
     o.n_c = p.n_c
     o.young, o.poisson, o.restitution = p.young, p.poisson, p.restitution
     o.mu_s, o.mu_k, o.u_k = p.mu_s, p.mu_k, p.u_k
+    o.n_sub = p.n_sub
     return o
 
 

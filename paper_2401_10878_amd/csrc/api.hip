@@ -81,7 +81,7 @@ hlbm_status ensure_populations(Ctx& c) {
 }
 
 void drop_graphs(Ctx& c) {
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 4; ++k) {
     if (c.graph_ready[k]) hipGraphExecDestroy(c.gexec[k]);
     c.graph_ready[k] = false;
   }
@@ -92,7 +92,7 @@ void drop_graphs(Ctx& c) {
 // momentum-exchange force that moves the particles in the first step.
 hlbm_status prologue(Ctx& c) {
   drop_graphs(c);
-  const int p = c.cur;
+  const int p = c.tcur;
   const size_t nb = sizeof(double) * 3 * (c.np > 0 ? c.np : 1);
   HIPCHECK(launch_clear_step(c, c.tab[p]));
   HIPCHECK(hipMemsetAsync(c.Fh, 0, nb, c.stream));
@@ -106,31 +106,45 @@ hlbm_status prologue(Ctx& c) {
   return check_flags(c);
 }
 
-// The launch sequence of one time step with parity p (buffers p -> 1-p).
-// ev (optional): NKERN + 1 events recorded around the launches.
-hipError_t enqueue_step(Ctx& c, int p, hipEvent_t* ev) {
+// The launch sequence of one time step with population parity p (buffers
+// p -> 1-p) starting from contact table t; the table parity flips once per
+// sub-step.  ev (optional): 2 + 5 n_sub events recorded around the launches.
+hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev) {
   hipError_t e;
-  auto mark = [&](int k) -> hipError_t {
-    return ev ? hipEventRecord(ev[k], c.stream) : hipSuccess;
+  int m = 0;
+  auto mark = [&]() -> hipError_t {
+    return ev ? hipEventRecord(ev[m++], c.stream) : hipSuccess;
   };
-  if ((e = mark(0))) return e;
-  if ((e = launch_clear_step(c, c.tab[1 - p]))) return e;
-  if ((e = mark(1))) return e;
-  if ((e = launch_treat(c, c.tab[p]))) return e;
-  if ((e = mark(2))) return e;
-  if ((e = launch_particles(c, 1))) return e;
-  if ((e = mark(3))) return e;
-  if ((e = launch_keep(c, c.tab[p], c.tab[1 - p]))) return e;
-  if ((e = mark(4))) return e;
-  if ((e = launch_detect(c, c.tab[1 - p]))) return e;
-  if ((e = mark(5))) return e;
+  if ((e = mark())) return e;
+  for (int s = 0; s < c.n_sub; ++s) {
+    if ((e = launch_clear_step(c, c.tab[1 - t]))) return e;
+    if ((e = mark())) return e;
+    if ((e = launch_treat(c, c.tab[t]))) return e;
+    if ((e = mark())) return e;
+    if ((e = launch_particles(c, s == 0 ? 1 : 2))) return e;
+    if ((e = mark())) return e;
+    if ((e = launch_keep(c, c.tab[t], c.tab[1 - t]))) return e;
+    if ((e = mark())) return e;
+    if ((e = launch_detect(c, c.tab[1 - t]))) return e;
+    if ((e = mark())) return e;
+    t = 1 - t;
+  }
   if ((e = launch_lattice(c, c.fbuf[p], c.fbuf[1 - p]))) return e;
-  return mark(6);
+  return mark();
+}
+
+// the step that the next hlbm_step would run, and the parities after it
+hipError_t run_step(Ctx& c, hipEvent_t* ev) {
+  hipError_t e = enqueue_step(c, c.cur, c.tcur, ev);
+  c.cur = 1 - c.cur;
+  c.tcur = (c.n_sub & 1) ? 1 - c.tcur : c.tcur;
+  c.step++;
+  return e;
 }
 
 void free_timing(Ctx& c) {
   if (c.tev) {
-    for (int i = 0; i < c.tcap * (NKERN + 1); ++i) hipEventDestroy(c.tev[i]);
+    for (int i = 0; i < c.tcap * c.ev_per_step; ++i) hipEventDestroy(c.tev[i]);
     delete[] c.tev;
   }
   c.tev = nullptr;
@@ -194,9 +208,11 @@ hipError_t snapshot_copy(Ctx& c, Snapshot& s, int dir) {
   };
   if (dir == 0) {
     s.cur = c.cur;
+    s.tcur = c.tcur;
     s.step = c.step;
   } else {
     c.cur = s.cur;
+    c.tcur = s.tcur;
     c.step = s.step;
   }
   if ((e = cp(s.f, c.fbuf[c.cur], pop_bytes(c)))) return e;
@@ -239,6 +255,7 @@ hlbm_status hlbm_create(const hlbm_params* params, void* stream, hlbm_ctx** out)
   if (P.tile_capacity < 1 || P.tile_capacity > LCAP_MAX) return bad("tile_capacity must be 1..64");
   if (P.max_pairs < 1 || P.max_pairs > (1 << 24)) return bad("max_pairs must be 1..2^24");
   if (P.precision < 0 || P.precision > 2) return bad("precision must be 0, 1 or 2");
+  if (P.n_sub < 1 || P.n_sub > 64) return bad("n_sub must be 1..64");
   if (!(P.eps_b > 0.0) || !(P.enlarge >= 0.0)) return bad("eps_b > 0 and enlarge >= 0 required");
   if (!(P.young > 0.0) || !(P.u_k > 0.0) || !(P.mu_s > 0.0))
     return bad("young, u_k and mu_s must be positive");
@@ -273,6 +290,9 @@ hlbm_status hlbm_create(const hlbm_params* params, void* stream, hlbm_ctx** out)
   c.ph.mu_s = P.mu_s;
   c.ph.mu_k = P.mu_k;
   c.ph.u_k = P.u_k;
+  c.n_sub = P.n_sub;
+  c.ph.dt_sub = 1.0 / (double)P.n_sub;
+  c.ev_per_step = 2 + 5 * P.n_sub;
 
   if (stream) {
     c.stream = (hipStream_t)stream;
@@ -487,6 +507,7 @@ hlbm_status hlbm_init_fluid_equilibrium(hlbm_ctx* h, double rho, const double u[
   hlbm_status st = ensure_populations(c);
   if (st) return st;
   c.cur = 0;
+  c.tcur = 0;
   HIPCHECK(launch_fill_equilibrium(c, c.fbuf[c.cur], rho, u));
   return prologue(c);
 }
@@ -500,6 +521,7 @@ hlbm_status hlbm_set_populations(hlbm_ctx* h, const double* f) {
   hlbm_status st = ensure_populations(c);
   if (st) return st;
   c.cur = 0;
+  c.tcur = 0;
   const size_t n = (size_t)c.g.ncell;
   for (int i = 0; i < Q; ++i) {
     HIPCHECK(hipMemcpyAsync(c.scratch, f + (size_t)i * n, sizeof(double) * n,
@@ -515,33 +537,34 @@ hlbm_status hlbm_step(hlbm_ctx* h, int nsteps) {
   if (!c.fluid_ready) return fail(c, HLBM_E_STATE, "initialise particles and fluid first");
   if (nsteps < 0) return fail(c, HLBM_E_ARG, "nsteps must be >= 0");
   for (int s = 0; s < nsteps; ++s) {
-    const int p = c.cur;
     if (c.timing) {
       if (c.tused >= c.tcap)
         return fail(c, HLBM_E_CAPACITY, "timing window of %d steps is full", c.tcap);
-      HIPCHECK(enqueue_step(c, p, c.tev + (size_t)c.tused * (NKERN + 1)));
+      HIPCHECK(run_step(c, c.tev + (size_t)c.tused * c.ev_per_step));
       c.tused++;
     } else if (c.use_graph) {
-      if (!c.graph_ready[p]) {
+      const int key = 2 * c.cur + c.tcur;
+      if (!c.graph_ready[key]) {
         hipGraph_t gr;
         HIPCHECK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue_step(c, p, nullptr);
+        hipError_t e = enqueue_step(c, c.cur, c.tcur, nullptr);
         hipError_t e2 = hipStreamEndCapture(c.stream, &gr);
         if (e != hipSuccess || e2 != hipSuccess)
           return fail(c, HLBM_E_DEVICE, "graph capture: %s",
                       hipGetErrorString(e != hipSuccess ? e : e2));
-        e = hipGraphInstantiate(&c.gexec[p], gr, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&c.gexec[key], gr, nullptr, nullptr, 0);
         hipGraphDestroy(gr);
         if (e != hipSuccess)
           return fail(c, HLBM_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
-        c.graph_ready[p] = true;
+        c.graph_ready[key] = true;
       }
-      HIPCHECK(hipGraphLaunch(c.gexec[p], c.stream));
+      HIPCHECK(hipGraphLaunch(c.gexec[key], c.stream));
+      c.cur = 1 - c.cur;
+      c.tcur = (c.n_sub & 1) ? 1 - c.tcur : c.tcur;
+      c.step++;
     } else {
-      HIPCHECK(enqueue_step(c, p, nullptr));
+      HIPCHECK(run_step(c, nullptr));
     }
-    c.cur = 1 - p;
-    c.step++;
   }
   return HLBM_OK;
 }
@@ -558,12 +581,12 @@ hlbm_status hlbm_timing_begin(hlbm_ctx* h, int max_steps) {
   if (max_steps < 1 || max_steps > 100000)
     return fail(c, HLBM_E_ARG, "timing window must be 1..100000 steps");
   free_timing(c);
-  c.tev = new (std::nothrow) hipEvent_t[(size_t)max_steps * (NKERN + 1)];
+  c.tev = new (std::nothrow) hipEvent_t[(size_t)max_steps * c.ev_per_step];
   if (!c.tev) return fail(c, HLBM_E_NOMEM, "timing events");
-  for (int i = 0; i < max_steps * (NKERN + 1); ++i) {
+  for (int i = 0; i < max_steps * c.ev_per_step; ++i) {
     hipError_t e = hipEventCreate(&c.tev[i]);
     if (e != hipSuccess) {
-      c.tcap = i / (NKERN + 1);
+      c.tcap = i / c.ev_per_step;
       free_timing(c);
       return fail(c, HLBM_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
     }
@@ -580,13 +603,19 @@ hlbm_status hlbm_timing_end(hlbm_ctx* h, double* kernel_ms, int* nsteps) {
   if (!c.timing) return fail(c, HLBM_E_STATE, "timing_begin was not called");
   HIPCHECK(hipStreamSynchronize(c.stream));
   for (int k = 0; k < NKERN; ++k) kernel_ms[k] = 0.0;
+  // events: start, then per sub-step after clear, treat, particles, keep,
+  // detect; then after the lattice pass
   for (int s = 0; s < c.tused; ++s) {
-    hipEvent_t* ev = c.tev + (size_t)s * (NKERN + 1);
-    for (int k = 0; k < NKERN; ++k) {
-      float ms = 0.0f;
-      HIPCHECK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
-      kernel_ms[k] += (double)ms;
-    }
+    hipEvent_t* ev = c.tev + (size_t)s * c.ev_per_step;
+    for (int sub = 0; sub < c.n_sub; ++sub)
+      for (int k = 0; k < 5; ++k) {
+        float ms = 0.0f;
+        HIPCHECK(hipEventElapsedTime(&ms, ev[5 * sub + k], ev[5 * sub + k + 1]));
+        kernel_ms[k] += (double)ms;
+      }
+    float ms = 0.0f;
+    HIPCHECK(hipEventElapsedTime(&ms, ev[c.ev_per_step - 2], ev[c.ev_per_step - 1]));
+    kernel_ms[5] += (double)ms;
   }
   *nsteps = c.tused;
   free_timing(c);
@@ -634,7 +663,7 @@ hlbm_status hlbm_read_contacts(hlbm_ctx* h, int capacity, hlbm_contact* out, int
   if (!h || !n_out || capacity < 0 || (capacity > 0 && !out)) return HLBM_E_ARG;
   Ctx& c = h->c;
   if (!c.fluid_ready) return fail(c, HLBM_E_STATE, "not initialised");
-  const PairTable& t = c.tab[c.cur];
+  const PairTable& t = c.tab[c.tcur];
   std::vector<uint64_t> keys(t.cap);
   std::vector<PairRec> rec(t.cap);
   HIPCHECK(hipMemcpyAsync(keys.data(), t.keys, sizeof(uint64_t) * t.cap,
@@ -700,9 +729,10 @@ hlbm_status hlbm_read_fields(hlbm_ctx* h, double* rho, double* u, int* owner) {
   if (owner)
     HIPCHECK(hipMemcpyAsync(owner, c.owner, sizeof(int) * n, hipMemcpyDeviceToHost, c.stream));
   HIPCHECK(hipStreamSynchronize(c.stream));
-  // every negative code of the device map reads as "no owner"
+  // every negative code of the device map reads as "no owner"; the interior
+  // flag is dropped
   if (owner)
-    for (size_t i = 0; i < n; ++i) owner[i] = owner[i] < 0 ? -1 : owner[i];
+    for (size_t i = 0; i < n; ++i) owner[i] = owner[i] < 0 ? -1 : (owner[i] & (OWNER_INTERIOR - 1));
   return check_flags(c);
 }
 
@@ -746,7 +776,7 @@ hlbm_status hlbm_fluid_acceleration(const hlbm_ctx* h, double a[3]) {
 namespace {
 struct StateHeader {
   char magic[8];
-  int version, precision, nx, ny, nz, np, cur, cap;
+  int version, precision, nx, ny, nz, np, cur, tcur, cap, n_sub;
   long long step;
   unsigned long long f_bytes, part_bytes, tile_bytes, psum_bytes, tab_bytes,
       owner_bytes;
@@ -780,7 +810,9 @@ hlbm_status hlbm_get_state(hlbm_ctx* h, void* blob, size_t* bytes) {
   hd.nx = c.g.nx; hd.ny = c.g.ny; hd.nz = c.g.nz;
   hd.np = c.np;
   hd.cur = c.cur;
+  hd.tcur = c.tcur;
   hd.cap = (int)cap;
+  hd.n_sub = c.n_sub;
   hd.step = c.step;
   hd.f_bytes = pop_bytes(c);
   hd.part_bytes = c.part_bytes;
@@ -823,7 +855,7 @@ hlbm_status hlbm_set_state(hlbm_ctx* h, const void* blob, size_t bytes) {
   if (memcmp(hd.magic, kMagic, 8) != 0 || hd.version != 1)
     return fail(c, HLBM_E_ARG, "not a state blob of this library");
   if (hd.precision != c.precision || hd.nx != c.g.nx || hd.ny != c.g.ny || hd.nz != c.g.nz ||
-      hd.np != c.np || hd.cap != (int)cap || hd.part_bytes != c.part_bytes ||
+      hd.np != c.np || hd.cap != (int)cap || hd.n_sub != c.n_sub || hd.part_bytes != c.part_bytes ||
       hd.tile_bytes != c.tile_bytes || hd.psum_bytes != c.psum_bytes)
     return fail(c, HLBM_E_ARG, "state blob was written by a different configuration");
   if (bytes < state_bytes(c)) return fail(c, HLBM_E_ARG, "state blob truncated");
@@ -831,6 +863,7 @@ hlbm_status hlbm_set_state(hlbm_ctx* h, const void* blob, size_t bytes) {
   if (st) return st;
   drop_graphs(c);
   c.cur = hd.cur;
+  c.tcur = hd.tcur;
   c.step = hd.step;
   const char* o = (const char*)blob + sizeof hd;
   auto put = [&](void* dev, size_t n) {
@@ -861,6 +894,7 @@ hlbm_status hlbm_adjoint_record(hlbm_ctx* h, int ksteps, int ckpt_every) {
   if (c.precision != HLBM_FP64)
     return fail(c, HLBM_E_ARG, "the adjoint runs on the FP64 form only");
   if (!c.g.periodic_z) return fail(c, HLBM_E_ARG, "the adjoint needs a fully periodic box");
+  if (c.n_sub != 1) return fail(c, HLBM_E_ARG, "the adjoint runs without contact sub-steps");
   if (c.timing) return fail(c, HLBM_E_STATE, "finish the timing window first");
   if (ksteps < 1 || ckpt_every < 1)
     return fail(c, HLBM_E_ARG, "ksteps and ckpt_every must be >= 1");
@@ -883,11 +917,7 @@ hlbm_status hlbm_adjoint_record(hlbm_ctx* h, int ksteps, int ckpt_every) {
   for (int seg = 0; seg < a.nseg; ++seg) {
     HIPCHECK(snapshot_copy(c, a.ck[seg], 0));
     const int n = std::min(a.L, a.K - seg * a.L);
-    for (int s = 0; s < n; ++s) {
-      HIPCHECK(enqueue_step(c, c.cur, nullptr));
-      c.cur = 1 - c.cur;
-      c.step++;
-    }
+    for (int s = 0; s < n; ++s) HIPCHECK(run_step(c, nullptr));
   }
   HIPCHECK(snapshot_copy(c, a.end, 0));
   hlbm_status st = check_flags(c);
@@ -942,9 +972,7 @@ hlbm_status hlbm_adjoint_gradient(hlbm_ctx* h, const double* dJ_dU, double* dJ_d
                               hipMemcpyDeviceToDevice, c.stream));
       HIPCHECK(launch_rec_particles(c, a.pst + (size_t)k * npp * PR));
       if (k == L) break;
-      HIPCHECK(enqueue_step(c, c.cur, nullptr));
-      c.cur = 1 - c.cur;
-      c.step++;
+      HIPCHECK(run_step(c, nullptr));
       HIPCHECK(launch_rec_forces(c, a.frc + (size_t)k * npp * 12));
     }
     for (int k = L - 1; k >= 0; --k)

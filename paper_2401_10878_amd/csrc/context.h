@@ -88,6 +88,7 @@ struct Phys {
   int n_c;
   double estar;           // effective modulus, eq. (5)
   double restitution, mu_s, mu_k, u_k;
+  double dt_sub;          // length of a contact sub-step (1 / n_sub)
 };
 
 constexpr int NKERN = 6;   // clear, treat, particles, keep, detect, lattice
@@ -103,7 +104,7 @@ struct Snapshot {
   PairRec* rec[2] = {nullptr, nullptr};
   int* owner = nullptr;
   Counters* ctr = nullptr;
-  int cur = 0;
+  int cur = 0, tcur = 0;
   long long step = 0;
 };
 
@@ -165,15 +166,19 @@ struct Ctx {
   // sizes of the state blocks (for snapshots)
   size_t part_bytes = 0, tile_bytes = 0, psum_bytes = 0;
   Adjoint adj;
-  // graphs: one per parity of (cur, fcur, tcur)
+  // graphs: one per (population parity, contact-table parity)
   bool use_graph;
-  hipGraphExec_t gexec[2];
-  bool graph_ready[2];
+  hipGraphExec_t gexec[4];
+  bool graph_ready[4];
+  int n_sub;
+  int ev_per_step;        // timing events per step: 2 + 5 n_sub
   std::string err;
 };
 
 // ---- launch wrappers (kernels live in the .hip files) --------------------
 hipError_t launch_clear_step(Ctx& c, PairTable next);
+// move: 0 bin only, 1 gather the hydrodynamic force and move, 2 move with
+// the stored hydrodynamic force (later sub-steps)
 hipError_t launch_particles(Ctx& c, int move);
 hipError_t launch_keep(Ctx& c, PairTable from, PairTable to);
 hipError_t launch_detect(Ctx& c, PairTable to);

@@ -27,6 +27,10 @@ constexpr int MAXC = 32;        // contacts per particle in one step
 // owner-map code of a node with no owner but a link neighbour that may have
 // one (every negative code means "no owner")
 constexpr int NEAR_NONE = -2;
+// flag on the owner code of a node whose 18 link neighbours are all owned by
+// the same particle (the node lies deep inside it and no other body reaches)
+constexpr int OWNER_INTERIOR = 1 << 30;
+__device__ inline int owner_id(int v) { return v < 0 ? -1 : (v & (OWNER_INTERIOR - 1)); }
 constexpr int WAVE = 64;
 constexpr double DETECT = 0.8660254037844386;   // sqrt(0.75), Sec. 3.3.1
 constexpr double PI = 3.141592653589793;

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(
       J[2] += cz(i) * f[i];
     }
     const double u[3] = {J[0] / rho, J[1] / rho, J[2] / rho};
-    o = owner[id];
+    o = owner_id(owner[id]);
     double B = 0.0, Bp = 0.0, up[3] = {0.0, 0.0, 0.0}, r[3] = {0.0, 0.0, 0.0};
     double nrm[3] = {0.0, 0.0, 0.0};
     const double* pr = nullptr;
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(256) void k_adj_mea(
   double inc[PB];
   for (int k = 0; k < PB; ++k) inc[k] = 0.0;
   int o = -1;
-  if (id < n) o = owner[id];
+  if (id < n) o = owner_id(owner[id]);
   if (o >= 0) {
     int x, y, z;
     node_xyz(id, g, x, y, z);
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(256) void k_adj_stream(
   if (id >= n) return;
   int x, y, z;
   node_xyz(id, g, x, y, z);
-  const int o = owner[id];
+  const int o = owner_id(owner[id]);
   double Sb[3] = {0.0, 0.0, 0.0}, up[3] = {0.0, 0.0, 0.0};
   if (o >= 0) {
     const double* pr = prec + (size_t)PREC_N * o;

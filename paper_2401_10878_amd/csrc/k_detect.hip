@@ -96,8 +96,8 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
   // Pass 1, FP32: classify each candidate against both thresholds with a
   // bound on the FP32 error; a lane is settled when every candidate is
   // clearly on one side of both thresholds and at most one can own it.
-  int bp = -1, nown = 0;
-  bool unsure = false, near = false;
+  int bp = -1, nown = 0, nnear = 0;
+  bool unsure = false, deep = false;
   uint64_t mask = 0;
   for (int c = 0; c < cnt; ++c) {
     const int p = __builtin_amdgcn_readlane(pid, c);
@@ -111,11 +111,13 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
     const float tol = 1e-3f + 1e-5f * (fabsf(f0) + fabsf(f1) + fabsf(f2) + size);
     const float ot = (float)own_t, dt = (float)det_t;
     // a link neighbour (at most sqrt 2 away) can be owned by p only if
-    // d < eps/2 + sqrt 2 here (signed distances are 1-Lipschitz)
-    if (d < ot + 1.4142135f + tol) near = true;
+    // d < eps/2 + sqrt 2 here, and is surely inside the owning band of p if
+    // d < -eps/2 - sqrt 2 (signed distances are 1-Lipschitz)
+    if (d < ot + 1.4142135f + tol) ++nnear;
     if (d < ot + tol) {
       ++nown;
       bp = p;
+      deep = d < -ot - 1.4142135f - tol;
       if (d > ot - tol) unsure = true;
     }
     if (d < dt + tol) {
@@ -155,11 +157,16 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
       mask = em;
     }
   }
-  // owner map: the owner, or NEAR_NONE for an unowned node with a possibly
-  // owned link neighbour, or -1 (no owner anywhere within one link)
+  // owner map: the owner (flagged OWNER_INTERIOR when the node is deep inside
+  // it, no other body comes within reach of a link neighbour and no link
+  // crosses a wall, so that all 18 link neighbours are owned by it), or
+  // NEAR_NONE for an unowned node with a possibly owned link neighbour, or
+  // -1 (no owner anywhere within one link)
+  const bool wall_adj = !perz && (z == 0 || z == g.nz - 1);
+  const bool interior = !exact && bp >= 0 && deep && nnear == 1 && !wall_adj;
   if (valid)
     owner[(long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z)] =
-        bp >= 0 ? bp : (near ? NEAR_NONE : -1);
+        bp >= 0 ? (interior ? (bp | OWNER_INTERIOR) : bp) : (nnear > 0 ? NEAR_NONE : -1);
 
   const uint64_t orm = wave_or_u64(mask);
   if (orm == 0) return;

@@ -327,6 +327,38 @@ __device__ inline void link_group_sums(H hval, unsigned msk, bool own,
   Tc[2] = (m1[0] * up[1] - m1[1] * up[0]) + w[2] * K - (xz * w[0] + yz * w[1] + zz * w[2]);
 }
 
+// link_group_sums for a node whose owner also owns all 18 link neighbours:
+// the complement sums vanish, so S = w x M1 and T_c = M1 x u_p + w K - M2 w
+// with the full moments of the 18 moving populations.  Their rest-weight
+// parts are sum_j w_j c_j = 0 and sum_j w_j c_j c_j^T = I/3 (K = 1).
+template <bool SHIFTED, typename H>
+__device__ inline void interior_sums(H hval, const double* up, const double* w,
+                                     double* S, double* Tc) {
+  using C = decltype(hval(1));
+  C M1x = 0, M1y = 0, M1z = 0, Mxx = 0, Myy = 0, Mzz = 0, Mxy = 0, Mxz = 0, Myz = 0;
+#pragma unroll
+  for (int j = 1; j < Q; ++j) {
+    const C h = hval(j);
+    if (cx(j)) { M1x += cx(j) > 0 ? h : -h; Mxx += h; }
+    if (cy(j)) { M1y += cy(j) > 0 ? h : -h; Myy += h; }
+    if (cz(j)) { M1z += cz(j) > 0 ? h : -h; Mzz += h; }
+    if (cx(j) * cy(j)) Mxy += cx(j) * cy(j) > 0 ? h : -h;
+    if (cx(j) * cz(j)) Mxz += cx(j) * cz(j) > 0 ? h : -h;
+    if (cy(j) * cz(j)) Myz += cy(j) * cz(j) > 0 ? h : -h;
+  }
+  const double third = SHIFTED ? 1.0 / 3.0 : 0.0;
+  const double m1[3] = {M1x, M1y, M1z};
+  const double xx = (double)Mxx + third, yy = (double)Myy + third, zz = (double)Mzz + third;
+  const double xy = Mxy, xz = Mxz, yz = Myz;
+  S[0] = w[1] * m1[2] - w[2] * m1[1];
+  S[1] = w[2] * m1[0] - w[0] * m1[2];
+  S[2] = w[0] * m1[1] - w[1] * m1[0];
+  const double K = (xx + yy) + zz;
+  Tc[0] = (m1[1] * up[2] - m1[2] * up[1]) + w[0] * K - (xx * w[0] + xy * w[1] + xz * w[2]);
+  Tc[1] = (m1[2] * up[0] - m1[0] * up[2]) + w[1] * K - (xy * w[0] + yy * w[1] + yz * w[2]);
+  Tc[2] = (m1[0] * up[1] - m1[1] * up[0]) + w[2] * K - (xz * w[0] + yz * w[1] + zz * w[2]);
+}
+
 // Offset of node (x, y, z) and the periodic / walled neighbour indices.
 struct Nbr {
   int xs[3], ys[3], zs[3];      // coordinates of x-1, x, x+1 etc. (wrapped)
@@ -397,11 +429,20 @@ __device__ void mea_compacted(C (*fl)[256], int (*meta)[2], int slot, int total,
   unsigned msk = 0, msk2 = 0, rem = 0;
   int x = 0, y = 0;
   const int z = nd.z;
+  bool inner = false;
   if (have) {
     const int t = meta[slot][0];
     x = nd.x - (int)(threadIdx.x % WAVE) + (t % WAVE);
     y = nd.y - nd.wave + t / WAVE;
-    o = meta[slot][1];
+    const int code = meta[slot][1];
+    o = owner_id(code);
+    inner = code >= 0 && (code & OWNER_INTERIOR);
+  }
+  if (inner) {
+    // every link neighbour is owned by o
+    q = o;
+    msk = 0x7fffeu;
+  } else if (have) {
     // owners of the 18 link neighbours (none beyond a wall).  Links whose
     // far node is owned: by the primary particle (the node's owner, else
     // the owner of its first owned neighbour), by a secondary particle, or
@@ -409,8 +450,11 @@ __device__ void mea_compacted(C (*fl)[256], int (*meta)[2], int slot, int total,
     const Nbr nb = neighbours(g, x, y, z);
     int on[Q];
 #pragma unroll
-    for (int j = 1; j < Q; ++j)
-      on[j] = nb.beyond(cz(j)) ? -1 : owner[nb.off(cx(j), cy(j), cz(j))];
+    for (int j = 1; j < Q; ++j) {
+      // the neighbour index is clamped at walls, so the load is always valid
+      const int v = owner[nb.off(cx(j), cy(j), cz(j))];
+      on[j] = nb.beyond(cz(j)) ? -1 : owner_id(v);
+    }
     q = o >= 0 ? o : -1;
 #pragma unroll
     for (int j = 1; j < Q; ++j)
@@ -434,20 +478,24 @@ __device__ void mea_compacted(C (*fl)[256], int (*meta)[2], int slot, int total,
   bool own = o >= 0;
   for (;;) {
     if (__ballot(q >= 0) == 0) break;
+    // wavefronts made only of interior entries take the unmasked sums
+    const bool all_inner = __ballot(q >= 0 && !(inner && own)) == 0;
     double Sv[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
     if (q >= 0) {
-      const double* Xq = P.X + 3 * q;
-      const double* Uq = P.U + 3 * q;
-      const double* Wq = P.W + 3 * q;
+      const double Xq[3] = {P.X[3 * q], P.X[3 * q + 1], P.X[3 * q + 2]};
+      const double Uq[3] = {P.U[3 * q], P.U[3 * q + 1], P.U[3 * q + 2]};
+      const double w[3] = {P.W[3 * q], P.W[3 * q + 1], P.W[3 * q + 2]};
       const double r[3] = {minimg((double)x - Xq[0], (double)g.nx, true),
                            minimg((double)y - Xq[1], (double)g.ny, true),
                            minimg((double)z - Xq[2], (double)g.nz, perz)};
-      const double w[3] = {Wq[0], Wq[1], Wq[2]};
       const double up[3] = {Uq[0] + (w[1] * r[2] - w[2] * r[1]),
                             Uq[1] + (w[2] * r[0] - w[0] * r[2]),
                             Uq[2] + (w[0] * r[1] - w[1] * r[0])};
       double Sc[3], Tcc[3];
-      link_group_sums<Store<S>::shifted>(hval, msk, own, up, w, Sc, Tcc);
+      if (all_inner)
+        interior_sums<Store<S>::shifted>(hval, up, w, Sc, Tcc);
+      else
+        link_group_sums<Store<S>::shifted>(hval, msk, own, up, w, Sc, Tcc);
       if (own && (wall_m || wall_p)) {
         // links that bounce back from a wall return to y as f_opp(j)(y) of
         // the next step: term (c_j + u_p(y)) f_opp(j)(y)
@@ -486,7 +534,7 @@ __device__ void mea_compacted(C (*fl)[256], int (*meta)[2], int slot, int total,
         xj = xj < 0 ? xj + g.nx : (xj >= g.nx ? xj - g.nx : xj);
         yj = yj < 0 ? yj + g.ny : (yj >= g.ny ? yj - g.ny : yj);
         zj = zj < 0 ? zj + g.nz : (zj >= g.nz ? zj - g.nz : zj);
-        return owner[xj + g.nx * (yj + g.ny * zj)];
+        return owner_id(owner[xj + g.nx * (yj + g.ny * zj)]);
       };
       q = link_owner(__ffs(rem) - 1);
       for (unsigned b = rem; b; b &= b - 1) {
@@ -511,7 +559,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   __shared__ double red[4][LCAP_MAX][6];
   __shared__ C fl[Q][256];
   __shared__ int meta[256][2];
-  __shared__ int wcount[4];
+  __shared__ int wcount[8];
   const BlockNode nd = block_node(g);
   const int x = nd.x, y = nd.y, z = nd.z;
   const bool valid = nd.valid;
@@ -522,20 +570,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const int self = nb.off(0, 0, 0);
 
   C f[Q];
-  int o = -1;
+  int o = -1, ocode = -1;
   if (valid) {
+    // one load per direction from a selected index (a branch per direction
+    // would make the compiler wait for memory between the loads), then the
+    // moving-wall term of the links that bounced back
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const int bw = nb.beyond(-cz(i));
-      if (bw) {
-        const double* uw = ph.wall_u[bw - 1];
-        const double cu = cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2];
-        f[i] = Store<S>::ld(src, opp(i) * n + self) + (C)(6.0 * wgt(i) * cu);
-      } else {
-        f[i] = Store<S>::ld(src, i * n + nb.off(-cx(i), -cy(i), -cz(i)));
+      const int src_i = nb.beyond(-cz(i)) ? opp(i) * n + self
+                                          : i * n + nb.off(-cx(i), -cy(i), -cz(i));
+      f[i] = Store<S>::ld(src, src_i);
+    }
+    ocode = owner[self];
+    o = owner_id(ocode);
+    if (nb.wall_m || nb.wall_p) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int bw = nb.beyond(-cz(i));
+        if (bw) {
+          const double* uw = ph.wall_u[bw - 1];
+          const double cu = cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2];
+          f[i] += (C)(6.0 * wgt(i) * cu);
+        }
       }
     }
-    o = owner[self];
   } else {
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[i] = Store<S>::shifted ? (C)0 : (C)wgt(i);
@@ -563,24 +621,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   C upy[3] = {(C)0, (C)0, (C)0};
   C B = (C)0;
   if (o >= 0) {
-    const double* Xo = P.X + 3 * o;
-    const C r0 = (C)minimg((double)x - Xo[0], (double)g.nx, true);
-    const C r1 = (C)minimg((double)y - Xo[1], (double)g.ny, true);
-    const C r2 = (C)minimg((double)z - Xo[2], (double)g.nz, perz);
+    // the owner's record, all loads issued before any use
+    const double X0 = P.X[3 * o], X1 = P.X[3 * o + 1], X2 = P.X[3 * o + 2];
+    const double U0 = P.U[3 * o], U1 = P.U[3 * o + 1], U2 = P.U[3 * o + 2];
+    const double W0 = P.W[3 * o], W1 = P.W[3 * o + 1], W2 = P.W[3 * o + 2];
+    const int shape = P.shape[o];
+    const double size = P.size[o];
+    double Ro[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Ro[k] = P.R[9 * o + k];
+    const C r0 = (C)minimg((double)x - X0, (double)g.nx, true);
+    const C r1 = (C)minimg((double)y - X1, (double)g.ny, true);
+    const C r2 = (C)minimg((double)z - X2, (double)g.nz, perz);
     C d;
     if constexpr (Store<S>::shifted) {
-      d = sdf32(P.shape[o], (float)P.size[o], P.R + 9 * o, r0, r1, r2);
+      d = sdf32(shape, (float)size, Ro, r0, r1, r2);
       B = weight32(d, (float)ph.eps);
     } else {
-      d = sdf(P.shape[o], P.size[o], P.R + 9 * o, r0, r1, r2);
+      d = sdf(shape, size, Ro, r0, r1, r2);
       B = weight(d, ph.eps);
     }
-    const double* Uo = P.U + 3 * o;
-    const double* Wo = P.W + 3 * o;
-    const C w0 = (C)Wo[0], w1 = (C)Wo[1], w2 = (C)Wo[2];
-    upy[0] = (C)Uo[0] + (w1 * r2 - w2 * r1);
-    upy[1] = (C)Uo[1] + (w2 * r0 - w0 * r2);
-    upy[2] = (C)Uo[2] + (w0 * r1 - w1 * r0);
+    const C w0 = (C)W0, w1 = (C)W1, w2 = (C)W2;
+    upy[0] = (C)U0 + (w1 * r2 - w2 * r1);
+    upy[1] = (C)U1 + (w2 * r0 - w0 * r2);
+    upy[2] = (C)U2 + (w0 * r1 - w1 * r0);
   }
   const C du0 = B * (upy[0] - u0) + (C)ph.a_ext[0];
   const C du1 = B * (upy[1] - u1) + (C)ph.a_ext[1];
@@ -619,21 +683,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   // or with a possibly owned link neighbour) into LDS, then let the four
   // wavefronts work through that list only.
   const int lane = threadIdx.x % WAVE;
-  const bool need = valid && o != -1;
-  const uint64_t nb_mask = __ballot(need);
-  if (lane == 0) wcount[nd.wave] = __popcll(nb_mask);
+  // Interior nodes (all link neighbours owned by the node's owner) go first,
+  // so that wavefronts of the list are mostly of one kind.
+  const bool need = valid && ocode != -1;
+  const bool inner = need && ocode >= 0 && (ocode & OWNER_INTERIOR);
+  const uint64_t in_mask = __ballot(inner);
+  const uint64_t bd_mask = __ballot(need && !inner);
+  if (lane == 0) {
+    wcount[nd.wave] = __popcll(in_mask);
+    wcount[4 + nd.wave] = __popcll(bd_mask);
+  }
   __syncthreads();
-  int base = 0, total = 0;
+  int base_in = 0, base_bd = 0, n_in = 0, total = 0;
   for (int w = 0; w < 4; ++w) {
-    if (w < nd.wave) base += wcount[w];
-    total += wcount[w];
+    if (w < nd.wave) {
+      base_in += wcount[w];
+      base_bd += wcount[4 + w];
+    }
+    n_in += wcount[w];
+    total += wcount[w] + wcount[4 + w];
   }
   if (need) {
-    const int slot = base + __popcll(nb_mask & ((1ull << lane) - 1ull));
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int slot = inner ? base_in + __popcll(in_mask & below)
+                           : n_in + base_bd + __popcll(bd_mask & below);
 #pragma unroll
     for (int j = 1; j < Q; ++j) fl[j][slot] = f[j];
     meta[slot][0] = (int)threadIdx.x;
-    meta[slot][1] = o;
+    meta[slot][1] = ocode;
   }
   int cnt = tl.lcount[tile];
   cnt = __builtin_amdgcn_readfirstlane(cnt < g.tile_cap ? cnt : g.tile_cap);
@@ -664,7 +741,7 @@ __global__ __launch_bounds__(256) void k_mea_only(const S* __restrict__ fs,
   const size_t n = (size_t)g.ncell;
   const bool perz = g.periodic_z != 0;
   const size_t id = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);
-  const int o = nd.valid ? owner[id] : -1;
+  const int o = nd.valid ? owner_id(owner[id]) : -1;
   Acc acc;
   acc.init();
   if (o >= 0) {

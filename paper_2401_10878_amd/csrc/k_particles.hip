@@ -86,17 +86,25 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
   for (int k = 0; k < 4; ++k) q[k] = P.q[4 * ip + k];
 
   if (move) {
-    // 1. F_p = sum of the per-tile partials (eqs. (17)-(18))
-    const int ne = tl.nent[ip];
-    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int k = lane; k < ne; k += WAVE) {
-      const double* pp = tl.part + ((size_t)ip * g.maxent + k) * 6;
-      for (int m = 0; m < 6; ++m) v[m] += pp[m];
-    }
+    // 1. F_p = sum of the per-tile partials (eqs. (17)-(18)); later
+    // sub-steps of the step keep the force of the first
     double F[3], T[3];
-    for (int m = 0; m < 3; ++m) {
-      F[m] = wave_sum(v[m]) + tl.ovf[6 * ip + m];
-      T[m] = wave_sum(v[3 + m]) + tl.ovf[6 * ip + 3 + m];
+    if (move == 1) {
+      const int ne = tl.nent[ip];
+      double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int k = lane; k < ne; k += WAVE) {
+        const double* pp = tl.part + ((size_t)ip * g.maxent + k) * 6;
+        for (int m = 0; m < 6; ++m) v[m] += pp[m];
+      }
+      for (int m = 0; m < 3; ++m) {
+        F[m] = wave_sum(v[m]) + tl.ovf[6 * ip + m];
+        T[m] = wave_sum(v[3 + m]) + tl.ovf[6 * ip + 3 + m];
+      }
+    } else {
+      for (int m = 0; m < 3; ++m) {
+        F[m] = Fh[3 * ip + m];
+        T[m] = Th[3 * ip + m];
+      }
     }
     // contact force and torque: the particle's slots summed in the order
     // of the partner id (lane k holds slot k; partners are distinct)
@@ -117,26 +125,27 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
         }
       }
     }
-    // 2. Newton-Euler, symplectic Euler with Delta t = 1 (eqs. (2)-(3));
+    // 2. Newton-Euler, symplectic Euler over the sub-step dt (eqs. (2)-(3));
     // gravity minus buoyancy (rho_p - rho_f) V g with rho_f = 1 (Sec. 5.1).
     const double V = P.vol[ip], m = P.mass[ip], I = P.inert[ip];
     const double s = P.dens[ip];
+    const double dt = ph.dt_sub;
     for (int k = 0; k < 3; ++k) {
       const double Fg = (s - 1.0) * V * ph.gravity[k];
       const double Ft = F[k] + Fcp[k] + Fg;
       const double Tt = T[k] + Tcp[k];
-      U[k] += Ft / m;
-      X[k] += U[k];
+      U[k] += Ft / m * dt;
+      X[k] += U[k] * dt;
       if (per[k]) {
         if (X[k] >= L[k]) X[k] -= L[k];
         else if (X[k] < 0.0) X[k] += L[k];
       }
-      W[k] += Tt / I;
+      W[k] += Tt / I * dt;
     }
-    // orientation: exact rotation through |w| about w, q <- dq (x) q
-    const double th = sqrt(W[0] * W[0] + W[1] * W[1] + W[2] * W[2]);
+    // orientation: exact rotation through |w| dt about w, q <- dq (x) q
+    const double th = sqrt(W[0] * W[0] + W[1] * W[1] + W[2] * W[2]) * dt;
     if (th > 0.0) {
-      const double c = cos(0.5 * th), sn = sin(0.5 * th) / th;
+      const double c = cos(0.5 * th), sn = sin(0.5 * th) / th * dt;
       const double d0 = c, d1 = sn * W[0], d2 = sn * W[1], d3 = sn * W[2];
       double r[4];
       r[0] = d0 * q[0] - (d1 * q[1] + d2 * q[2] + d3 * q[3]);
@@ -153,7 +162,8 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
         Fc[3 * ip + k] = Fcp[k];
         Tc[3 * ip + k] = Tcp[k];
       }
-      for (int k = 0; k < 6; ++k) tl.ovf[6 * ip + k] = 0.0;
+      if (move == 1)
+        for (int k = 0; k < 6; ++k) tl.ovf[6 * ip + k] = 0.0;
     }
   }
   quat_to_rot(q, R);

@@ -43,7 +43,7 @@ class Params(C.Structure):
                 ("restitution", C.c_double), ("mu_s", C.c_double),
                 ("mu_k", C.c_double), ("u_k", C.c_double),
                 ("max_pairs", C.c_int), ("tile_capacity", C.c_int),
-                ("precision", C.c_int)]
+                ("precision", C.c_int), ("n_sub", C.c_int)]
 
 
 class Contact(C.Structure):
@@ -126,7 +126,7 @@ def make_params(p) -> Params:
     o = Params()
     for f in ("nx", "ny", "nz", "periodic_z", "tau", "balance", "eps_b",
               "enlarge", "n_c", "young", "poisson", "restitution", "mu_s",
-              "mu_k", "u_k", "max_pairs", "tile_capacity", "precision"):
+              "mu_k", "u_k", "max_pairs", "tile_capacity", "precision", "n_sub"):
         setattr(o, f, getattr(p, f))
     for w in range(2):
         for k in range(3):

@@ -69,6 +69,7 @@ class Params:
     max_pairs: int = 4096
     tile_capacity: int = 48
     precision: int = 0     # 0 FP64, 1 FP32, 2 FP16 storage of deviations
+    n_sub: int = 1         # contact sub-steps per time step
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)

@@ -195,6 +195,8 @@ def test_invalid_configuration_rejected(W, H):
     wl = W.c1_two_spheres()
     with pytest.raises(H.HlbmError):
         H.Simulation(wl.params.replace(tau=0.5), wl.scene)
+    with pytest.raises(H.HlbmError):
+        H.Simulation(wl.params.replace(n_sub=0), wl.scene)
     # a periodic box shorter than twice the particle reach
     with pytest.raises(H.HlbmError):
         H.Simulation(wl.params.replace(nx=8), wl.scene)
@@ -284,3 +286,52 @@ def test_state_checkpoint_resume(W, H, prec):
     with pytest.raises(H.HlbmError) as e:
         other.set_state(blob)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("n_sub", [2, 3])
+def test_substep_parity(O, W, H, n_sub):
+    """Contact sub-steps (treatment, motion over 1/n_sub, detection, with
+    the hydrodynamic force held) against the oracle, FP64, with walls."""
+    seed, dims, n, pz = CASES[1]
+    sc = W.random_small_scene(seed, dims, n, periodic_z=pz,
+                              size_range=(1.6, 3.0), gap=-0.8, speed=0.01,
+                              spin=0.004)
+    p = W.Params(nx=dims[0], ny=dims[1], nz=dims[2], periodic_z=pz, tau=0.7,
+                 gravity=(0.0, 0.0, -2e-4), young=0.4, u_k=3e-4,
+                 max_pairs=256, tile_capacity=16, n_sub=n_sub)
+    f0 = W.perturbed_populations(seed, dims, O.feq(1.0, [0.004, -0.002, 0.001]),
+                                 amp=0.01)
+    o, g = _pair(O, H, p, sc, f0)
+    Fref = np.abs(np.array(p.gravity)).max() * 0.5 * (4 / 3 * math.pi * 1.6 ** 3)
+    for _ in range(3):
+        o.step(2)
+        g.step(2)
+        eo, eg = o.forces(), g.forces()
+        err = max(force_err(eg["Fh"], eo["Fh"], Fref), force_err(eg["Fc"], eo["Fc"], Fref))
+        _say(f"  n_sub {n_sub} step {o.step_count}: force {err:.2e}")
+        assert err <= 1e-11
+        assert np.array_equal(g.fields()["owner"], o.fields()["owner"])
+        assert [(c["a"], c["b"], c["count"]) for c in o.contacts()] == \
+               [(c["a"], c["b"], c["count"]) for c in g.contacts()]
+        po, pg = o.particles(), g.particles()
+        assert np.abs(pg["X"] - po["X"]).max() <= 1e-12 * max(dims)
+    assert rel_field(g.populations(), o.populations()) <= 1e-12
+
+
+def test_substep_graph_matches_stream(W, H):
+    sc = W.random_small_scene(22, (24, 20, 16), 6, size_range=(1.6, 2.8),
+                              gap=-0.6, speed=0.01)
+    p = W.Params(nx=24, ny=20, nz=16, tau=0.7, young=0.4, u_k=3e-4,
+                 max_pairs=256, tile_capacity=16, precision=1, n_sub=2)
+    a = H.Simulation(p, sc)
+    b = H.Simulation(p, sc, graph=True)
+    a.init_equilibrium(u=(0.003, 0, 0))
+    b.init_equilibrium(u=(0.003, 0, 0))
+    for _ in range(3):
+        a.step(3)
+        b.step(3)
+        assert np.array_equal(b.populations(), a.populations())
+        pa, pb = a.particles(), b.particles()
+        assert np.array_equal(pa["X"], pb["X"])
+        assert [(c["a"], c["b"], c["count"]) for c in a.contacts()] == \
+               [(c["a"], c["b"], c["count"]) for c in b.contacts()]

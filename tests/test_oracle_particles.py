@@ -105,3 +105,82 @@ def test_archimedes_unit_conversion(W):
         assert abs(lu["g"] * d ** 3 * 0.5 / lu["nu"] ** 2 - ar) < 1e-9 * ar
     assert round(0.3 * 256 ** 3 / 14 ** 3) == 1834
     assert round(0.1 * 128 ** 3 / 12 ** 3) == 121
+
+
+def test_substeps_constant_force_closed_form(O, W):
+    """n sub-steps of length 1/n under a constant force a (gravity minus
+    buoyancy, hydrodynamic force zero for a particle 1e12 times denser than
+    the fluid): after k steps U = U0 + k a and, per step, X advances by
+    U_start + a (n + 1) / (2 n) (the sum of the sub-step velocities / n)."""
+    g = 2e-4
+    s_ratio = 1e12
+    a = -g * (1 - 1 / s_ratio)
+    U0 = np.array([0.01, 0.0, 0.002])
+    om = np.array([0.0, 0.03, 0.0])
+    for n in (1, 3, 8):
+        p = W.Params(nx=16, ny=16, nz=32, tau=0.7, gravity=(0.0, 0.0, -g), n_sub=n)
+        sim = O.OracleSim(p, _heavy(W, 0, U0, om, s=s_ratio, X=(8.0, 8.0, 20.0)))
+        sim.init_equilibrium()
+        k = 6
+        sim.step(k)
+        st = sim.particles()
+        Uz = U0[2] + k * a
+        Zexp = 20.0 + sum(U0[2] + j * a + a * (n + 1) / (2 * n) for j in range(k))
+        assert abs(st["U"][0, 2] - Uz) < 1e-13
+        assert abs(st["X"][0, 2] - Zexp) < 1e-12, (n, st["X"][0, 2], Zexp)
+        assert abs(st["X"][0, 0] - (8.0 + k * U0[0])) < 1e-12
+        # the rotation over a step is the same whatever the sub-division
+        th = k * np.linalg.norm(om)
+        qe = np.array([math.cos(th / 2), 0.0, math.sin(th / 2), 0.0])
+        q = st["q"][0]
+        assert min(np.abs(q - qe).max(), np.abs(q + qe).max()) < 1e-12
+
+
+def _head_on(W, n_sub, young, speed=0.02):
+    sc = W.Scene(np.array([0, 0], np.int32), np.array([3.0, 3.0]),
+                 np.array([2000.0, 2000.0]),
+                 np.array([[9.0, 10.0, 10.0], [15.6, 10.0, 10.0]]),
+                 np.array([[1.0, 0, 0, 0], [1.0, 0, 0, 0]]),
+                 np.array([[speed, 0, 0], [-speed, 0, 0]]), np.zeros((2, 3)))
+    p = W.Params(nx=26, ny=20, nz=20, tau=0.8, young=young, u_k=3e-4,
+                 max_pairs=16, tile_capacity=8, n_sub=n_sub)
+    return p, sc
+
+
+def test_substeps_head_on_momentum_balance(O, W):
+    """Contact forces act equal and opposite in every sub-step, and the
+    hydrodynamic impulse of a step is F_h whatever the sub-division: the
+    particles' momentum changes by the summed hydrodynamic impulse only."""
+    for n in (1, 4):
+        p, sc = _head_on(W, n, young=50.0)
+        sim = O.OracleSim(p, sc)
+        sim.init_equilibrium()
+        m = 2000.0 * 4.0 / 3.0 * math.pi * 27.0
+        P0 = m * (sc.U[0] + sc.U[1])
+        imp = np.zeros(3)
+        touched = False
+        for _ in range(60):
+            sim.step(1)
+            f = sim.forces()
+            imp += f["Fh"][0] + f["Fh"][1]
+            touched = touched or np.abs(f["Fc"]).max() > 0
+        st = sim.particles()
+        P1 = m * (st["U"][0] + st["U"][1])
+        assert touched
+        np.testing.assert_allclose(P1 - P0, imp, rtol=0, atol=1e-12 * m * 0.02)
+
+
+def test_substeps_converge_on_a_stiff_collision(O, W):
+    """With a stiff contact the collision lasts only a few steps; the
+    velocity after the rebound converges as the sub-steps refine it (the
+    difference to a 32-sub-step run shrinks from 2 to 8 sub-steps)."""
+    def rebound(n):
+        p, sc = _head_on(W, n, young=2e4)
+        sim = O.OracleSim(p, sc)
+        sim.init_equilibrium()
+        sim.step(40)
+        return sim.particles()["U"][0, 0]
+    ref = rebound(32)
+    e2, e8 = abs(rebound(2) - ref), abs(rebound(8) - ref)
+    assert ref < 0.0                 # the sphere bounced back
+    assert e8 < 0.5 * e2, (e2, e8)
