@@ -64,7 +64,9 @@ typedef enum {
     HLBM_FP16S = 2          /* f - w stored as IEEE binary16, FP32 collision */
 } hlbm_precision;
 
-typedef enum { HLBM_SPHERE = 0, HLBM_CUBE = 1 } hlbm_shape;
+/* Convex bodies with exact signed distances; size is the radius (sphere),
+   the edge (cube) or the centre-to-vertex distance (regular octahedron). */
+typedef enum { HLBM_SPHERE = 0, HLBM_CUBE = 1, HLBM_OCTAHEDRON = 2 } hlbm_shape;
 
 typedef struct {
     int nx, ny, nz;             /* lattice nodes per axis */
@@ -122,7 +124,8 @@ hlbm_status hlbm_create(const hlbm_params *params, void *stream,
 hlbm_status hlbm_bind_populations(hlbm_ctx *ctx, void *dev_a, void *dev_b,
                                   size_t bytes);
 
-/* Upload n particles (host arrays).  size = radius (sphere) or edge (cube);
+/* Upload n particles (host arrays).  shape: hlbm_shape; size = radius
+   (sphere), edge (cube) or centre-to-vertex distance (octahedron);
    density = particle/fluid density ratio.  Positions on periodic axes are
    wrapped into [0, n).  Periodic axes must exceed twice the particle reach
    (circumradius + detection margin). */

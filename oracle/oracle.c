@@ -95,16 +95,76 @@ void orc_rotation(const double q[4], double R[9])
     R[8] = 1.0 - 2.0 * (x * x + y * y);
 }
 
+/* Regular octahedron |x| + |y| + |z| <= a (size = a, the centre-to-vertex
+   distance), body frame.  Folded into the positive octant (q = |p|), the
+   surface there is the triangle A = (a,0,0), B = (0,a,0), C = (0,0,a) on
+   the plane x + y + z = a.  Inside, the nearest surface point lies on that
+   face plane; outside, it is the closest point of the triangle: on the face
+   when the projection onto the plane lands inside it (all coordinates of
+   the projection >= 0), else on one of its three edges.  gq receives the
+   gradient with respect to q (unit length). */
+static double octa_sdf_q(double a, const double q[3], double gq[3])
+{
+    const double inv3 = 0.57735026918962584;      /* 1 / sqrt(3) */
+    double s = (q[0] + q[1]) + q[2];
+    double pd = (s - a) * inv3;                    /* signed plane distance */
+    double t[3];
+    for (int k = 0; k < 3; ++k) t[k] = q[k] - (s - a) / 3.0;
+    if (s <= a || (t[0] >= 0.0 && t[1] >= 0.0 && t[2] >= 0.0)) {
+        for (int k = 0; k < 3; ++k) gq[k] = inv3;
+        return pd;
+    }
+    /* closest point on the edges A-B, B-C, C-A */
+    double best = 1e300, bc[3] = {0.0, 0.0, 0.0};
+    for (int e = 0; e < 3; ++e) {
+        int i = e, j = (e + 1) % 3;               /* vertex a e_i to a e_j */
+        /* segment P0 = a e_i, P1 = a e_j, direction (P1 - P0) */
+        double u = ((q[j] - q[i]) + a) / (2.0 * a);
+        if (u < 0.0) u = 0.0;
+        if (u > 1.0) u = 1.0;
+        double cp[3] = {0.0, 0.0, 0.0};
+        cp[i] = a * (1.0 - u);
+        cp[j] = a * u;
+        double dx = q[0] - cp[0], dy = q[1] - cp[1], dz = q[2] - cp[2];
+        double d2 = (dx * dx + dy * dy) + dz * dz;
+        if (d2 < best) {
+            best = d2;
+            bc[0] = cp[0]; bc[1] = cp[1]; bc[2] = cp[2];
+        }
+    }
+    double d = sqrt(best);
+    for (int k = 0; k < 3; ++k) gq[k] = d > 0.0 ? (q[k] - bc[k]) / d : inv3;
+    return d;
+}
+
 /* Exact Euclidean signed distance (negative inside) of a sphere (size =
-   radius) or cube (size = edge) at world offset r from its centre.  The
-   paper maps B from a level-set function (Sec. 3.2) and evaluates signed
-   distances at nodes (Sec. 3.3.1); these are the exact level sets of the two
-   shapes used in its experiments.  grad (may be NULL) is the world-frame
-   gradient; inside a cube it is the normal of the nearest face (ties to the
-   lowest axis), and at the exact centre of a sphere it is zero. */
+   radius), cube (size = edge) or regular octahedron (size = centre-to-vertex
+   distance) at world offset r from its centre.  The paper maps B from a
+   level-set function (Sec. 3.2) and evaluates signed distances at nodes
+   (Sec. 3.3.1) for arbitrary convex bodies; sphere and cube are the shapes
+   of its experiments, the octahedron a further convex body.  grad (may be
+   NULL) is the world-frame gradient; inside a cube it is the normal of the
+   nearest face (ties to the lowest axis), and at the exact centre of a
+   sphere it is zero. */
 double orc_sdf(int shape, double size, const double R[9], const double r[3],
                double grad[3])
 {
+    if (shape == 2) {
+        double p[3], q[3], gq[3];
+        for (int k = 0; k < 3; ++k) {
+            p[k] = R[0 + k] * r[0] + R[3 + k] * r[1] + R[6 + k] * r[2];
+            q[k] = fabs(p[k]);
+        }
+        double d = octa_sdf_q(size, q, gq);
+        if (grad) {
+            double gb[3];
+            for (int k = 0; k < 3; ++k) gb[k] = (p[k] < 0.0 ? -1.0 : 1.0) * gq[k];
+            for (int k = 0; k < 3; ++k)
+                grad[k] = R[3 * k + 0] * gb[0] + R[3 * k + 1] * gb[1] +
+                          R[3 * k + 2] * gb[2];
+        }
+        return d;
+    }
     if (shape == 0) {
         double n2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
         double n = sqrt(n2);
@@ -177,14 +237,18 @@ static void cross(const double a[3], const double b[3], double out[3])
 
 static double volume_of(const orc_particle *p)
 {
-    if (p->shape == 0) return 4.0 / 3.0 * M_PI * p->size * p->size * p->size;
-    return p->size * p->size * p->size;
+    double a = p->size;
+    if (p->shape == 0) return 4.0 / 3.0 * M_PI * a * a * a;
+    if (p->shape == 2) return 4.0 / 3.0 * a * a * a;   /* two pyramids */
+    return a * a * a;
 }
 
-/* isotropic moment of inertia of a homogeneous sphere or cube */
+/* isotropic moment of inertia of a homogeneous sphere, cube or regular
+   octahedron (<x^2> = a^2 / 10 over |x|+|y|+|z| <= a, so I = m a^2 / 5) */
 static double inertia_of(const orc_particle *p, double m)
 {
     if (p->shape == 0) return 0.4 * m * p->size * p->size;
+    if (p->shape == 2) return 0.2 * m * p->size * p->size;
     return m * p->size * p->size / 6.0;
 }
 

@@ -43,7 +43,7 @@ typedef struct {
 } orc_params;
 
 typedef struct {
-    int shape;               /* 0 sphere, 1 cube */
+    int shape;               /* 0 sphere, 1 cube, 2 regular octahedron */
     double size;             /* sphere radius or cube edge */
     double dens;             /* particle / fluid density ratio */
     double X[3], q[4], U[3], w[3];

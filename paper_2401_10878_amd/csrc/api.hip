@@ -379,14 +379,15 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
   std::vector<double> sz(n), ds(n), vol(n), mass(n), inert(n), Xh(3 * n), qh(4 * n),
       Uh(3 * n), Wh(3 * n);
   for (int i = 0; i < n; ++i) {
-    if (shape[i] != 0 && shape[i] != 1)
-      return fail(c, HLBM_E_ARG, "particle %d: shape must be 0 (sphere) or 1 (cube)", i);
+    if (shape[i] < 0 || shape[i] > 2)
+      return fail(c, HLBM_E_ARG,
+                  "particle %d: shape must be 0 (sphere), 1 (cube) or 2 (octahedron)", i);
     if (!(size[i] > 0.0) || !(density[i] > 0.0) || !isfinite(size[i]) || !isfinite(density[i]))
       return fail(c, HLBM_E_ARG, "particle %d: size and density must be positive", i);
     sh[i] = shape[i];
     sz[i] = size[i];
     ds[i] = density[i];
-    const double circ = shape[i] == 0 ? size[i] : 0.5 * size[i] * sqrt(3.0);
+    const double circ = shape[i] == 1 ? 0.5 * size[i] * sqrt(3.0) : size[i];
     for (int k = 0; k < 3; ++k) {
       if (per[k] && !(L[k] > 2.0 * (circ + margin)))
         return fail(c, HLBM_E_ARG,
@@ -411,11 +412,14 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
     for (int k = 0; k < 4; ++k) qh[4 * i + k] = q[4 * i + k];
     if (fabs(nq - 1.0) > 1e-12)
       for (int k = 0; k < 4; ++k) qh[4 * i + k] = q[4 * i + k] / sqrt(nq);
-    vol[i] = shape[i] == 0 ? 4.0 / 3.0 * PI * size[i] * size[i] * size[i]
-                           : size[i] * size[i] * size[i];
+    // volume and (isotropic) moment of inertia: sphere 4 pi a^3 / 3,
+    // 2 m a^2 / 5; cube a^3, m a^2 / 6; octahedron 4 a^3 / 3, m a^2 / 5
+    const double a = size[i];
+    vol[i] = shape[i] == 0 ? 4.0 / 3.0 * PI * a * a * a
+                           : (shape[i] == 2 ? 4.0 / 3.0 * a * a * a : a * a * a);
     mass[i] = density[i] * vol[i];
-    inert[i] = shape[i] == 0 ? 0.4 * mass[i] * size[i] * size[i]
-                             : mass[i] * size[i] * size[i] / 6.0;
+    inert[i] = shape[i] == 0 ? 0.4 * mass[i] * a * a
+                             : (shape[i] == 2 ? 0.2 * mass[i] * a * a : mass[i] * a * a / 6.0);
   }
   drop_graphs(c);
   free_particles(c);
@@ -446,7 +450,7 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
   {
     double emax = 0.0;
     for (int i = 0; i < n; ++i)
-      emax = fmax(emax, sh[i] == 0 ? sz[i] : 0.5 * sz[i] * sqrt(3.0));
+      emax = fmax(emax, sh[i] == 1 ? 0.5 * sz[i] * sqrt(3.0) : sz[i]);
     const double span = 2.0 * (emax + margin) + 3.0;
     const int ts[3] = {LX, LY, LZ}, nt[3] = {c.g.ltx, c.g.lty, c.g.ltz};
     long long me = 1;

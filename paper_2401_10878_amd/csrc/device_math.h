@@ -106,11 +106,72 @@ __device__ inline int image_shift(double v, double L, bool periodic) {
   return 0;
 }
 
+// Regular octahedron |x| + |y| + |z| <= a, folded into the positive octant
+// (q = |p|): inside, the distance to the face plane x + y + z = a; outside,
+// the distance to the face triangle a e_0, a e_1, a e_2 (its interior when
+// the projection onto the plane has no negative coordinate, else the
+// nearest of its three edges, first edge kept on ties).  T is double or
+// float; gq (may be null) receives the unit gradient with respect to q.
+template <typename T>
+__device__ inline T octa_edge(T a, T qi, T qj, T& ci, T& cj) {
+  T u = ((qj - qi) + a) / ((T)2 * a);
+  u = u < (T)0 ? (T)0 : (u > (T)1 ? (T)1 : u);
+  ci = a * ((T)1 - u);
+  cj = a * u;
+  return u;
+}
+template <typename T>
+__device__ inline T octa_q(T a, T q0, T q1, T q2, T& g0, T& g1, T& g2) {
+  const T inv3 = (T)0.57735026918962584;
+  const T s = (q0 + q1) + q2;
+  const T pd = (s - a) * inv3;
+  const T t0 = q0 - (s - a) / (T)3, t1 = q1 - (s - a) / (T)3, t2 = q2 - (s - a) / (T)3;
+  if (s <= a || (t0 >= (T)0 && t1 >= (T)0 && t2 >= (T)0)) {
+    g0 = g1 = g2 = inv3;
+    return pd;
+  }
+  T c0, c1, c2, best, b0, b1, b2;
+  {  // edge a e_0 - a e_1
+    octa_edge(a, q0, q1, c0, c1);
+    const T dx = q0 - c0, dy = q1 - c1, dz = q2;
+    best = (dx * dx + dy * dy) + dz * dz;
+    b0 = c0; b1 = c1; b2 = (T)0;
+  }
+  {  // edge a e_1 - a e_2
+    octa_edge(a, q1, q2, c1, c2);
+    const T dx = q0, dy = q1 - c1, dz = q2 - c2;
+    const T d2 = (dx * dx + dy * dy) + dz * dz;
+    if (d2 < best) { best = d2; b0 = (T)0; b1 = c1; b2 = c2; }
+  }
+  {  // edge a e_2 - a e_0
+    octa_edge(a, q2, q0, c2, c0);
+    const T dx = q0 - c0, dy = q1, dz = q2 - c2;
+    const T d2 = (dx * dx + dy * dy) + dz * dz;
+    if (d2 < best) { best = d2; b0 = c0; b1 = (T)0; b2 = c2; }
+  }
+  const T d = sqrt(best);
+  g0 = d > (T)0 ? (q0 - b0) / d : inv3;
+  g1 = d > (T)0 ? (q1 - b1) / d : inv3;
+  g2 = d > (T)0 ? (q2 - b2) / d : inv3;
+  return d;
+}
+template <typename T>
+__device__ inline T octa_q(T a, T q0, T q1, T q2) {
+  T g0, g1, g2;
+  return octa_q<T>(a, q0, q1, q2, g0, g1, g2);
+}
+
 // Exact signed distance (negative inside) at world offset r from the centre.
 // sphere: |r| - radius.  cube (edge a): body offset p = R^T r,
 // q_k = |p_k| - a/2, d = |max(q, 0)| + min(max_k q_k, 0).
 __device__ inline double sdf(int shape, double size, const double* R,
                              double r0, double r1, double r2) {
+  if (shape == 2) {
+    const double p0 = R[0] * r0 + R[3] * r1 + R[6] * r2;
+    const double p1 = R[1] * r0 + R[4] * r1 + R[7] * r2;
+    const double p2 = R[2] * r0 + R[5] * r1 + R[8] * r2;
+    return octa_q<double>(size, fabs(p0), fabs(p1), fabs(p2));
+  }
   if (shape == 0) {
     const double n2 = r0 * r0 + r1 * r1 + r2 * r2;
     return sqrt(n2) - size;
@@ -137,6 +198,7 @@ __device__ inline float sdf32(int shape, float size, const double* R, float r0,
   const float p0 = (float)R[0] * r0 + (float)R[3] * r1 + (float)R[6] * r2;
   const float p1 = (float)R[1] * r0 + (float)R[4] * r1 + (float)R[7] * r2;
   const float p2 = (float)R[2] * r0 + (float)R[5] * r1 + (float)R[8] * r2;
+  if (shape == 2) return octa_q<float>(size, fabsf(p0), fabsf(p1), fabsf(p2));
   const float q0 = fabsf(p0) - h, q1 = fabsf(p1) - h, q2 = fabsf(p2) - h;
   const float m0 = fmaxf(q0, 0.0f), m1 = fmaxf(q1, 0.0f), m2 = fmaxf(q2, 0.0f);
   return sqrtf(m0 * m0 + m1 * m1 + m2 * m2) + fminf(fmaxf(fmaxf(q0, q1), q2), 0.0f);
@@ -150,6 +212,7 @@ __device__ inline float sdf32_r(int shape, float size, const float* R, float r0,
   const float p0 = R[0] * r0 + R[3] * r1 + R[6] * r2;
   const float p1 = R[1] * r0 + R[4] * r1 + R[7] * r2;
   const float p2 = R[2] * r0 + R[5] * r1 + R[8] * r2;
+  if (shape == 2) return octa_q<float>(size, fabsf(p0), fabsf(p1), fabsf(p2));
   const float q0 = fabsf(p0) - h, q1 = fabsf(p1) - h, q2 = fabsf(p2) - h;
   const float m0 = fmaxf(q0, 0.0f), m1 = fmaxf(q1, 0.0f), m2 = fmaxf(q2, 0.0f);
   return sqrtf(m0 * m0 + m1 * m1 + m2 * m2) + fminf(fmaxf(fmaxf(q0, q1), q2), 0.0f);
@@ -160,14 +223,27 @@ __device__ inline float sdf32_r(int shape, float size, const float* R, float r0,
 // at a sphere's centre it is zero.
 __device__ inline double sdf_grad(int shape, double size, const double* R,
                                   const double* r, double* g) {
+  if (shape == 2) {
+    const double p0 = R[0] * r[0] + R[3] * r[1] + R[6] * r[2];
+    const double p1 = R[1] * r[0] + R[4] * r[1] + R[7] * r[2];
+    const double p2 = R[2] * r[0] + R[5] * r[1] + R[8] * r[2];
+    double q0, q1, q2;
+    const double d = octa_q<double>(size, fabs(p0), fabs(p1), fabs(p2), q0, q1, q2);
+    const double b0 = p0 < 0.0 ? -q0 : q0, b1 = p1 < 0.0 ? -q1 : q1, b2 = p2 < 0.0 ? -q2 : q2;
+    #pragma unroll
+    for (int k = 0; k < 3; ++k) g[k] = R[3 * k + 0] * b0 + R[3 * k + 1] * b1 + R[3 * k + 2] * b2;
+    return d;
+  }
   if (shape == 0) {
     const double n2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
     const double n = sqrt(n2);
+    #pragma unroll
     for (int k = 0; k < 3; ++k) g[k] = n > 0.0 ? r[k] / n : 0.0;
     return n - size;
   }
   const double h = 0.5 * size;
   double p[3], qd[3], m[3];
+  #pragma unroll
   for (int k = 0; k < 3; ++k) {
     p[k] = R[0 + k] * r[0] + R[3 + k] * r[1] + R[6 + k] * r[2];
     qd[k] = fabs(p[k]) - h;
@@ -177,13 +253,20 @@ __device__ inline double sdf_grad(int shape, double size, const double* R,
   const double inside = fmin(fmax(fmax(qd[0], qd[1]), qd[2]), 0.0);
   double gb[3] = {0.0, 0.0, 0.0};
   if (outside > 0.0) {
+    #pragma unroll
     for (int k = 0; k < 3; ++k) gb[k] = (p[k] < 0.0 ? -1.0 : 1.0) * m[k] / outside;
   } else {
+    // nearest face: largest q_k, ties to the lowest axis (selects, no
+    // run-time array index)
     int km = 0;
-    if (qd[1] > qd[km]) km = 1;
-    if (qd[2] > qd[km]) km = 2;
-    gb[km] = p[km] < 0.0 ? -1.0 : 1.0;
+    double qm = qd[0];
+    if (qd[1] > qm) { km = 1; qm = qd[1]; }
+    if (qd[2] > qm) km = 2;
+    gb[0] = km == 0 ? (p[0] < 0.0 ? -1.0 : 1.0) : 0.0;
+    gb[1] = km == 1 ? (p[1] < 0.0 ? -1.0 : 1.0) : 0.0;
+    gb[2] = km == 2 ? (p[2] < 0.0 ? -1.0 : 1.0) : 0.0;
   }
+  #pragma unroll
   for (int k = 0; k < 3; ++k)
     g[k] = R[3 * k + 0] * gb[0] + R[3 * k + 1] * gb[1] + R[3 * k + 2] * gb[2];
   return outside + inside;

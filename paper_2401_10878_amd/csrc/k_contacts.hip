@@ -181,10 +181,12 @@ __global__ __launch_bounds__(256) void k_treat(PairTable t, Particles P, Geom g,
 
   // ---- box correction, one pass -----------------------------------------
   bool ok = true;
-  for (int face = 0; face < 6 && ok; ++face) {
+  // fully unrolled, so that the face's axis k (and u, v) index registers
+#pragma unroll
+  for (int face = 0; face < 6; ++face) {
     for (int k = 0; k < 3; ++k)
       if (!(hi[k] > lo[k])) ok = false;
-    if (!ok) break;
+    if (!ok) continue;
     const int k = face / 2, plus = face % 2;
     const int u = k == 0 ? 1 : 0, v = k == 2 ? 1 : 2;
     const double hu = (hi[u] - lo[u]) / (double)nc;

@@ -29,6 +29,7 @@ import numpy as np
 
 SPHERE = 0
 CUBE = 1
+OCTAHEDRON = 2         # size = centre-to-vertex distance
 
 # Physical constants of the hindered-settling set-up (Sec. 5.1, Sec. 2.3).
 D_S_PHYS = 1.5e-3          # m
@@ -408,22 +409,26 @@ def c5_adjoint_cubes(seed: int = 5) -> Workload:
 
 def random_small_scene(seed: int, dims, n_particles: int, periodic_z=1,
                        size_range=(2.0, 4.5), gap=-0.3, speed=0.01,
-                       spin=0.004) -> Scene:
-    """Mixed spheres/cubes in a small box; neighbours may nearly touch.
+                       spin=0.004, shapes=(SPHERE, CUBE)) -> Scene:
+    """Mixed convex bodies (spheres, cubes and, if asked, octahedra) in a
+    small box; neighbours may nearly touch.
 
     `gap` is the allowed surface gap between bounding spheres (negative
-    values let bounding spheres interpenetrate, so that cube corners and
+    values let bounding spheres interpenetrate, so that corners and
     enlarged surfaces come into contact and the contact path is exercised).
     """
     rng = np.random.default_rng(seed)
     dims = np.asarray(dims, float)
     periodic = np.array([True, True, bool(periodic_z)])
-    shape = rng.integers(0, 2, n_particles).astype(np.int32)
+    shape = np.asarray(shapes, np.int32)[rng.integers(0, len(shapes), n_particles)]
     size = np.empty(n_particles)
     rb = np.empty(n_particles)
     for i in range(n_particles):
         if shape[i] == SPHERE:
             size[i] = rng.uniform(*size_range)
+            rb[i] = size[i]
+        elif shape[i] == OCTAHEDRON:
+            size[i] = 1.3 * rng.uniform(*size_range)
             rb[i] = size[i]
         else:
             size[i] = 2.0 * rng.uniform(*size_range) / math.sqrt(3.0) * 1.4

@@ -335,3 +335,38 @@ def test_substep_graph_matches_stream(W, H):
         assert np.array_equal(pa["X"], pb["X"])
         assert [(c["a"], c["b"], c["count"]) for c in a.contacts()] == \
                [(c["a"], c["b"], c["count"]) for c in b.contacts()]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_octahedra_parity(O, W, H, prec):
+    """Scenes mixing spheres, cubes and regular octahedra: owner map, pair
+    set and counts bit-exact at the start (and after each FP64 step), fields
+    and forces within the precision's tolerance."""
+    seed, dims, n, pz = 41, (28, 24, 20), 8, 1
+    sc = W.random_small_scene(seed, dims, n, periodic_z=pz, size_range=(1.6, 3.0),
+                              gap=-0.8, speed=0.01, spin=0.004, shapes=(0, 1, 2))
+    assert (sc.shape == 2).sum() >= 3
+    p = W.Params(nx=dims[0], ny=dims[1], nz=dims[2], periodic_z=pz, tau=0.7,
+                 gravity=(0.0, 0.0, -2e-4), balance=1, young=0.4, u_k=3e-4,
+                 max_pairs=256, tile_capacity=16, precision=prec)
+    f0 = W.perturbed_populations(seed, dims, O.feq(1.0, [0.003, 0.002, -0.001]),
+                                 amp=0.01)
+    o, g = _pair(O, H, p, sc, f0)
+    assert np.array_equal(g.fields()["owner"], o.fields()["owner"])
+    oc = o.contacts()
+    assert any(sc.shape[c["a"]] == 2 or (c["b"] >= 0 and sc.shape[c["b"]] == 2) for c in oc)
+    compare_contacts(oc, g.contacts(), 0.0)
+    Fref = np.abs(np.array(p.gravity)).max() * 0.5 * (4 / 3 * math.pi * 1.6 ** 3)
+    tol = TOL[prec]
+    for k in range(3):
+        o.step(2)
+        g.step(2)
+        eo, eg = o.forces(), g.forces()
+        err = max(force_err(eg["Fh"], eo["Fh"], Fref), force_err(eg["Fc"], eo["Fc"], Fref))
+        _say(f"  octahedra precision {prec} step {o.step_count}: force {err:.2e}")
+        assert err <= max(tol, 1e-11) * (10 if prec else 1)
+        if prec == 0:
+            assert np.array_equal(g.fields()["owner"], o.fields()["owner"])
+            assert [(c["a"], c["b"], c["count"]) for c in o.contacts()] == \
+                   [(c["a"], c["b"], c["count"]) for c in g.contacts()]
+    assert rel_field(g.populations(), o.populations()) <= tol

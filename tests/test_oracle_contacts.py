@@ -224,3 +224,37 @@ def test_no_contact_when_apart(O, W):
         for c in s.contacts():
             assert c["volume"] == 0.0
         assert np.abs(s.forces()["Fc"]).max() == 0.0
+
+
+@pytest.mark.parametrize("D", [4.6, 5.3])
+def test_octahedra_vertex_overlap_exact(O, W, D):
+    """Two axis-aligned octahedra of centre-to-vertex a, centres D apart
+    along x, no enlargement: their overlap is the octahedron of
+    centre-to-vertex a - D/2 around the midpoint, V = 4 (a - D/2)^3 / 3; the
+    depth max -(d_a + d_b) is attained at the midpoint, 2 (a - D/2) / sqrt 3,
+    and the normal is -x ... +x by symmetry."""
+    a = 3.0
+    p = W.Params(nx=64, ny=64, nz=64, enlarge=0.0, n_c=64)
+    q = np.array([1.0, 0, 0, 0])
+    Xa = np.array([20.0, 20.0, 20.0])
+    Xb = Xa + [D, 0.0, 0.0]
+    pa = O.make_particle(2, a, 2.0, Xa, q)
+    pb = O.make_particle(2, a, 2.0, Xb, q)
+    c = a - D / 2
+    mid = (Xa + Xb) / 2
+    lo = mid - c - 0.6
+    hi = mid + c + 0.45
+    r = O.treat_pair(p, pa, pb, 1, lo, hi, npass=100)
+    V = 4.0 * c ** 3 / 3.0
+    assert abs(r["volume"] - V) < 3e-3 * V
+    # the depth is a maximum over cell-midpoint samples: at most the exact
+    # value, and short of it by at most twice the half-diagonal of a cell
+    # (each distance is 1-Lipschitz)
+    cell = (np.array(r["hi"]) - np.array(r["lo"])) / 64
+    exact = 2 * c / math.sqrt(3.0)
+    assert r["depth"] <= exact + 1e-12
+    assert exact - r["depth"] <= np.linalg.norm(cell) + 1e-12
+    # the corrected box is the overlap's bounding box to within a cell
+    np.testing.assert_allclose(r["lo"], mid - c, atol=cell.max())
+    np.testing.assert_allclose(r["hi"], mid + c, atol=cell.max())
+    assert abs(abs(r["normal"][0]) - 1.0) < 1e-12
