@@ -186,6 +186,12 @@ hlbm_status hlbm_read_fields(hlbm_ctx *ctx, double *rho, double *u,
 /* Post-collision populations as FP64 [19][nz][ny][nx] (FP16S: w_i + h_i). */
 hlbm_status hlbm_read_populations(hlbm_ctx *ctx, double *f);
 
+/* Coupling field at the current particle state (Sec. 3.2): per node the
+   weight B(d) of the owner's signed distance and the owner's velocity at
+   the node, u_p = U + w x r (u[3*node + k]); 0 where no particle owns the
+   node.  FP64, host arrays of N and 3N values; NULL skips. */
+hlbm_status hlbm_read_coupling(hlbm_ctx *ctx, double *B, double *up);
+
 /* Latest detection: pairs with count > 0 and the sum of their counts
    (overlap node count); totals accumulated over all steps so far. */
 hlbm_status hlbm_counters(hlbm_ctx *ctx, long long *pairs,

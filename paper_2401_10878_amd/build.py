@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhlbm.so")
 SOURCES = ["api.hip", "k_particles.hip", "k_detect.hip", "k_lattice.hip",
-           "k_contacts.hip", "k_adjoint.hip"]
+           "k_contacts.hip", "k_adjoint.hip", "k_fields.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -740,6 +740,29 @@ hlbm_status hlbm_read_fields(hlbm_ctx* h, double* rho, double* u, int* owner) {
   return check_flags(c);
 }
 
+hlbm_status hlbm_read_coupling(hlbm_ctx* h, double* B, double* up) {
+  if (!h) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (!c.fluid_ready) return fail(c, HLBM_E_STATE, "not initialised");
+  const size_t n = (size_t)c.g.ncell;
+  std::vector<double> tmp(up ? n : 0);
+  if (B) {
+    HIPCHECK(launch_coupling_field(c, -1, c.scratch));
+    HIPCHECK(hipMemcpyAsync(B, c.scratch, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
+  }
+  if (up) {
+    for (int k = 0; k < 3; ++k) {
+      HIPCHECK(launch_coupling_field(c, k, c.scratch));
+      HIPCHECK(hipMemcpyAsync(tmp.data(), c.scratch, sizeof(double) * n,
+                              hipMemcpyDeviceToHost, c.stream));
+      HIPCHECK(hipStreamSynchronize(c.stream));
+      for (size_t i = 0; i < n; ++i) up[3 * i + k] = tmp[i];
+    }
+  }
+  HIPCHECK(hipStreamSynchronize(c.stream));
+  return check_flags(c);
+}
+
 hlbm_status hlbm_read_populations(hlbm_ctx* h, double* f) {
   if (!h || !f) return HLBM_E_ARG;
   Ctx& c = h->c;

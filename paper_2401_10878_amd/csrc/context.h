@@ -191,6 +191,8 @@ hipError_t launch_store_direction(Ctx& c, void* f, int i, const double* src);
 hipError_t launch_load_direction(Ctx& c, const void* f, int i, double* dst);
 // comp = -1: density, 0..2: velocity component of f* (FP64, into out[ncell])
 hipError_t launch_moment(Ctx& c, const void* f, int comp, double* out);
+// coupling field: comp = -1 weight B, 0..2 particle velocity component
+hipError_t launch_coupling_field(Ctx& c, int comp, double* out);
 // adjoint (k_adjoint.hip)
 int adjoint_record_doubles();
 int adjoint_slots();

@@ -1,0 +1,43 @@
+// Read-out of the coupling field (Sec. 3.2) for tests and diagnostics.
+#include "context.h"
+
+namespace hlbm {
+
+namespace {
+
+// Coupling field at the current particle state (Sec. 3.2), FP64: comp = -1
+// writes B(d_owner), 0..2 the component of u_p = U + w x r of the owner
+// (0 where no particle owns the node).
+__global__ void k_coupling_field(const int* __restrict__ owner, Particles P,
+                                 Geom g, Phys ph, int comp, double* __restrict__ out) {
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= g.ncell) return;
+  const int o = owner_id(owner[id]);
+  double v = 0.0;
+  if (o >= 0) {
+    const int x = (int)(id % g.nx), y = (int)((id / g.nx) % g.ny);
+    const int z = (int)(id / ((long long)g.nx * g.ny));
+    const double r[3] = {minimg((double)x - P.X[3 * o], (double)g.nx, true),
+                         minimg((double)y - P.X[3 * o + 1], (double)g.ny, true),
+                         minimg((double)z - P.X[3 * o + 2], (double)g.nz, g.periodic_z != 0)};
+    if (comp < 0) {
+      v = weight(sdf(P.shape[o], P.size[o], P.R + 9 * o, r[0], r[1], r[2]), ph.eps);
+    } else {
+      const double* W = P.W + 3 * o;
+      const double wr[3] = {W[1] * r[2] - W[2] * r[1], W[2] * r[0] - W[0] * r[2],
+                            W[0] * r[1] - W[1] * r[0]};
+      v = P.U[3 * o + comp] + wr[comp == 0 ? 0 : (comp == 1 ? 1 : 2)];
+    }
+  }
+  out[id] = v;
+}
+
+}  // namespace
+
+hipError_t launch_coupling_field(Ctx& c, int comp, double* out) {
+  hipLaunchKernelGGL(k_coupling_field, dim3((unsigned)((c.g.ncell + 255) / 256)), dim3(256), 0,
+                     c.stream, c.owner, c.part, c.g, c.ph, comp, out);
+  return hipGetLastError();
+}
+
+}  // namespace hlbm

@@ -94,6 +94,7 @@ def load():
     L.hlbm_read_contacts.argtypes = [v, i, P(Contact), P(i)]
     L.hlbm_read_fields.argtypes = [v, P(d), P(d), P(i)]
     L.hlbm_read_populations.argtypes = [v, P(d)]
+    L.hlbm_read_coupling.argtypes = [v, P(d), P(d)]
     L.hlbm_counters.argtypes = [v] + [P(C.c_longlong)] * 4
     L.hlbm_stream.argtypes = [v]
     L.hlbm_stream.restype = v
@@ -271,6 +272,13 @@ class Simulation:
             self.h, _dp(r) if rho else None, _dp(uu) if u else None,
             _ip(o) if owner else None))
         return dict(rho=r, u=uu, owner=o)
+
+    def coupling(self):
+        """B(d_owner) and u_p per node (FP64), as in the collision."""
+        s = self.shape3()
+        B, up = np.zeros(s), np.zeros(s + (3,))
+        self._check(self.L.hlbm_read_coupling(self.h, _dp(B), _dp(up)))
+        return dict(B=B, up=up)
 
     def populations(self):
         f = np.zeros((Q,) + self.shape3())

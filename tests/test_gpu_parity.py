@@ -370,3 +370,60 @@ def test_octahedra_parity(O, W, H, prec):
             assert [(c["a"], c["b"], c["count"]) for c in o.contacts()] == \
                    [(c["a"], c["b"], c["count"]) for c in g.contacts()]
     assert rel_field(g.populations(), o.populations()) <= tol
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_coupling_field_parity(O, W, H, case):
+    """The per-node coupling weight B(d_owner) and particle velocity u_p
+    (Sec. 3.2) against the oracle's, at the start and after moving steps."""
+    seed, dims, n, pz = case
+    sc = W.random_small_scene(seed, dims, n, periodic_z=pz, size_range=(1.6, 3.0),
+                              gap=-0.8, speed=0.01, spin=0.004, shapes=(0, 1, 2))
+    p = W.Params(nx=dims[0], ny=dims[1], nz=dims[2], periodic_z=pz, tau=0.7,
+                 young=0.4, u_k=3e-4, max_pairs=256, tile_capacity=16)
+    o, g = _pair(O, H, p, sc)
+    for k in range(2):
+        fo, fg = o.fields(), g.coupling()
+        assert (fo["B"] > 0).sum() > 100
+        assert np.abs(fg["B"] - fo["B"]).max() <= 1e-14
+        assert np.abs(fg["up"] - fo["up"]).max() <= 1e-15
+        o.step(3)
+        g.step(3)
+
+
+@pytest.mark.parametrize("pz", [1, 0])
+def test_no_particles_pure_fluid(O, W, H, pz):
+    """An empty particle set: the step is the plain stream-collide (with
+    half-way bounce-back at walls), FP64 against the oracle."""
+    dims = (21, 18, 23)
+    p = W.Params(nx=dims[0], ny=dims[1], nz=dims[2], periodic_z=pz, tau=0.62,
+                 fluid_accel=(1e-5, 0.0, 0.0),
+                 wall_velocity=((0.0, 0.0, 0.0), (0.002, 0.0, 0.0)),
+                 young=0.4, u_k=3e-4, max_pairs=16, tile_capacity=4)
+    f0 = W.perturbed_populations(5, dims, O.feq(1.0, [0.002, 0.001, 0.0]), amp=0.02)
+    o, g = _pair(O, H, p, W.Scene.empty(), f0)
+    o.step(7)
+    g.step(7)
+    assert rel_field(g.populations(), o.populations()) <= 1e-13
+    assert g.contacts() == [] and g.counters()["pairs"] == 0
+    assert (g.fields()["owner"] == -1).all()
+
+
+def test_pair_table_overflow_reported(W, H):
+    """More contact pairs than the table holds is an error, not a silent
+    truncation."""
+    sc = W.random_small_scene(3, (20, 20, 20), 10, size_range=(2.0, 3.0), gap=-1.2)
+    p = W.Params(nx=20, ny=20, nz=20, tau=0.7, young=0.4, u_k=3e-4,
+                 max_pairs=1, tile_capacity=32)
+    g = H.Simulation(p, sc)
+    with pytest.raises(H.HlbmError) as e:
+        g.init_equilibrium()
+    assert e.value.code == -4
+
+
+def test_oversized_lattice_rejected(W, H):
+    """32-bit population offsets: a lattice with 19 N >= 2^31 is refused
+    before any allocation."""
+    p = W.Params(nx=1400, ny=1400, nz=1400, tau=0.7, young=0.4, u_k=3e-4)
+    with pytest.raises(H.HlbmError):
+        H.Simulation(p, W.Scene.empty())
