@@ -443,10 +443,7 @@ __device__ void mea_compacted(C (*fl)[256], int (*meta)[2], int slot, int total,
     q = o;
     msk = 0x7fffeu;
   } else if (have) {
-    // owners of the 18 link neighbours (none beyond a wall).  Links whose
-    // far node is owned: by the primary particle (the node's owner, else
-    // the owner of its first owned neighbour), by a secondary particle, or
-    // by others (rare, found again below)
+    // owners of the 18 link neighbours (none beyond a wall)
     const Nbr nb = neighbours(g, x, y, z);
     int on[Q];
 #pragma unroll
@@ -455,20 +452,21 @@ __device__ void mea_compacted(C (*fl)[256], int (*meta)[2], int slot, int total,
       const int v = owner[nb.off(cx(j), cy(j), cz(j))];
       on[j] = nb.beyond(cz(j)) ? -1 : owner_id(v);
     }
-    q = o >= 0 ? o : -1;
+    // primary particle: the node's owner, else the largest neighbour owner
+    // (any fixed choice would do); links of other particles stay in `rem`
+    // and are grouped by the discovery step of the loop below
+    int qmax = -1;
 #pragma unroll
-    for (int j = 1; j < Q; ++j)
-      if (q < 0 && on[j] >= 0) q = on[j];
-#pragma unroll
-    for (int j = 1; j < Q; ++j)
-      if (q2 < 0 && on[j] >= 0 && on[j] != q) q2 = on[j];
+    for (int j = 1; j < Q; ++j) qmax = on[j] > qmax ? on[j] : qmax;
+    q = o >= 0 ? o : qmax;
+    unsigned owned = 0;
 #pragma unroll
     for (int j = 1; j < Q; ++j) {
-      if (on[j] < 0) continue;
-      if (on[j] == q) msk |= 1u << j;
-      else if (on[j] == q2) msk2 |= 1u << j;
-      else rem |= 1u << j;
+      owned |= on[j] >= 0 ? 1u << j : 0u;
+      msk |= on[j] == q ? 1u << j : 0u;
     }
+    msk &= owned;
+    rem = owned & ~msk;
   }
   const bool perz = g.periodic_z != 0;
   const bool wall_m = !perz && z == 0, wall_p = !perz && z == g.nz - 1;
