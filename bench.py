@@ -5,10 +5,11 @@ Default workload: dense settling box, 256^3 periodic lattice, 1834 cubes of
 edge 14 (phi = 0.30, s = 1.5, Ar = 1000), populations in FP32, synthetic
 seeded scene.  A step is the whole time step: contact treatment, particle
 motion and tile binning, contact carry-over, coupling map with rough
-detection, and the fused stream-collide pass with the momentum exchange.
+detection, the stream-collide pass with the coupling, and the momentum
+exchange over the populations it wrote.
 
 Prints ONE JSON line with the metric, the roofline of the dominant kernel
-(the fused lattice pass, HBM-bound) and the FP64 CPU oracle timed on a
+(the stream-collide pass, HBM-bound) and the FP64 CPU oracle timed on a
 bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--precision fp32|fp64|fp16s]

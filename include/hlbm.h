@@ -153,12 +153,13 @@ hlbm_status hlbm_step(hlbm_ctx *ctx, int nsteps);
 hlbm_status hlbm_use_graph(hlbm_ctx *ctx, int on);
 
 /* Per-kernel timing of the next steps: hlbm_step records HIP events on the
-   context stream around each of its six kernel launches (bookkeeping clear,
-   contact treatment, particle motion + tile binning, contact carry-over,
-   coupling map + rough detection, fused lattice pass) for up to max_steps
-   steps (graphs are bypassed meanwhile).  hlbm_timing_end synchronises and
-   returns the summed milliseconds per kernel in that order, kernel_ms[6],
-   and the number of timed steps. */
+   context stream around each of its seven kernel launches (bookkeeping
+   clear, contact treatment, particle motion + tile binning, contact
+   carry-over, coupling map + rough detection, stream-collide lattice pass,
+   momentum exchange) for up to max_steps steps (graphs are bypassed
+   meanwhile).  hlbm_timing_end synchronises and returns the summed
+   milliseconds per kernel in that order, kernel_ms[7], and the number of
+   timed steps. */
 hlbm_status hlbm_timing_begin(hlbm_ctx *ctx, int max_steps);
 hlbm_status hlbm_timing_end(hlbm_ctx *ctx, double *kernel_ms, int *nsteps);
 

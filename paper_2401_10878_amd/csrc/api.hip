@@ -100,7 +100,7 @@ hlbm_status prologue(Ctx& c) {
   HIPCHECK(hipMemsetAsync(c.tl.ovf, 0, 2 * nb, c.stream));
   HIPCHECK(launch_particles(c, 0));
   HIPCHECK(launch_detect(c, c.tab[p]));
-  HIPCHECK(launch_mea_only(c, c.fbuf[p]));
+  HIPCHECK(launch_mea(c, c.fbuf[p]));
   c.step = 0;
   c.fluid_ready = true;
   return check_flags(c);
@@ -108,7 +108,7 @@ hlbm_status prologue(Ctx& c) {
 
 // The launch sequence of one time step with population parity p (buffers
 // p -> 1-p) starting from contact table t; the table parity flips once per
-// sub-step.  ev (optional): 2 + 5 n_sub events recorded around the launches.
+// sub-step.  ev (optional): 3 + 5 n_sub events recorded around the launches.
 hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev) {
   hipError_t e;
   int m = 0;
@@ -130,6 +130,8 @@ hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev) {
     t = 1 - t;
   }
   if ((e = launch_lattice(c, c.fbuf[p], c.fbuf[1 - p]))) return e;
+  if ((e = mark())) return e;
+  if ((e = launch_mea(c, c.fbuf[1 - p]))) return e;
   return mark();
 }
 
@@ -270,6 +272,10 @@ hlbm_status hlbm_create(const hlbm_params* params, void* stream, hlbm_ctx** out)
   c.g.ltx = (P.nx + LX - 1) / LX;
   c.g.lty = (P.ny + LY - 1) / LY;
   c.g.ltz = (P.nz + LZ - 1) / LZ;
+  c.g.fdtx = make_fastdiv((unsigned)c.g.dtx);
+  c.g.fdty = make_fastdiv((unsigned)c.g.dty);
+  c.g.fltx = make_fastdiv((unsigned)c.g.ltx);
+  c.g.flty = make_fastdiv((unsigned)c.g.lty);
   c.g.tile_cap = P.tile_capacity;
   c.g.ncell = ncell;
   c.ph.tau = P.tau;
@@ -292,7 +298,7 @@ hlbm_status hlbm_create(const hlbm_params* params, void* stream, hlbm_ctx** out)
   c.ph.u_k = P.u_k;
   c.n_sub = P.n_sub;
   c.ph.dt_sub = 1.0 / (double)P.n_sub;
-  c.ev_per_step = 2 + 5 * P.n_sub;
+  c.ev_per_step = 3 + 5 * P.n_sub;
 
   if (stream) {
     c.stream = (hipStream_t)stream;
@@ -608,7 +614,7 @@ hlbm_status hlbm_timing_end(hlbm_ctx* h, double* kernel_ms, int* nsteps) {
   HIPCHECK(hipStreamSynchronize(c.stream));
   for (int k = 0; k < NKERN; ++k) kernel_ms[k] = 0.0;
   // events: start, then per sub-step after clear, treat, particles, keep,
-  // detect; then after the lattice pass
+  // detect; then after the lattice pass and after the momentum exchange
   for (int s = 0; s < c.tused; ++s) {
     hipEvent_t* ev = c.tev + (size_t)s * c.ev_per_step;
     for (int sub = 0; sub < c.n_sub; ++sub)
@@ -617,9 +623,11 @@ hlbm_status hlbm_timing_end(hlbm_ctx* h, double* kernel_ms, int* nsteps) {
         HIPCHECK(hipEventElapsedTime(&ms, ev[5 * sub + k], ev[5 * sub + k + 1]));
         kernel_ms[k] += (double)ms;
       }
-    float ms = 0.0f;
-    HIPCHECK(hipEventElapsedTime(&ms, ev[c.ev_per_step - 2], ev[c.ev_per_step - 1]));
-    kernel_ms[5] += (double)ms;
+    for (int k = 0; k < 2; ++k) {
+      float ms = 0.0f;
+      HIPCHECK(hipEventElapsedTime(&ms, ev[c.ev_per_step - 3 + k], ev[c.ev_per_step - 2 + k]));
+      kernel_ms[5 + k] += (double)ms;
+    }
   }
   *nsteps = c.tused;
   free_timing(c);
@@ -733,10 +741,6 @@ hlbm_status hlbm_read_fields(hlbm_ctx* h, double* rho, double* u, int* owner) {
   if (owner)
     HIPCHECK(hipMemcpyAsync(owner, c.owner, sizeof(int) * n, hipMemcpyDeviceToHost, c.stream));
   HIPCHECK(hipStreamSynchronize(c.stream));
-  // every negative code of the device map reads as "no owner"; the interior
-  // flag is dropped
-  if (owner)
-    for (size_t i = 0; i < n; ++i) owner[i] = owner[i] < 0 ? -1 : (owner[i] & (OWNER_INTERIOR - 1));
   return check_flags(c);
 }
 

@@ -44,11 +44,30 @@ struct Counters {
 };
 
 // Scalar parameters handed to every kernel by value.
+// Division of 0 <= n < 2^31 by a fixed divisor d >= 1 with one multiply-high
+// and a shift (Granlund and Montgomery, PLDI 1994): with s = ceil(log2 d)
+// and m = floor(2^32 (2^s - d) / d) + 1, n / d = (mulhi(n, m) + n) >> s; the
+// sum stays below 2^32 because mulhi(n, m) <= n.
+struct FastDiv {
+  unsigned d, m, s;
+};
+inline FastDiv make_fastdiv(unsigned d) {
+  unsigned s = 0;
+  while ((1ull << s) < d) ++s;
+  const unsigned long long m = ((1ull << 32) * ((1ull << s) - d)) / d + 1;
+  return FastDiv{d, (unsigned)m, s};
+}
+__host__ __device__ inline unsigned fdiv(unsigned n, FastDiv f) {
+  return (unsigned)(((((unsigned long long)n * f.m) >> 32) + n) >> f.s);
+}
+
 struct Geom {
   int nx, ny, nz;
   int periodic_z;
   int dtx, dty, dtz;      // detection tiles per axis (DX x DY x DZ nodes)
   int ltx, lty, ltz;      // lattice blocks per axis (LX x LY x LZ nodes)
+  FastDiv fdtx, fdty;     // divisions by dtx, dty
+  FastDiv fltx, flty;     // divisions by ltx, lty
   int tile_cap;           // particles per candidate list (both tilings)
   int maxent;             // lattice blocks per particle (partial-sum slots)
   long long ncell;
@@ -91,7 +110,7 @@ struct Phys {
   double dt_sub;          // length of a contact sub-step (1 / n_sub)
 };
 
-constexpr int NKERN = 6;   // clear, treat, particles, keep, detect, lattice
+constexpr int NKERN = 7;   // clear, treat, particles, keep, detect, lattice, mea
 
 // Device copy of the whole step state (populations f*, particle block,
 // candidate lists and partial sums, both pair tables, owner map, counters).
@@ -159,7 +178,7 @@ struct Ctx {
   // state
   bool particles_ready, fluid_ready;
   long long step;
-  // per-kernel timing: NKERN+1 events per step, a pool for `tcap` steps
+  // per-kernel timing: ev_per_step events per step, a pool for `tcap` steps
   bool timing;
   int tcap, tused;
   hipEvent_t* tev;
@@ -182,8 +201,10 @@ hipError_t launch_clear_step(Ctx& c, PairTable next);
 hipError_t launch_particles(Ctx& c, int move);
 hipError_t launch_keep(Ctx& c, PairTable from, PairTable to);
 hipError_t launch_detect(Ctx& c, PairTable to);
+// stream-collide src -> dst with the coupling of the current owner map
 hipError_t launch_lattice(Ctx& c, const void* src, void* dst);
-hipError_t launch_mea_only(Ctx& c, const void* fstar);
+// momentum exchange over the collided populations fstar (force of the next step)
+hipError_t launch_mea(Ctx& c, const void* fstar);
 hipError_t launch_treat(Ctx& c, PairTable t);
 hipError_t launch_fill_equilibrium(Ctx& c, void* f, double rho,
                                    const double u[3]);

@@ -24,13 +24,8 @@ constexpr int DX = 4, DY = 4, DZ = 4;
 constexpr int LX = 64, LY = 4, LZ = 1;
 constexpr int LCAP_MAX = 64;    // lattice-block candidate capacity
 constexpr int MAXC = 32;        // contacts per particle in one step
-// owner-map code of a node with no owner but a link neighbour that may have
-// one (every negative code means "no owner")
-constexpr int NEAR_NONE = -2;
-// flag on the owner code of a node whose 18 link neighbours are all owned by
-// the same particle (the node lies deep inside it and no other body reaches)
-constexpr int OWNER_INTERIOR = 1 << 30;
-__device__ inline int owner_id(int v) { return v < 0 ? -1 : (v & (OWNER_INTERIOR - 1)); }
+// owner-map entry: the owning particle's id, or -1 (no owner)
+__device__ inline int owner_id(int v) { return v < 0 ? -1 : v; }
 constexpr int WAVE = 64;
 constexpr double DETECT = 0.8660254037844386;   // sqrt(0.75), Sec. 3.3.1
 constexpr double PI = 3.141592653589793;
@@ -204,10 +199,11 @@ __device__ inline float sdf32(int shape, float size, const double* R, float r0,
   return sqrtf(m0 * m0 + m1 * m1 + m2 * m2) + fminf(fmaxf(fmaxf(q0, q1), q2), 0.0f);
 }
 
-// As sdf32, with the rotation already in FP32.
+// As sdf32, with the rotation already in FP32 and the hardware square root
+// (within 1 ulp; used for screening against an error bound).
 __device__ inline float sdf32_r(int shape, float size, const float* R, float r0,
                                 float r1, float r2) {
-  if (shape == 0) return sqrtf(r0 * r0 + r1 * r1 + r2 * r2) - size;
+  if (shape == 0) return __builtin_amdgcn_sqrtf(r0 * r0 + r1 * r1 + r2 * r2) - size;
   const float h = 0.5f * size;
   const float p0 = R[0] * r0 + R[3] * r1 + R[6] * r2;
   const float p1 = R[1] * r0 + R[4] * r1 + R[7] * r2;
@@ -215,7 +211,8 @@ __device__ inline float sdf32_r(int shape, float size, const float* R, float r0,
   if (shape == 2) return octa_q<float>(size, fabsf(p0), fabsf(p1), fabsf(p2));
   const float q0 = fabsf(p0) - h, q1 = fabsf(p1) - h, q2 = fabsf(p2) - h;
   const float m0 = fmaxf(q0, 0.0f), m1 = fmaxf(q1, 0.0f), m2 = fmaxf(q2, 0.0f);
-  return sqrtf(m0 * m0 + m1 * m1 + m2 * m2) + fminf(fmaxf(fmaxf(q0, q1), q2), 0.0f);
+  return __builtin_amdgcn_sqrtf(m0 * m0 + m1 * m1 + m2 * m2) +
+         fminf(fmaxf(fmaxf(q0, q1), q2), 0.0f);
 }
 
 // Signed distance with its world-frame gradient.  Inside a cube the

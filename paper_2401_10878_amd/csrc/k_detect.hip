@@ -63,12 +63,17 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
                                                 Tiles tl, int* __restrict__ owner,
                                                 PairTable tab, Counters* ctr) {
   const int lane = threadIdx.x % WAVE;
-  const long long ntiles = (long long)g.dtx * g.dty * g.dtz;
-  const long long tile = (long long)blockIdx.x * 4 + threadIdx.x / WAVE;
+  // tile id, uniform over the wavefront (fewer than 2^31 tiles: the cell
+  // count is bounded on the host)
+  const unsigned ntiles = (unsigned)g.dtx * (unsigned)g.dty * (unsigned)g.dtz;
+  const unsigned tile =
+      blockIdx.x * 4u + (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x) / WAVE;
   if (tile >= ntiles) return;                     // whole wavefront exits
-  const int tx = (int)(tile % g.dtx);
-  const int ty = (int)((tile / g.dtx) % g.dty);
-  const int tz = (int)(tile / ((long long)g.dtx * g.dty));
+  const unsigned tyz = fdiv(tile, g.fdtx);
+  const unsigned utz = fdiv(tyz, g.fdty);
+  const int tx = (int)(tile - tyz * (unsigned)g.dtx);
+  const int ty = (int)(tyz - utz * (unsigned)g.dty);
+  const int tz = (int)utz;
   const int x = tx * DX + (lane % DX);
   const int y = ty * DY + (lane / DX) % DY;
   const int z = tz * DZ + lane / (DX * DY);
@@ -81,7 +86,7 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
   // c of the list whatever the count); the loops take candidate c's id with
   // readlane and its FP32 screening record (centre, rotation) through
   // scalar loads.
-  const int* list = tl.dlist + tile * g.tile_cap;
+  const int* list = tl.dlist + (size_t)tile * g.tile_cap;
   const int cnt_raw = tl.dcount[tile];
   const int my_id = lane < g.tile_cap ? list[lane] : 0;
   int cnt = __builtin_amdgcn_readfirstlane(cnt_raw);
@@ -94,11 +99,19 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
   const double det_t = DETECT + ph.delta_c;       // detection: d < sqrt(0.75) + delta_c
 
   // Pass 1, FP32: classify each candidate against both thresholds with a
-  // bound on the FP32 error; a lane is settled when every candidate is
-  // clearly on one side of both thresholds and at most one can own it.
-  int bp = -1, nown = 0, nnear = 0;
-  bool unsure = false, deep = false;
-  uint64_t mask = 0;
+  // bound on the FP32 error.  Per lane: pown = candidates that may own the
+  // node (d < eps/2 + tol), near_own = one of them lies within tol of eps/2,
+  // dun = candidates within tol of the detection threshold, mask = the FP32
+  // detection decision (final for candidates outside dun).
+  //
+  // The error bound tol = 1e-3 + 1e-5 (|r|_1 + size) is taken with |r|_1 at
+  // its largest for a node within reach of either threshold, sqrt 3 (R + 2)
+  // with R the circumradius, so it is uniform per candidate: a node farther
+  // out has d far above both thresholds, where the bound is not needed.
+  int bp = -1;
+  bool near_own = false;
+  uint64_t pown = 0, dun = 0, mask = 0;
+  const float ot = (float)own_t, dt = (float)det_t;
   for (int c = 0; c < cnt; ++c) {
     const int p = __builtin_amdgcn_readlane(pid, c);
     const float* xr = P.XR32 + 12 * p;      // uniform: scalar loads
@@ -108,65 +121,61 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
     const float f1 = minimg_f(fyf - xr[1], Lyf, true);
     const float f2 = minimg_f(fzf - xr[2], Lzf, perz);
     const float d = sdf32_r(shape, size, xr + 3, f0, f1, f2);
-    const float tol = 1e-3f + 1e-5f * (fabsf(f0) + fabsf(f1) + fabsf(f2) + size);
-    const float ot = (float)own_t, dt = (float)det_t;
-    // a link neighbour (at most sqrt 2 away) can be owned by p only if
-    // d < eps/2 + sqrt 2 here, and is surely inside the owning band of p if
-    // d < -eps/2 - sqrt 2 (signed distances are 1-Lipschitz)
-    if (d < ot + 1.4142135f + tol) ++nnear;
+    const float rc = shape == 1 ? 0.8660254f * size : size;
+    const float tol = 1e-3f + 1e-5f * (1.7320508f * (rc + 2.0f) + size);
+    const uint64_t bit = 1ull << c;
     if (d < ot + tol) {
-      ++nown;
+      pown |= bit;
       bp = p;
-      deep = d < -ot - 1.4142135f - tol;
-      if (d > ot - tol) unsure = true;
+      if (d > ot - tol) near_own = true;
     }
     if (d < dt + tol) {
-      mask |= 1ull << c;
-      if (d > dt - tol) unsure = true;
+      mask |= bit;
+      if (d > dt - tol) dun |= bit;
     }
   }
-  if (!valid) {
-    bp = -1;
-    mask = 0;
-  }
-  // Pass 2, FP64, for the lanes pass 1 did not settle: the exact signed
-  // distances decide the owner (smallest (d, id)) and the detection set.
-  const bool exact = valid && (unsure || nown > 1);
-  if (__ballot(exact)) {
+  // Pass 2, FP64, only where pass 1 did not settle: the owner when two or
+  // more candidates may own the node or one lies within tol of eps/2
+  // (smallest (d, id) over the possible owners), and the detection bit of
+  // each candidate within tol of its threshold.  The wavefront loops over
+  // the union of those candidates; each lane evaluates only its own.
+  const bool own_open = valid && (near_own || (pown & (pown - 1)) != 0);
+  const uint64_t need = valid ? ((own_open ? pown : 0) | dun) : 0;
+  uint64_t todo = wave_or_u64(need);
+  if (todo) {
     double bd = 1.0e300;
     int ep = -1;
-    uint64_t em = 0;
-    for (int c = 0; c < cnt; ++c) {
+    while (todo) {
+      const int c = __builtin_ctzll(todo);
+      todo &= todo - 1;
       const int p = __builtin_amdgcn_readlane(pid, c);
-      if (exact) {
+      if ((need >> c) & 1ull) {
         const double X0 = P.X[3 * p], X1 = P.X[3 * p + 1], X2 = P.X[3 * p + 2];
         const double* R = P.R + 9 * p;
         const double r0 = minimg(fx - X0, Lx, true);
         const double r1 = minimg(fy - X1, Ly, true);
         const double r2 = minimg(fz - X2, Lz, perz);
         const double d = sdf(P.shape[p], P.size[p], R, r0, r1, r2);
-        if (d < own_t && (d < bd || (d == bd && p < ep))) {
+        if (own_open && ((pown >> c) & 1ull) && d < own_t &&
+            (d < bd || (d == bd && p < ep))) {
           bd = d;
           ep = p;
         }
-        if (d - ph.delta_c < DETECT) em |= 1ull << c;
+        if ((dun >> c) & 1ull) {
+          if (d - ph.delta_c < DETECT) mask |= 1ull << c;
+          else mask &= ~(1ull << c);
+        }
       }
     }
-    if (exact) {
-      bp = ep;
-      mask = em;
-    }
+    if (own_open) bp = ep;
   }
-  // owner map: the owner (flagged OWNER_INTERIOR when the node is deep inside
-  // it, no other body comes within reach of a link neighbour and no link
-  // crosses a wall, so that all 18 link neighbours are owned by it), or
-  // NEAR_NONE for an unowned node with a possibly owned link neighbour, or
-  // -1 (no owner anywhere within one link)
-  const bool wall_adj = !perz && (z == 0 || z == g.nz - 1);
-  const bool interior = !exact && bp >= 0 && deep && nnear == 1 && !wall_adj;
+  if (!valid) {
+    bp = -1;
+    mask = 0;
+  }
+  // owner map: the owner's id, or -1
   if (valid)
-    owner[(long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z)] =
-        bp >= 0 ? (interior ? (bp | OWNER_INTERIOR) : bp) : (nnear > 0 ? NEAR_NONE : -1);
+    owner[(long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z)] = bp;
 
   const uint64_t orm = wave_or_u64(mask);
   if (orm == 0) return;

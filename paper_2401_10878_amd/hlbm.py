@@ -213,13 +213,14 @@ class Simulation:
     def use_graph(self, on=True):
         self._check(self.L.hlbm_use_graph(self.h, 1 if on else 0))
 
-    KERNELS = ("clear", "treat", "particles", "keep", "detect", "lattice")
+    KERNELS = ("clear", "treat", "particles", "keep", "detect", "lattice",
+               "mea")
 
     def timing_begin(self, max_steps):
         self._check(self.L.hlbm_timing_begin(self.h, max_steps))
 
     def timing_end(self):
-        ms = np.zeros(6)
+        ms = np.zeros(len(self.KERNELS))
         n = C.c_int()
         self._check(self.L.hlbm_timing_end(self.h, _dp(ms), C.byref(n)))
         return dict(zip(self.KERNELS, ms.tolist())), n.value
