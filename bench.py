@@ -28,7 +28,7 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PREC = {"fp64": 0, "fp32": 1, "fp16s": 2}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f16-storage/f32-compute"}
 VALUE_BYTES = {0: 8, 1: 4, 2: 2}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lattice_c3_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lattice_k_mea_c3_traffic.json")
 LATTICE_SRC = os.path.join(ROOT, "paper_2401_10878_amd", "csrc", "k_lattice.hip")
 
 
@@ -36,17 +36,19 @@ def lattice_source_hash():
     return hashlib.sha256(open(LATTICE_SRC, "rb").read()).hexdigest()[:16]
 
 
-def traffic_for(prec_name):
-    """HBM bytes per lattice launch from the committed rocprofv3 counters,
-    or None if the counters were taken on another version of the kernel."""
+def traffic_for(prec_name, section="per_precision", field="bytes_per_launch"):
+    """HBM bytes per launch of the stream-collide pass (section
+    per_precision) or the momentum-exchange pass (mea_per_precision) from the
+    committed rocprofv3 counters, or None if the counters were taken on
+    another version of the kernels."""
     try:
         d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_sha256_16") != lattice_source_hash():
         return None
-    e = d.get("per_precision", {}).get(prec_name)
-    return e.get("bytes_per_launch") if e else None
+    e = d.get(section, {}).get(prec_name)
+    return e.get(field) if e else None
 
 
 def run_gpu(wl, prec, steps, warmup, graph):
@@ -208,6 +210,11 @@ def main():
                 traffic=traffic, kernel="k_lattice",
                 bytes_per_launch=main_res["bytes_alg"],
                 avg_launch_ms=round(lat_ms, 5))
+    mea_ms = main_res["kernel_ms_per_step"]["mea"]
+    mea_read = traffic_for(args.precision, "mea_per_precision", "read_bytes")
+    mea = dict(kernel="k_mea", avg_launch_ms=round(mea_ms, 5),
+               hbm_read_bytes=mea_read,
+               read_gbs=None if mea_read is None else round(mea_read / (mea_ms * 1e6), 1))
     cpu = cpu_baseline(wl, args.cpu_steps) if args.cpu_steps > 0 else None
     p = wl.params
     line = dict(
@@ -227,6 +234,7 @@ def main():
         graph_ms_per_step=None if graph_ms is None else round(graph_ms, 4),
         precisions=others,
         roofline=roof,
+        mea_pass=mea,
         cpu_baseline=cpu,
     )
     print(json.dumps(line), flush=True)

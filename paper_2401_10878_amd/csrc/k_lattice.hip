@@ -68,8 +68,10 @@ __device__ inline unsigned xcd_block(unsigned bid, unsigned nblocks) {
   return xcd * m + (xcd < r ? xcd : r) + k;
 }
 
-// Lattice block of the workgroup (64 x 4 x 1 nodes, one x-row per
-// wavefront), with consecutive block ids kept on one XCD.
+// Lattice block of the workgroup (LX x LY x LZ nodes, one x-row per
+// wavefront, the four rows stacked along y or z), with consecutive block ids
+// kept on one XCD.
+static_assert(LX == WAVE && LY * LZ == 4 && (LY == 1 || LZ == 1), "block shape");
 struct BlockNode {
   long long block;
   int x, y, z, wave;
@@ -85,10 +87,10 @@ __device__ inline BlockNode block_node(const Geom& g) {
   const unsigned bz = fdiv(yz, g.flty);
   const int bx = (int)(lb - yz * (unsigned)g.ltx);
   const int by = (int)(yz - bz * (unsigned)g.lty);
-  r.wave = threadIdx.x / WAVE;
+  r.wave = (int)((unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x) / WAVE);
   r.x = bx * LX + (int)(threadIdx.x % WAVE);
-  r.y = by * LY + r.wave;
-  r.z = (int)bz;
+  r.y = by * LY + (LY > 1 ? r.wave : 0);
+  r.z = (int)bz * LZ + (LZ > 1 ? r.wave : 0);
   r.valid = r.x < g.nx && r.y < g.ny && r.z < g.nz;
   return r;
 }
