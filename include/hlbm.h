@@ -75,7 +75,14 @@ typedef struct {
     double wall_velocity[2][3]; /* bottom (0) and top (1) wall velocity */
     double gravity[3];          /* gravitational acceleration on particles */
     double fluid_accel[3];      /* uniform acceleration added to the fluid */
-    int balance;                /* add the zero-net-flow balance force */
+    int balance;                /* balance force (Sec. 5.1) on a fully periodic
+                                   box: 0 none; 1 the uniform fluid
+                                   acceleration -sum (s_p - 1) V_p g / N that
+                                   cancels the particles' net weight; 2 hold
+                                   the net volume flow (lattice momentum) at
+                                   zero: after each collision the
+                                   acceleration of the next is set from the
+                                   lattice momentum of the last two steps */
     double eps_b;               /* width of the B(d) band around the surface */
     double enlarge;             /* enlargement in contact treatment (0.2) */
     int n_c;                    /* contact resolution (8), 1..32 */
@@ -202,8 +209,9 @@ hlbm_status hlbm_counters(hlbm_ctx *ctx, long long *pairs,
 /* The context's stream (hipStream_t) and precision. */
 void *hlbm_stream(const hlbm_ctx *ctx);
 
-/* The uniform fluid acceleration in use (fluid_accel + balance force). */
-hlbm_status hlbm_fluid_acceleration(const hlbm_ctx *ctx, double a[3]);
+/* The uniform fluid acceleration the next collision uses (fluid_accel +
+   balance force; with balance mode 2 read from the device). */
+hlbm_status hlbm_fluid_acceleration(hlbm_ctx *ctx, double a[3]);
 
 /* Checkpoint and resume.  hlbm_get_state copies the whole step state
    (populations in their storage precision, particle records, candidate

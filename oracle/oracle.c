@@ -287,6 +287,9 @@ struct orc_sim {
     orc_particle *p;
     double *Fh, *Th, *Fc, *Tc;
     double a_ext[3];
+    /* zero-net-flux balance (balance mode 2): lattice mass, lattice
+       momentum after the last collision, controller part of a_ext */
+    double bal_M, bal_P[3], bal_b[3];
     /* coupling fields at the current particle state */
     int *owner;
     double *dist, *B, *up;
@@ -388,7 +391,7 @@ orc_sim *orc_create(const orc_params *P, int np, const int *shape,
        force, and hence the net volume flow, stays zero on a fully periodic
        box.  Applied only when requested and the box is fully periodic. */
     for (int k = 0; k < 3; ++k) S->a_ext[k] = P->fluid_accel[k];
-    if (P->balance && P->periodic_z) {
+    if (P->balance == 1 && P->periodic_z) {
         double tot[3] = {0.0, 0.0, 0.0};
         for (int i = 0; i < np; ++i) {
             double V = volume_of(&S->p[i]);
@@ -1126,8 +1129,60 @@ static void collide(orc_sim *S)
  * begins with the streaming half of the previous "collide and stream".  The
  * contact forces reported are those of the last sub-step.
  * ====================================================================== */
+/* ======================================================================
+ * Zero-net-flux balance force (balance mode 2), a reading of Sec. 5.1: the
+ * uniform fluid acceleration is chosen so that the suspension keeps a net
+ * volume flow rate of zero.  The lattice covers the particles too (their
+ * nodes move with u_p), so the net flow is the lattice momentum
+ * P = sum_x sum_i c_i f_i*.  Streaming conserves P on a periodic box; the
+ * collision of step t adds C_t (coupling and any fluid_accel) plus b_t M,
+ * with M = sum_x rho the lattice mass and b_t the controller part of the
+ * acceleration.  Aiming at P_{t+1} = 0 with the coupling of step t+1 taken
+ * as that of step t:
+ *     C_t = P_t - P_{t-1} - b_t M,   b_{t+1} = -(P_t + C_t) / M,
+ * and b_0 = -P_{-1} / M from the initial populations.  P stays at the size
+ * of the step-to-step change of C instead of accumulating it.
+ * ====================================================================== */
+static void lattice_momentum(const orc_sim *S, double *M, double *P)
+{
+    long n = S->n;
+    double m = 0.0, p[3] = {0.0, 0.0, 0.0};
+    for (long id = 0; id < n; ++id)
+        for (int i = 0; i < ORC_Q; ++i) {
+            double v = S->fs[i * n + id];
+            m += v;
+            for (int k = 0; k < 3; ++k) p[k] += CV[i][k] * v;
+        }
+    if (M) *M = m;
+    for (int k = 0; k < 3; ++k) P[k] = p[k];
+}
+
+static void balance_start(orc_sim *S)
+{
+    if (S->P.balance != 2 || !S->P.periodic_z) return;
+    lattice_momentum(S, &S->bal_M, S->bal_P);
+    for (int k = 0; k < 3; ++k) {
+        S->bal_b[k] = -S->bal_P[k] / S->bal_M;
+        S->a_ext[k] = S->P.fluid_accel[k] + S->bal_b[k];
+    }
+}
+
+static void balance_update(orc_sim *S)
+{
+    if (S->P.balance != 2 || !S->P.periodic_z) return;
+    double P[3];
+    lattice_momentum(S, NULL, P);
+    for (int k = 0; k < 3; ++k) {
+        double C = P[k] - S->bal_P[k] - S->bal_b[k] * S->bal_M;
+        S->bal_b[k] = -(P[k] + C) / S->bal_M;
+        S->bal_P[k] = P[k];
+        S->a_ext[k] = S->P.fluid_accel[k] + S->bal_b[k];
+    }
+}
+
 static int prologue(orc_sim *S)
 {
+    balance_start(S);
     if (couple_and_detect_nodes(S) != 0) {
         set_err(S, "detection set overflow (more than ORC_MAXK particles at a node)");
         return -1;
@@ -1170,6 +1225,7 @@ int orc_step(orc_sim *S, int nsteps)
             detect_and_merge(S, nkeep);
         }
         collide(S);
+        balance_update(S);
         S->step++;
     }
     return 0;

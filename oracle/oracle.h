@@ -34,7 +34,9 @@ typedef struct {
     double wall_u[2][3];     /* velocity of the bottom (0) and top (1) wall */
     double gravity[3];       /* gravitational acceleration on particles */
     double fluid_accel[3];   /* uniform acceleration added to the fluid */
-    int balance;             /* add the zero-net-flow balance acceleration */
+    int balance;             /* balance force on a fully periodic box:
+                                0 none; 1 cancel the particles' net weight;
+                                2 hold the lattice momentum at zero */
     double eps;              /* width of the B(d) transition band */
     double delta_c;          /* enlargement during contact treatment */
     int n_c;                 /* contact resolution */

@@ -100,7 +100,8 @@ hlbm_status prologue(Ctx& c) {
   HIPCHECK(hipMemsetAsync(c.tl.ovf, 0, 2 * nb, c.stream));
   HIPCHECK(launch_particles(c, 0));
   HIPCHECK(launch_detect(c, c.tab[p]));
-  HIPCHECK(launch_mea(c, c.fbuf[p]));
+  HIPCHECK(launch_mea(c, c.fbuf[c.cur]));
+  if (c.ph.bal_mode == 2) HIPCHECK(launch_balance(c, c.fbuf[c.cur], 1));
   c.step = 0;
   c.fluid_ready = true;
   return check_flags(c);
@@ -130,6 +131,7 @@ hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev) {
     t = 1 - t;
   }
   if ((e = launch_lattice(c, c.fbuf[p], c.fbuf[1 - p]))) return e;
+  if (c.ph.bal_mode == 2 && (e = launch_balance(c, nullptr, 0))) return e;
   if ((e = mark())) return e;
   if ((e = launch_mea(c, c.fbuf[1 - p]))) return e;
   return mark();
@@ -258,6 +260,7 @@ hlbm_status hlbm_create(const hlbm_params* params, void* stream, hlbm_ctx** out)
   if (P.max_pairs < 1 || P.max_pairs > (1 << 24)) return bad("max_pairs must be 1..2^24");
   if (P.precision < 0 || P.precision > 2) return bad("precision must be 0, 1 or 2");
   if (P.n_sub < 1 || P.n_sub > 64) return bad("n_sub must be 1..64");
+  if (P.balance < 0 || P.balance > 2) return bad("balance must be 0, 1 or 2");
   if (!(P.eps_b > 0.0) || !(P.enlarge >= 0.0)) return bad("eps_b > 0 and enlarge >= 0 required");
   if (!(P.young > 0.0) || !(P.u_k > 0.0) || !(P.mu_s > 0.0))
     return bad("young, u_k and mu_s must be positive");
@@ -319,7 +322,9 @@ hlbm_status hlbm_create(const hlbm_params* params, void* stream, hlbm_ctx** out)
   bool okm = hipMalloc(&c.owner, sizeof(int) * ncell) == hipSuccess &&
              hipMalloc(&c.tile_block, tbytes) == hipSuccess &&
              hipMalloc(&c.counters, sizeof(Counters)) == hipSuccess &&
-             hipMalloc(&c.scratch, sizeof(double) * ncell) == hipSuccess;
+             hipMalloc(&c.scratch, sizeof(double) * ncell) == hipSuccess &&
+             (P.balance != 2 ||
+              hipMalloc(&c.bal_part, sizeof(double) * 4 * (size_t)nlt) == hipSuccess);
   for (int k = 0; k < 2 && okm; ++k) {
     c.tab[k].cap = cap;
     okm = hipMalloc(&c.tab[k].keys, sizeof(uint64_t) * cap) == hipSuccess &&
@@ -494,9 +499,12 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
     HIPCHECK(hipMemcpyAsync(c.part.U, Uh.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c.stream));
     HIPCHECK(hipMemcpyAsync(c.part.W, Wh.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c.stream));
   }
-  // zero-net-flow balance force (Sec. 5.1) on fully periodic boxes
+  // zero-net-flow balance force (Sec. 5.1) on fully periodic boxes: mode 1
+  // cancels the particles' net weight here; mode 2 is a controller on the
+  // lattice momentum, updated on the device after every collision
   for (int k = 0; k < 3; ++k) c.ph.a_ext[k] = c.P.fluid_accel[k];
-  if (c.P.balance && c.g.periodic_z) {
+  c.ph.bal_mode = (c.P.balance == 2 && c.g.periodic_z) ? 2 : 0;
+  if (c.P.balance == 1 && c.g.periodic_z) {
     double tot[3] = {0.0, 0.0, 0.0};
     for (int i = 0; i < n; ++i)
       for (int k = 0; k < 3; ++k) tot[k] += (ds[i] - 1.0) * vol[i] * c.P.gravity[k];
@@ -797,9 +805,18 @@ hlbm_status hlbm_counters(hlbm_ctx* h, long long* pairs, long long* cells,
 
 void* hlbm_stream(const hlbm_ctx* h) { return h ? (void*)h->c.stream : nullptr; }
 
-hlbm_status hlbm_fluid_acceleration(const hlbm_ctx* h, double a[3]) {
+hlbm_status hlbm_fluid_acceleration(hlbm_ctx* h, double a[3]) {
   if (!h || !a) return HLBM_E_ARG;
-  for (int k = 0; k < 3; ++k) a[k] = h->c.ph.a_ext[k];
+  Ctx& c = h->c;
+  if (c.ph.bal_mode == 2) {
+    if (!c.fluid_ready) return fail(c, HLBM_E_STATE, "initialise particles and fluid first");
+    Counters k;
+    HIPCHECK(hipMemcpyAsync(&k, c.counters, sizeof k, hipMemcpyDeviceToHost, c.stream));
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    for (int i = 0; i < 3; ++i) a[i] = k.bal_a[i];
+    return HLBM_OK;
+  }
+  for (int k = 0; k < 3; ++k) a[k] = c.ph.a_ext[k];
   return HLBM_OK;
 }
 
@@ -926,6 +943,8 @@ hlbm_status hlbm_adjoint_record(hlbm_ctx* h, int ksteps, int ckpt_every) {
     return fail(c, HLBM_E_ARG, "the adjoint runs on the FP64 form only");
   if (!c.g.periodic_z) return fail(c, HLBM_E_ARG, "the adjoint needs a fully periodic box");
   if (c.n_sub != 1) return fail(c, HLBM_E_ARG, "the adjoint runs without contact sub-steps");
+  if (c.ph.bal_mode == 2)
+    return fail(c, HLBM_E_ARG, "the adjoint supports balance modes 0 and 1 only");
   if (c.timing) return fail(c, HLBM_E_STATE, "finish the timing window first");
   if (ksteps < 1 || ckpt_every < 1)
     return fail(c, HLBM_E_ARG, "ksteps and ckpt_every must be >= 1");
@@ -1067,6 +1086,7 @@ void hlbm_destroy(hlbm_ctx* h) {
   if (c.owner) hipFree(c.owner);
   if (c.tile_block) hipFree(c.tile_block);
   if (c.counters) hipFree(c.counters);
+  if (c.bal_part) hipFree(c.bal_part);
   if (c.scratch) hipFree(c.scratch);
   for (int k = 0; k < 2; ++k) {
     if (c.tab[k].keys) hipFree(c.tab[k].keys);

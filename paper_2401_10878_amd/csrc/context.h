@@ -41,9 +41,12 @@ struct Counters {
   int pair_overflow;
   int unstable;
   int contact_overflow;   // more than MAXC contacts on one particle
+  // zero-net-flux balance force (balance mode 2): controller part b of the
+  // fluid acceleration, lattice momentum P after the last collision,
+  // lattice mass M, and the acceleration a = fluid_accel + b in use
+  double bal_b[3], bal_P[3], bal_M, bal_a[3];
 };
 
-// Scalar parameters handed to every kernel by value.
 // Division of 0 <= n < 2^31 by a fixed divisor d >= 1 with one multiply-high
 // and a shift (Granlund and Montgomery, PLDI 1994): with s = ceil(log2 d)
 // and m = floor(2^32 (2^s - d) / d) + 1, n / d = (mulhi(n, m) + n) >> s; the
@@ -61,6 +64,7 @@ __host__ __device__ inline unsigned fdiv(unsigned n, FastDiv f) {
   return (unsigned)(((((unsigned long long)n * f.m) >> 32) + n) >> f.s);
 }
 
+// Scalar parameters handed to every kernel by value.
 struct Geom {
   int nx, ny, nz;
   int periodic_z;
@@ -102,7 +106,8 @@ struct Phys {
   double tau, omega;      // relaxation time and 1/tau
   double wall_u[2][3];
   double gravity[3];
-  double a_ext[3];        // uniform fluid acceleration (incl. balance)
+  double a_ext[3];        // uniform fluid acceleration (incl. balance 1)
+  int bal_mode;           // 2: the acceleration is Counters::bal_a (device)
   double eps, delta_c;
   int n_c;
   double estar;           // effective modulus, eq. (5)
@@ -175,6 +180,7 @@ struct Ctx {
   int tcur;               // tab[tcur] = current contact list
   Counters* counters;     // device
   double* scratch;        // [ncell] FP64 staging for host conversions
+  double* bal_part = nullptr;  // per-block (mass, momentum) sums, balance mode 2
   // state
   bool particles_ready, fluid_ready;
   long long step;
@@ -205,6 +211,9 @@ hipError_t launch_detect(Ctx& c, PairTable to);
 hipError_t launch_lattice(Ctx& c, const void* src, void* dst);
 // momentum exchange over the collided populations fstar (force of the next step)
 hipError_t launch_mea(Ctx& c, const void* fstar);
+// balance mode 2: lattice mass and momentum of f at the start (init = 1), or
+// the controller update after a collision from the lattice pass's block sums
+hipError_t launch_balance(Ctx& c, const void* f, int init);
 hipError_t launch_treat(Ctx& c, PairTable t);
 hipError_t launch_fill_equilibrium(Ctx& c, void* f, double rho,
                                    const double u[3]);

@@ -141,6 +141,22 @@ __device__ void store_block(double (*red)[LCAP_MAX][6], const int* list,
   }
 }
 
+// Block sums of four per-lane values (widened to FP64): wavefront sums,
+// then the four wavefronts' rows added in fixed order by thread 0 and
+// stored at out[4 * block ..].  Every thread of the block must call it.
+__device__ void block_sums4(double a, double b, double c, double d,
+                            const BlockNode& nd, double* out) {
+  __shared__ double rows[4][4];
+  const double v[4] = {wave_sum(a), wave_sum(b), wave_sum(c), wave_sum(d)};
+  if (threadIdx.x % WAVE == 0)
+    for (int k = 0; k < 4; ++k) rows[nd.wave][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int k = threadIdx.x;
+    out[4 * nd.block + k] = ((rows[0][k] + rows[1][k]) + rows[2][k]) + rows[3][k];
+  }
+}
+
 // Offset of node (x, y, z) and the periodic / walled neighbour indices.
 struct Nbr {
   int xs[3], ys[3], zs[3];      // coordinates of x-1, x, x+1 etc. (wrapped)
@@ -188,7 +204,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                                                  S* __restrict__ dst,
                                                  const int* __restrict__ owner,
                                                  Particles P, Geom g, Phys ph,
-                                                 Counters* ctr) {
+                                                 Counters* ctr,
+                                                 double* __restrict__ bal_part) {
   using C = typename Store<S>::C;
   const BlockNode nd = block_node(g);
   const int x = nd.x, y = nd.y, z = nd.z;
@@ -274,9 +291,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     upy[1] = (C)U1 + (w2 * r0 - w0 * r2);
     upy[2] = (C)U2 + (w0 * r1 - w1 * r0);
   }
-  const C du0 = B * (upy[0] - u0) + (C)ph.a_ext[0];
-  const C du1 = B * (upy[1] - u1) + (C)ph.a_ext[1];
-  const C du2 = B * (upy[2] - u2) + (C)ph.a_ext[2];
+  // uniform fluid acceleration: fixed, or the zero-net-flux controller's
+  double ax = ph.a_ext[0], ay = ph.a_ext[1], az = ph.a_ext[2];
+  if (ph.bal_mode == 2) {
+    ax = ctr->bal_a[0];
+    ay = ctr->bal_a[1];
+    az = ctr->bal_a[2];
+  }
+  const C du0 = B * (upy[0] - u0) + (C)ax;
+  const C du1 = B * (upy[1] - u1) + (C)ay;
+  const C du2 = B * (upy[2] - u2) + (C)az;
   const C v0 = u0 + du0, v1 = u1 + du1, v2 = u2 + du2;
   const C uu = u0 * u0 + u1 * u1 + u2 * u2;
   const C vv = v0 * v0 + v1 * v1 + v2 * v2;
@@ -304,6 +328,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   if (valid) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) Store<S>::st(dst, i * n + self, f[i]);
+  }
+  if (ph.bal_mode == 2) {
+    // mass and momentum of the collided populations, per block in fixed
+    // order, for the zero-net-flux balance controller
+    C m = 0, j0 = 0, j1 = 0, j2 = 0;
+    if (valid) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        m += f[i];
+        if (cx(i)) j0 += cx(i) > 0 ? f[i] : -f[i];
+        if (cy(i)) j1 += cy(i) > 0 ? f[i] : -f[i];
+        if (cz(i)) j2 += cz(i) > 0 ? f[i] : -f[i];
+      }
+      if constexpr (Store<S>::shifted) m += (C)1;
+    }
+    block_sums4(m, j0, j1, j2, nd, bal_part);
   }
 }
 
@@ -387,6 +427,68 @@ __global__ __launch_bounds__(256) void k_mea(const S* __restrict__ fs,
   store_block(red, list, ent, cnt, g, tl.part);
 }
 
+// Mass and momentum of a population field, per lattice block (the initial
+// state of the zero-net-flux balance controller).
+template <typename S>
+__global__ __launch_bounds__(256) void k_pop_moments(const S* __restrict__ f, Geom g,
+                                                     double* __restrict__ out) {
+  using C = typename Store<S>::C;
+  const BlockNode nd = block_node(g);
+  const int n = (int)g.ncell;
+  double m = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
+  if (nd.valid) {
+    const int self = nd.x + g.nx * (nd.y + g.ny * nd.z);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double v = full_f<S>(Store<S>::ld(f, i * n + self), i);
+      m += v;
+      j0 += cx(i) * v;
+      j1 += cy(i) * v;
+      j2 += cz(i) * v;
+    }
+  }
+  block_sums4(m, j0, j1, j2, nd, out);
+}
+
+// Zero-net-flux balance controller (balance mode 2), one workgroup: the
+// block sums are added in fixed order (thread t takes blocks t, t + 256, ..,
+// then a fixed tree), giving the lattice mass M and momentum P.
+// init: M, P_{-1} = P, b_0 = -P / M.  Update after the collision of step t
+// (which used b_t): C_t = P_t - P_{t-1} - b_t M, b_{t+1} = -(P_t + C_t) / M.
+// The acceleration in use is a = fluid_accel + b.
+__global__ __launch_bounds__(256) void k_balance(const double* __restrict__ part,
+                                                 unsigned nblocks, Counters* ctr,
+                                                 Phys ph, int init) {
+  __shared__ double sh[256][4];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (unsigned b = threadIdx.x; b < nblocks; b += 256)
+    for (int k = 0; k < 4; ++k) acc[k] += part[4 * (size_t)b + k];
+  for (int k = 0; k < 4; ++k) sh[threadIdx.x][k] = acc[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int k = 0; k < 4; ++k) sh[threadIdx.x][k] += sh[threadIdx.x + w][k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (init) ctr->bal_M = sh[0][0];
+    const double M = ctr->bal_M;
+    for (int k = 0; k < 3; ++k) {
+      const double P = sh[0][1 + k];
+      double b;
+      if (init) {
+        b = -P / M;
+      } else {
+        const double Ct = P - ctr->bal_P[k] - ctr->bal_b[k] * M;
+        b = -(P + Ct) / M;
+      }
+      ctr->bal_b[k] = b;
+      ctr->bal_P[k] = P;
+      ctr->bal_a[k] = ph.a_ext[k] + b;
+    }
+  }
+}
+
 template <typename S>
 __global__ void k_fill_eq(S* f, size_t n, double rho, double u0, double u1,
                           double u2) {
@@ -451,7 +553,7 @@ template <typename S>
 static void run_lattice(Ctx& c, const void* src, void* dst) {
   hipLaunchKernelGGL(k_lattice<S>, dim3(tile_blocks(c.g)), dim3(256), 0,
                      c.stream, (const S*)src, (S*)dst, c.owner, c.part, c.g,
-                     c.ph, c.counters);
+                     c.ph, c.counters, c.bal_part);
 }
 
 hipError_t launch_lattice(Ctx& c, const void* src, void* dst) {
@@ -467,6 +569,19 @@ static void run_mea(Ctx& c, const void* fs) {
 
 hipError_t launch_mea(Ctx& c, const void* fstar) {
   DISPATCH(c, run_mea, (c, fstar));
+  return hipGetLastError();
+}
+
+template <typename S>
+static void run_pop_moments(Ctx& c, const void* f) {
+  hipLaunchKernelGGL(k_pop_moments<S>, dim3(tile_blocks(c.g)), dim3(256), 0,
+                     c.stream, (const S*)f, c.g, c.bal_part);
+}
+
+hipError_t launch_balance(Ctx& c, const void* f, int init) {
+  if (init) DISPATCH(c, run_pop_moments, (c, f));
+  hipLaunchKernelGGL(k_balance, dim3(1), dim3(256), 0, c.stream, c.bal_part,
+                     tile_blocks(c.g), c.counters, c.ph, init);
   return hipGetLastError();
 }
 

@@ -390,6 +390,43 @@ def c4_dense_spheres(seed: int = 3, L: int = 256, phi: float = 0.30,
                     f"{L}^3 periodic, {n} spheres D={dsph:.2f}, phi~{phi}, s=1.5, Ar=2000")
 
 
+def settling_box(shape: int, phi: float, n_per_d: float = 9.0,
+                 l_over_d: float = 12.0, ar: float = 1000.0, s: float = 3.3,
+                 tau: float = 0.55, seed: int = 11, precision: int = 1,
+                 edge_cells: Optional[int] = None,
+                 balance: int = 2) -> Workload:
+    """Periodic hindered-settling box of Sec. 5.1: spheres of diameter
+    D = n_per_d cells (or cubes of the same volume), edge L = l_over_d * D
+    (or edge_cells), n = phi L^3 / V_s particles at rest on a jittered,
+    thinned FCC lattice (cubes randomly oriented without overlap), density
+    ratio s (3.3 in the paper), gravity from the Archimedes number, balance
+    force on.  Dense cube boxes need an edge whose FCC cell count leaves the
+    cubes room to turn (e.g. L = 120 for D = 9 at phi = 0.3)."""
+    d = float(n_per_d)
+    L = int(edge_cells) if edge_cells else int(round(l_over_d * d))
+    vs = math.pi / 6.0 * d ** 3
+    n = max(1, int(round(phi * L ** 3 / vs)))
+    lu = lattice_units(d, s, ar, tau)
+    X = _dense_centres(seed, L, n, d)
+    if shape == SPHERE:
+        size = 0.5 * d
+        q = np.tile(np.array([1.0, 0.0, 0.0, 0.0]), (n, 1))
+    elif shape == CUBE:
+        size = d * (math.pi / 6.0) ** (1.0 / 3.0)
+        rng = np.random.default_rng(seed + 1000)
+        q = cube_orientations(rng, X, size, (L, L, L), (True, True, True))
+    else:
+        raise ValueError("settling boxes hold spheres or cubes")
+    sc = Scene(np.full(n, shape, np.int32), np.full(n, size), np.full(n, s), X,
+               q, np.zeros((n, 3)), np.zeros((n, 3)))
+    p = _base_params((L, L, L), 1, tau, lu, balance).replace(
+        max_pairs=max(1024, 8 * n), tile_capacity=48, precision=precision)
+    kind = "spheres" if shape == SPHERE else "cubes"
+    return Workload("settling", p, sc, 0,
+                    f"{L}^3 periodic, {n} {kind}, D={d:g} cells, phi~{phi}, "
+                    f"s={s}, Ar={ar:g}")
+
+
 def c5_adjoint_cubes(seed: int = 5) -> Workload:
     """96^3 periodic, 27 cubes a=10 on a jittered 3x3x3 grid, Ar 500."""
     a, s, ar, tau, L = 10.0, 1.5, 500.0, 0.55, 96
