@@ -15,7 +15,9 @@ Definitions (lattice units, fluid density 1, eta = nu):
       (eq. (23)), and k = 1 or k = 0.89 exp(-Ar / 1e5) (Yao et al., eq. (24));
   normalised time  t* = t D g (s - 1) / (18 nu)  (Sec. 5.1);
   the bulk velocity is the mean over particles of the velocity component
-      along gravity, averaged in time from t*_avg on (the paper: 50 of 400).
+      along gravity, averaged in time from t*_avg on (the paper: 50 of 400);
+  also reported against the Stokes velocity g D^2 (s - 1) / (18 nu), the
+      single-particle velocity with C_d = 24/Re.
 
     python -m paper_2401_10878_amd.settling --shape sphere cube --phi 0.1 0.3
 """
@@ -129,6 +131,7 @@ def settling_run(wl: W.Workload, t_end: float, t_avg: float,
     steps = int(math.ceil(t_end / dts))
     steps = sample_every * int(math.ceil(steps / sample_every))
     ustar = single_particle_velocity(g, d, s, nu)
+    ustokes = g * d * d * (s - 1.0) / (18.0 * nu)
     re = ustar * d / nu
     ar = g * d ** 3 * (s - 1.0) / (nu * nu)
     sim = hlbm.Simulation(p, sc, device=device, graph=graph)
@@ -150,8 +153,9 @@ def settling_run(wl: W.Workload, t_end: float, t_avg: float,
     k = k_yao(ar)
     return dict(
         n_particles=sc.n, lattice=[p.nx, p.ny, p.nz], d_cells=d, s=s,
-        ar=ar, re=re, u_star=ustar, steps=steps, t_end=steps * dts,
-        t_avg_from=t_avg, u_bar=ubar, u_bar_over_u_star=ubar / ustar,
+        ar=ar, re=re, u_star=ustar, u_stokes=ustokes, steps=steps,
+        t_end=steps * dts, t_avg_from=t_avg, u_bar=ubar,
+        u_bar_over_u_star=ubar / ustar, u_bar_over_u_stokes=ubar / ustokes,
         richardson_zaki=power_law(_phi(wl), 1.0, n_richardson_zaki(re)),
         garside_al_dibouni_yao=power_law(_phi(wl), k, n_garside_al_dibouni(re)),
         wall_s=wall, ms_per_step=1e3 * wall / steps,
@@ -209,13 +213,13 @@ def main(argv=None):
                 r.update(shape=shp, phi=round(_phi(wl), 4))
                 rows.append(r)
                 print(json.dumps(r), flush=True)
-    print("| Ar | phi | shape | n | u_bar/u* | RZ | GaD+Yao | ms/step |")
-    print("|---|---|---|---|---|---|---|---|")
+    print("| Ar | phi | shape | n | u_bar/u* | RZ | GaD+Yao | u_bar/u_Stokes | ms/step |")
+    print("|---|---|---|---|---|---|---|---|---|")
     for r in rows:
         print(f"| {r['ar']:.0f} | {r['phi']:.3f} | {r['shape']} | "
               f"{r['n_particles']} | {r['u_bar_over_u_star']:.3f} | "
               f"{r['richardson_zaki']:.3f} | {r['garside_al_dibouni_yao']:.3f} | "
-              f"{r['ms_per_step']:.3f} |")
+              f"{r['u_bar_over_u_stokes']:.3f} | {r['ms_per_step']:.3f} |")
     return 0
 
 
