@@ -137,6 +137,247 @@ static double octa_sdf_q(double a, const double q[3], double gq[3])
     return d;
 }
 
+/* ======================================================================
+ * Convex polyhedra (arbitrary convex bodies, Sec. 1 and Sec. 3.3: the
+ * method needs only a signed distance and its gradient).  A type is given
+ * by vertices and faces; the face planes n_f . p <= h_f follow from the
+ * face polygons (Newell's normal, offset through the face's vertex mean).
+ * ====================================================================== */
+static void cross(const double a[3], const double b[3], double out[3]);
+
+#define ORC_PV 64
+#define ORC_PF 64
+#define ORC_PFV 384
+#define ORC_PE 128
+
+typedef struct {
+    int nv, nf, ne;
+    double v[ORC_PV][3];
+    double n[ORC_PF][3], h[ORC_PF];
+    int fs[ORC_PF + 1], fv[ORC_PFV];
+    int e[ORC_PE][2];
+    double vol, J[9], rc;
+} orc_poly;
+
+static orc_poly g_poly[ORC_MAXPOLY];
+static int g_poly_ok[ORC_MAXPOLY];
+static char g_poly_err[160];
+
+const char *orc_poly_error(void) { return g_poly_err; }
+
+static int poly_fail(const char *msg)
+{
+    snprintf(g_poly_err, sizeof g_poly_err, "%s", msg);
+    return -1;
+}
+
+int orc_define_polyhedron(int type, int nv, const double *v, int nf,
+                          const int *fsize, const int *fidx)
+{
+    if (type < 0 || type >= ORC_MAXPOLY) return poly_fail("type out of range");
+    g_poly_ok[type] = 0;
+    if (nv < 4 || nv > ORC_PV || nf < 4 || nf > ORC_PF)
+        return poly_fail("vertex or face count out of range");
+    orc_poly P;
+    memset(&P, 0, sizeof P);
+    P.nv = nv;
+    P.nf = nf;
+    for (int i = 0; i < nv; ++i)
+        for (int k = 0; k < 3; ++k) P.v[i][k] = v[3 * i + k];
+    int m = 0;
+    for (int f = 0; f < nf; ++f) {
+        if (fsize[f] < 3) return poly_fail("face with fewer than 3 vertices");
+        P.fs[f] = m;
+        for (int j = 0; j < fsize[f]; ++j) {
+            if (m >= ORC_PFV) return poly_fail("too many face-vertex entries");
+            int a = fidx[m];
+            if (a < 0 || a >= nv) return poly_fail("face vertex index out of range");
+            P.fv[m++] = a;
+        }
+    }
+    P.fs[nf] = m;
+    /* closed, consistently oriented surface: every directed edge once, and
+       its reverse once; collect the undirected edges */
+    for (int f = 0; f < nf; ++f) {
+        int c = P.fs[f + 1] - P.fs[f];
+        for (int j = 0; j < c; ++j) {
+            int a = P.fv[P.fs[f] + j], b = P.fv[P.fs[f] + (j + 1) % c];
+            if (a == b) return poly_fail("repeated vertex in a face");
+            int same = 0, rev = 0;
+            for (int g = 0; g < nf; ++g) {
+                int cg = P.fs[g + 1] - P.fs[g];
+                for (int t = 0; t < cg; ++t) {
+                    int x = P.fv[P.fs[g] + t], y = P.fv[P.fs[g] + (t + 1) % cg];
+                    if (x == a && y == b) ++same;
+                    if (x == b && y == a) ++rev;
+                }
+            }
+            if (same != 1 || rev != 1) return poly_fail("surface not closed or not consistently oriented");
+            if (a < b) {
+                if (P.ne >= ORC_PE) return poly_fail("too many edges");
+                P.e[P.ne][0] = a;
+                P.e[P.ne][1] = b;
+                ++P.ne;
+            }
+        }
+    }
+    if (nv - P.ne + nf != 2) return poly_fail("Euler characteristic is not 2");
+    /* volume and centroid: tetrahedra (0, v0, v_j, v_{j+1}) of each face fan */
+    double vol = 0.0, cen[3] = {0.0, 0.0, 0.0};
+    for (int f = 0; f < nf; ++f) {
+        int c = P.fs[f + 1] - P.fs[f];
+        const double *a = P.v[P.fv[P.fs[f]]];
+        for (int j = 1; j + 1 < c; ++j) {
+            const double *b = P.v[P.fv[P.fs[f] + j]], *d = P.v[P.fv[P.fs[f] + j + 1]];
+            double t = (a[0] * (b[1] * d[2] - b[2] * d[1]) - a[1] * (b[0] * d[2] - b[2] * d[0]) +
+                        a[2] * (b[0] * d[1] - b[1] * d[0])) / 6.0;
+            vol += t;
+            for (int k = 0; k < 3; ++k) cen[k] += t * (a[k] + b[k] + d[k]) / 4.0;
+        }
+    }
+    if (!(vol > 0.0)) return poly_fail("faces must run counter-clockwise seen from outside");
+    for (int k = 0; k < 3; ++k) cen[k] /= vol;
+    for (int i = 0; i < nv; ++i)
+        for (int k = 0; k < 3; ++k) P.v[i][k] -= cen[k];
+    P.vol = vol;
+    /* second moment about the centroid: per tetrahedron with a vertex at the
+       origin, int p p^T = V/20 (sum_k v_k v_k^T + (sum v_k)(sum v_k)^T) */
+    for (int f = 0; f < nf; ++f) {
+        int c = P.fs[f + 1] - P.fs[f];
+        const double *a = P.v[P.fv[P.fs[f]]];
+        for (int j = 1; j + 1 < c; ++j) {
+            const double *b = P.v[P.fv[P.fs[f] + j]], *d = P.v[P.fv[P.fs[f] + j + 1]];
+            double t = (a[0] * (b[1] * d[2] - b[2] * d[1]) - a[1] * (b[0] * d[2] - b[2] * d[0]) +
+                        a[2] * (b[0] * d[1] - b[1] * d[0])) / 6.0;
+            for (int r = 0; r < 3; ++r)
+                for (int q = 0; q < 3; ++q) {
+                    double sv = a[r] + b[r] + d[r], sw = a[q] + b[q] + d[q];
+                    P.J[3 * r + q] += t / 20.0 *
+                        (a[r] * a[q] + b[r] * b[q] + d[r] * d[q] + sv * sw);
+                }
+        }
+    }
+    /* face planes */
+    double scale = 0.0;
+    for (int i = 0; i < nv; ++i) {
+        double r = sqrt(P.v[i][0] * P.v[i][0] + P.v[i][1] * P.v[i][1] + P.v[i][2] * P.v[i][2]);
+        if (r > scale) scale = r;
+    }
+    P.rc = scale;
+    for (int f = 0; f < nf; ++f) {
+        int c = P.fs[f + 1] - P.fs[f];
+        double nn[3] = {0.0, 0.0, 0.0}, mean[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j < c; ++j) {
+            const double *a = P.v[P.fv[P.fs[f] + j]], *b = P.v[P.fv[P.fs[f] + (j + 1) % c]];
+            nn[0] += (a[1] - b[1]) * (a[2] + b[2]);
+            nn[1] += (a[2] - b[2]) * (a[0] + b[0]);
+            nn[2] += (a[0] - b[0]) * (a[1] + b[1]);
+            for (int k = 0; k < 3; ++k) mean[k] += a[k] / c;
+        }
+        double len = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+        if (!(len > 0.0)) return poly_fail("degenerate face");
+        for (int k = 0; k < 3; ++k) P.n[f][k] = nn[k] / len;
+        P.h[f] = P.n[f][0] * mean[0] + P.n[f][1] * mean[1] + P.n[f][2] * mean[2];
+        /* planar face, every vertex on the inner side (convexity) */
+        for (int i = 0; i < nv; ++i) {
+            double s = P.n[f][0] * P.v[i][0] + P.n[f][1] * P.v[i][1] + P.n[f][2] * P.v[i][2] - P.h[f];
+            if (s > 1e-9 * scale) return poly_fail("not convex (a vertex lies outside a face plane)");
+        }
+        for (int j = 0; j < c; ++j) {
+            const double *a = P.v[P.fv[P.fs[f] + j]];
+            double s = P.n[f][0] * a[0] + P.n[f][1] * a[1] + P.n[f][2] * a[2] - P.h[f];
+            if (fabs(s) > 1e-9 * scale) return poly_fail("face not planar");
+        }
+    }
+    g_poly[type] = P;
+    g_poly_ok[type] = 1;
+    g_poly_err[0] = 0;
+    return 0;
+}
+
+int orc_poly_info(int type, double *vol, double J[9], double *rc, double *v)
+{
+    if (type < 0 || type >= ORC_MAXPOLY || !g_poly_ok[type]) return -1;
+    const orc_poly *P = &g_poly[type];
+    if (vol) *vol = P->vol;
+    if (J) for (int k = 0; k < 9; ++k) J[k] = P->J[k];
+    if (rc) *rc = P->rc;
+    if (v) for (int i = 0; i < P->nv; ++i) for (int k = 0; k < 3; ++k) v[3 * i + k] = P->v[i][k];
+    return 0;
+}
+
+/* Signed distance of the unit-scale polyhedron at body point p, and its
+   body-frame gradient gb.  Inside (every plane distance <= 0) the nearest
+   boundary point lies on the nearest face plane: d = max_f (n_f . p - h_f),
+   gradient n_f of the first maximal face.  Outside, the nearest point is in
+   the interior of a face whose plane the point is above (its projection
+   inside the face polygon), or on an edge; d is the smallest of those
+   candidate distances (first face, then edges in order, on ties). */
+static double poly_sdf_unit(const orc_poly *P, const double p[3], double gb[3])
+{
+    double best = -1e300;
+    int fm = 0;
+    double dist[ORC_PF];
+    for (int f = 0; f < P->nf; ++f) {
+        dist[f] = (P->n[f][0] * p[0] + P->n[f][1] * p[1]) + P->n[f][2] * p[2] - P->h[f];
+        if (dist[f] > best) {
+            best = dist[f];
+            fm = f;
+        }
+    }
+    if (best <= 0.0) {
+        if (gb) for (int k = 0; k < 3; ++k) gb[k] = P->n[fm][k];
+        return best;
+    }
+    double dmin2 = 1e300, cp[3] = {0.0, 0.0, 0.0};
+    int face_hit = -1;
+    for (int f = 0; f < P->nf; ++f) {
+        if (dist[f] <= 0.0) continue;
+        double q[3];
+        for (int k = 0; k < 3; ++k) q[k] = p[k] - dist[f] * P->n[f][k];
+        int c = P->fs[f + 1] - P->fs[f], inside = 1;
+        for (int j = 0; j < c && inside; ++j) {
+            const double *a = P->v[P->fv[P->fs[f] + j]], *b = P->v[P->fv[P->fs[f] + (j + 1) % c]];
+            double e[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+            double w[3] = {q[0] - a[0], q[1] - a[1], q[2] - a[2]};
+            double x[3];
+            cross(e, w, x);
+            if ((x[0] * P->n[f][0] + x[1] * P->n[f][1]) + x[2] * P->n[f][2] < 0.0) inside = 0;
+        }
+        if (inside && dist[f] * dist[f] < dmin2) {
+            dmin2 = dist[f] * dist[f];
+            face_hit = f;
+            for (int k = 0; k < 3; ++k) cp[k] = q[k];
+        }
+    }
+    for (int i = 0; i < P->ne; ++i) {
+        const double *a = P->v[P->e[i][0]], *b = P->v[P->e[i][1]];
+        double e[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+        double w[3] = {p[0] - a[0], p[1] - a[1], p[2] - a[2]};
+        double ee = (e[0] * e[0] + e[1] * e[1]) + e[2] * e[2];
+        double t = ((w[0] * e[0] + w[1] * e[1]) + w[2] * e[2]) / ee;
+        if (t < 0.0) t = 0.0;
+        if (t > 1.0) t = 1.0;
+        double c[3] = {a[0] + t * e[0], a[1] + t * e[1], a[2] + t * e[2]};
+        double dx = p[0] - c[0], dy = p[1] - c[1], dz = p[2] - c[2];
+        double d2 = (dx * dx + dy * dy) + dz * dz;
+        if (d2 < dmin2) {
+            dmin2 = d2;
+            face_hit = -1;
+            for (int k = 0; k < 3; ++k) cp[k] = c[k];
+        }
+    }
+    double d = sqrt(dmin2);
+    if (gb) {
+        if (face_hit >= 0) {
+            for (int k = 0; k < 3; ++k) gb[k] = P->n[face_hit][k];
+        } else {
+            for (int k = 0; k < 3; ++k) gb[k] = (p[k] - cp[k]) / d;
+        }
+    }
+    return d;
+}
+
 /* Exact Euclidean signed distance (negative inside) of a sphere (size =
    radius), cube (size = edge) or regular octahedron (size = centre-to-vertex
    distance) at world offset r from its centre.  The paper maps B from a
@@ -149,6 +390,18 @@ static double octa_sdf_q(double a, const double q[3], double gq[3])
 double orc_sdf(int shape, double size, const double R[9], const double r[3],
                double grad[3])
 {
+    if (shape >= ORC_POLY0) {
+        const orc_poly *P = &g_poly[shape - ORC_POLY0];
+        double p[3], gb[3];
+        for (int k = 0; k < 3; ++k)
+            p[k] = (R[0 + k] * r[0] + R[3 + k] * r[1] + R[6 + k] * r[2]) / size;
+        double d = size * poly_sdf_unit(P, p, grad ? gb : NULL);
+        if (grad)
+            for (int k = 0; k < 3; ++k)
+                grad[k] = R[3 * k + 0] * gb[0] + R[3 * k + 1] * gb[1] +
+                          R[3 * k + 2] * gb[2];
+        return d;
+    }
     if (shape == 2) {
         double p[3], q[3], gq[3];
         for (int k = 0; k < 3; ++k) {
@@ -238,9 +491,54 @@ static void cross(const double a[3], const double b[3], double out[3])
 static double volume_of(const orc_particle *p)
 {
     double a = p->size;
+    if (p->shape >= ORC_POLY0) return g_poly[p->shape - ORC_POLY0].vol * a * a * a;
     if (p->shape == 0) return 4.0 / 3.0 * M_PI * a * a * a;
     if (p->shape == 2) return 4.0 / 3.0 * a * a * a;   /* two pyramids */
     return a * a * a;
+}
+
+/* inverse body-frame inertia tensor of a homogeneous polyhedron of density
+   rho and scale s: I_b = rho s^5 (tr(J) 1 - J) with J the unit-scale second
+   moment about the centroid; the inverse by cofactors */
+static void poly_inv_inertia(const orc_particle *p, double Ii[9])
+{
+    const orc_poly *P = &g_poly[p->shape - ORC_POLY0];
+    double s2 = p->size * p->size, f = p->dens * s2 * s2 * p->size;
+    double tr = P->J[0] + P->J[4] + P->J[8], I[9];
+    for (int k = 0; k < 9; ++k) I[k] = f * ((k % 4 == 0 ? tr : 0.0) - P->J[k]);
+    double c0 = I[4] * I[8] - I[5] * I[7], c1 = I[5] * I[6] - I[3] * I[8],
+           c2 = I[3] * I[7] - I[4] * I[6];
+    double det = I[0] * c0 + I[1] * c1 + I[2] * c2;
+    Ii[0] = c0 / det;
+    Ii[1] = (I[2] * I[7] - I[1] * I[8]) / det;
+    Ii[2] = (I[1] * I[5] - I[2] * I[4]) / det;
+    Ii[3] = c1 / det;
+    Ii[4] = (I[0] * I[8] - I[2] * I[6]) / det;
+    Ii[5] = (I[2] * I[3] - I[0] * I[5]) / det;
+    Ii[6] = c2 / det;
+    Ii[7] = (I[1] * I[6] - I[0] * I[7]) / det;
+    Ii[8] = (I[0] * I[4] - I[1] * I[3]) / det;
+}
+
+/* angular acceleration of eq. (3) for a polyhedron particle under torque T
+   (world frame): R I_b^-1 R^T T (exposed for tests) */
+void orc_poly_angular_accel(int shape, double size, double dens,
+                            const double q[4], const double T[3], double dw[3])
+{
+    orc_particle p;
+    memset(&p, 0, sizeof p);
+    p.shape = shape;
+    p.size = size;
+    p.dens = dens;
+    double R[9], Ii[9], tb[3], wb[3];
+    orc_rotation(q, R);
+    poly_inv_inertia(&p, Ii);
+    for (int k = 0; k < 3; ++k)
+        tb[k] = (R[0 + k] * T[0] + R[3 + k] * T[1]) + R[6 + k] * T[2];
+    for (int k = 0; k < 3; ++k)
+        wb[k] = (Ii[3 * k] * tb[0] + Ii[3 * k + 1] * tb[1]) + Ii[3 * k + 2] * tb[2];
+    for (int k = 0; k < 3; ++k)
+        dw[k] = (R[3 * k] * wb[0] + R[3 * k + 1] * wb[1]) + R[3 * k + 2] * wb[2];
 }
 
 /* isotropic moment of inertia of a homogeneous sphere, cube or regular
@@ -339,6 +637,10 @@ orc_sim *orc_create(const orc_params *P, int np, const int *shape,
                     const double *size, const double *dens, const double *X,
                     const double *q, const double *U, const double *w)
 {
+    for (int i = 0; i < np; ++i)
+        if (shape[i] < 0 || (shape[i] >= ORC_POLY0 &&
+                             (shape[i] >= ORC_POLY0 + ORC_MAXPOLY || !g_poly_ok[shape[i] - ORC_POLY0])))
+            return NULL;
     orc_sim *S = (orc_sim *)calloc(1, sizeof(orc_sim));
     if (!S) return NULL;
     S->P = *P;
@@ -561,6 +863,16 @@ static int couple_and_detect_nodes(orc_sim *S)
             if (pp->shape == 1)
                 e = 0.5 * pp->size *
                     (fabs(R[3 * k]) + fabs(R[3 * k + 1]) + fabs(R[3 * k + 2]));
+            if (pp->shape >= ORC_POLY0) {
+                const orc_poly *Q = &g_poly[pp->shape - ORC_POLY0];
+                e = 0.0;
+                for (int i = 0; i < Q->nv; ++i) {
+                    double c = fabs((R[3 * k] * Q->v[i][0] + R[3 * k + 1] * Q->v[i][1]) +
+                                    R[3 * k + 2] * Q->v[i][2]);
+                    if (c > e) e = c;
+                }
+                e *= pp->size;
+            }
             reach[k] = e + margin;
         }
         int cnt[3];
@@ -1053,18 +1365,33 @@ static void move_particles(orc_sim *S, double dt)
         orc_particle *pp = &S->p[ip];
         double V = volume_of(pp);
         double m = pp->dens * V;
-        double I = inertia_of(pp, m);
+        double T[3];
         for (int k = 0; k < 3; ++k) {
             double Fg = (pp->dens - 1.0) * V * P->gravity[k];
             double F = S->Fh[3 * ip + k] + S->Fc[3 * ip + k] + Fg;
-            double T = S->Th[3 * ip + k] + S->Tc[3 * ip + k];
+            T[k] = S->Th[3 * ip + k] + S->Tc[3 * ip + k];
             pp->U[k] += F / m * dt;
             pp->X[k] += pp->U[k] * dt;
             if (per[k]) {
                 if (pp->X[k] >= (double)dims[k]) pp->X[k] -= (double)dims[k];
                 else if (pp->X[k] < 0.0) pp->X[k] += (double)dims[k];
             }
-            pp->w[k] += T / I * dt;
+        }
+        if (pp->shape >= ORC_POLY0) {
+            /* eq. (3) with the world-frame tensor I_w = R I_b R^T at the
+               current orientation: omega += R I_b^-1 R^T T dt */
+            double R[9], Ii[9], tb[3], wb[3];
+            orc_rotation(pp->q, R);
+            poly_inv_inertia(pp, Ii);
+            for (int k = 0; k < 3; ++k)
+                tb[k] = (R[0 + k] * T[0] + R[3 + k] * T[1]) + R[6 + k] * T[2];
+            for (int k = 0; k < 3; ++k)
+                wb[k] = (Ii[3 * k] * tb[0] + Ii[3 * k + 1] * tb[1]) + Ii[3 * k + 2] * tb[2];
+            for (int k = 0; k < 3; ++k)
+                pp->w[k] += ((R[3 * k] * wb[0] + R[3 * k + 1] * wb[1]) + R[3 * k + 2] * wb[2]) * dt;
+        } else {
+            double I = inertia_of(pp, m);
+            for (int k = 0; k < 3; ++k) pp->w[k] += T[k] / I * dt;
         }
         double th = sqrt(pp->w[0] * pp->w[0] + pp->w[1] * pp->w[1] +
                          pp->w[2] * pp->w[2]) * dt;

@@ -101,6 +101,25 @@ void orc_get_balance(const orc_sim *S, double *a_ext);
 void orc_feq(double rho, const double u[3], double out[ORC_Q]);
 void orc_lattice(int c[ORC_Q][3], double w[ORC_Q], int opp[ORC_Q]);
 void orc_rotation(const double q[4], double R[9]);
+/* Convex polyhedra: shapes ORC_POLY0 .. ORC_POLY0 + ORC_MAXPOLY - 1 refer to
+   polyhedron types defined here (before orc_create).  Vertices (nv x 3,
+   body frame) and faces (nf vertex lists, counter-clockwise seen from
+   outside, fsize[f] entries each, concatenated in fidx).  The solid is
+   re-centred at its centroid; a particle's size scales it uniformly.
+   Returns 0, or -1 with a message in orc_poly_error() when the input is
+   not a closed convex polyhedron within the capacities. */
+#define ORC_POLY0 3
+#define ORC_MAXPOLY 8
+int orc_define_polyhedron(int type, int nv, const double *v, int nf,
+                          const int *fsize, const int *fidx);
+const char *orc_poly_error(void);
+/* unit-scale volume, second moment J = int p p^T dV about the centroid,
+   circumradius, and the re-centred vertices (nv x 3) of a defined type */
+int orc_poly_info(int type, double *vol, double J[9], double *rc, double *v);
+/* R I_b^-1 R^T T for a polyhedron particle (eq. (3), world frame) */
+void orc_poly_angular_accel(int shape, double size, double dens,
+                            const double q[4], const double T[3], double dw[3]);
+
 double orc_sdf(int shape, double size, const double R[9], const double r[3],
                double grad[3]);
 double orc_weight(double d, double eps);

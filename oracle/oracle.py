@@ -102,6 +102,12 @@ def lib():
                                      P(OrcParticle), i, i, P(d), P(d),
                                      P(OrcContact)]
         L.orc_threads.restype = i
+        L.orc_define_polyhedron.argtypes = [i, i, P(d), i, P(i), P(i)]
+        L.orc_define_polyhedron.restype = i
+        L.orc_poly_error.restype = C.c_char_p
+        L.orc_poly_info.argtypes = [i, P(d), P(d), P(d), P(d)]
+        L.orc_poly_info.restype = i
+        L.orc_poly_angular_accel.argtypes = [i, d, d, P(d), P(d), P(d)]
         _lib = L
     return _lib
 
@@ -303,6 +309,41 @@ def sdf(shape, size, q, r, want_grad=False):
     g = np.empty(3)
     d = lib().orc_sdf(int(shape), float(size), _dp(R), _dp(rr), _dp(g))
     return (d, g) if want_grad else d
+
+
+POLY0 = 3
+
+
+def define_polyhedron(ptype, vertices, faces):
+    """Register convex polyhedron type ptype (shape code POLY0 + ptype):
+    vertices (n, 3), faces as vertex-index lists, counter-clockwise seen
+    from outside."""
+    v = np.ascontiguousarray(vertices, np.float64).reshape(-1)
+    fs = np.array([len(f) for f in faces], np.int32)
+    fi = np.array([k for f in faces for k in f], np.int32)
+    rc = lib().orc_define_polyhedron(int(ptype), v.size // 3, _dp(v), len(faces),
+                                     _ip(fs), _ip(fi))
+    if rc != 0:
+        raise ValueError(lib().orc_poly_error().decode())
+
+
+def polyhedron_info(ptype, nv):
+    """(unit volume, second moment J (3x3) about the centroid,
+    circumradius, re-centred vertices) of a defined type."""
+    vol, rc = np.zeros(1), np.zeros(1)
+    J, v = np.zeros(9), np.zeros(3 * nv)
+    if lib().orc_poly_info(int(ptype), _dp(vol), _dp(J), _dp(rc), _dp(v)) != 0:
+        raise ValueError("polyhedron type not defined")
+    return vol[0], J.reshape(3, 3), rc[0], v.reshape(nv, 3)
+
+
+def poly_angular_accel(shape, size, dens, q, T):
+    qq = np.ascontiguousarray(q, np.float64)
+    tt = np.ascontiguousarray(T, np.float64)
+    out = np.empty(3)
+    lib().orc_poly_angular_accel(int(shape), float(size), float(dens), _dp(qq),
+                                 _dp(tt), _dp(out))
+    return out
 
 
 def weight(d, eps=1.0):

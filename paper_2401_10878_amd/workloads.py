@@ -30,6 +30,7 @@ import numpy as np
 SPHERE = 0
 CUBE = 1
 OCTAHEDRON = 2         # size = centre-to-vertex distance
+POLY0 = 3              # shape POLY0 + k: convex polyhedron type k, size = scale
 
 # Physical constants of the hindered-settling set-up (Sec. 5.1, Sec. 2.3).
 D_S_PHYS = 1.5e-3          # m
@@ -135,6 +136,66 @@ def lattice_units(d_s_cells: float, s: float, ar: float, tau: float) -> dict:
 def cube_equiv_diameter(edge: float) -> float:
     """Diameter of the sphere with the volume of a cube of this edge."""
     return edge * (6.0 / math.pi) ** (1.0 / 3.0)
+
+
+# --------------------------------------------------------------------------
+# convex polyhedron geometries (vertices and faces, counter-clockwise seen
+# from outside); inputs only, the volume, inertia and distances are the
+# method's and live in the library and in the oracle
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class Polyhedron:
+    vertices: np.ndarray   # (nv, 3)
+    faces: list            # vertex-index lists
+
+
+def polyhedron_cuboid(a: float, b: float, c: float) -> Polyhedron:
+    """Box with edges a, b, c along x, y, z, centred at the origin."""
+    h = np.array([a, b, c]) / 2.0
+    v = np.array([[sx * h[0], sy * h[1], sz * h[2]]
+                  for sz in (-1, 1) for sy in (-1, 1) for sx in (-1, 1)])
+    # vertex k = ix + 2 iy + 4 iz with i = 0 for the negative side
+    faces = [[0, 2, 3, 1], [4, 5, 7, 6], [0, 1, 5, 4], [2, 6, 7, 3],
+             [0, 4, 6, 2], [1, 3, 7, 5]]
+    return Polyhedron(v, faces)
+
+
+def polyhedron_tetrahedron(edge: float = 1.0) -> Polyhedron:
+    """Regular tetrahedron on alternate corners of a cube."""
+    s = edge / (2.0 * math.sqrt(2.0))
+    v = s * np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float)
+    faces = [[0, 1, 2], [0, 3, 1], [0, 2, 3], [1, 3, 2]]
+    return Polyhedron(v, faces)
+
+
+def polyhedron_octahedron(a: float = 1.0) -> Polyhedron:
+    """Regular octahedron |x| + |y| + |z| <= a."""
+    v = a * np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0],
+                      [0, 0, 1], [0, 0, -1]], float)
+    faces = [[0, 2, 4], [2, 1, 4], [1, 3, 4], [3, 0, 4],
+             [2, 0, 5], [1, 2, 5], [3, 1, 5], [0, 3, 5]]
+    return Polyhedron(v, faces)
+
+
+def polyhedron_random(rng: np.random.Generator, npts: int = 12,
+                      stretch=(1.0, 0.8, 0.6)) -> Polyhedron:
+    """Convex hull of random points on a stretched sphere, triangulated,
+    each triangle ordered counter-clockwise seen from outside."""
+    from scipy.spatial import ConvexHull
+    p = rng.normal(size=(npts, 3))
+    p /= np.linalg.norm(p, axis=1)[:, None]
+    p *= np.asarray(stretch)[None, :]
+    hull = ConvexHull(p)
+    used = np.unique(hull.simplices)
+    remap = -np.ones(npts, int)
+    remap[used] = np.arange(used.size)
+    faces = []
+    for tri, eq in zip(hull.simplices, hull.equations):
+        a, b, c = p[tri]
+        if np.dot(np.cross(b - a, c - a), eq[:3]) < 0:
+            tri = tri[[0, 2, 1]]
+        faces.append([int(remap[k]) for k in tri])
+    return Polyhedron(p[used], faces)
 
 
 # --------------------------------------------------------------------------
