@@ -65,8 +65,11 @@ typedef enum {
 } hlbm_precision;
 
 /* Convex bodies with exact signed distances; size is the radius (sphere),
-   the edge (cube) or the centre-to-vertex distance (regular octahedron). */
-typedef enum { HLBM_SPHERE = 0, HLBM_CUBE = 1, HLBM_OCTAHEDRON = 2 } hlbm_shape;
+   the edge (cube), the centre-to-vertex distance (regular octahedron), or
+   the scale factor of a convex polyhedron type k defined with
+   hlbm_define_polyhedron (shape HLBM_POLYHEDRON0 + k, k < 8). */
+typedef enum { HLBM_SPHERE = 0, HLBM_CUBE = 1, HLBM_OCTAHEDRON = 2,
+               HLBM_POLYHEDRON0 = 3 } hlbm_shape;
 
 typedef struct {
     int nx, ny, nz;             /* lattice nodes per axis */
@@ -131,8 +134,27 @@ hlbm_status hlbm_create(const hlbm_params *params, void *stream,
 hlbm_status hlbm_bind_populations(hlbm_ctx *ctx, void *dev_a, void *dev_b,
                                   size_t bytes);
 
+/* Define convex polyhedron type `type` (0..7; particles of shape
+   HLBM_POLYHEDRON0 + type) from nv vertices (host, nv x 3, FP64) and nf
+   faces, face f listing fsize[f] vertex indices counter-clockwise seen from
+   outside, all lists concatenated in fidx.  At most 64 vertices, 64 faces,
+   384 face-vertex entries and 128 edges.  The surface must be closed,
+   consistently oriented, planar-faced and convex (HLBM_E_ARG otherwise).
+   The solid is re-centred at its centroid (the particle's X is its centre
+   of mass); a particle's size scales it uniformly.  Signed distances are
+   exact (the nearest face plane inside; face interiors, edges and vertices
+   outside, the method needs only a signed distance and its gradient, Sec.
+   3.3).  Particle motion follows eq. (3) with the world-frame inertia
+   tensor R I_b R^T of the homogeneous solid.  Call before
+   hlbm_init_particles (HLBM_E_STATE after).  Polyhedra are not supported
+   by the adjoint. */
+hlbm_status hlbm_define_polyhedron(hlbm_ctx *ctx, int type, int nv,
+                                   const double *v, int nf, const int *fsize,
+                                   const int *fidx);
+
 /* Upload n particles (host arrays).  shape: hlbm_shape; size = radius
-   (sphere), edge (cube) or centre-to-vertex distance (octahedron);
+   (sphere), edge (cube), centre-to-vertex distance (octahedron) or scale
+   (polyhedron);
    density = particle/fluid density ratio.  Positions on periodic axes are
    wrapped into [0, n).  Periodic axes must exceed twice the particle reach
    (circumradius + detection margin). */

@@ -46,7 +46,35 @@ int next_pow2(long long v) {
 
 // reach beyond the body used for tile binning (must match k_particles)
 double margin_of(const Ctx& c) {
-  return fmax(0.5 * c.ph.eps + 1.4142135623730951, DETECT + c.ph.delta_c) + 0.25;
+  return fmax(0.5 * c.ph.eps, DETECT + c.ph.delta_c) + 0.25;
+}
+
+// circumradius of a particle of the given shape and size
+double circumradius(const Ctx& c, int shape, double size) {
+  if (shape >= POLY0) return size * c.poly_host[shape - POLY0].dev.rc;
+  return shape == 1 ? 0.5 * size * sqrt(3.0) : size;
+}
+
+// Inverse body inertia tensor of a homogeneous polyhedron of density ratio
+// dens and scale s: I_b = dens s^5 (tr(J) 1 - J) with J the unit-scale second
+// moment about the centroid (eq. (3)), inverted by cofactors.
+void poly_inverse_inertia(const Ctx::PolyHost& P, double s, double dens, double* Ii) {
+  const double s2 = s * s, f = dens * s2 * s2 * s;
+  const double tr = P.J[0] + P.J[4] + P.J[8];
+  double I[9];
+  for (int k = 0; k < 9; ++k) I[k] = f * ((k % 4 == 0 ? tr : 0.0) - P.J[k]);
+  const double c0 = I[4] * I[8] - I[5] * I[7], c1 = I[5] * I[6] - I[3] * I[8],
+               c2 = I[3] * I[7] - I[4] * I[6];
+  const double det = I[0] * c0 + I[1] * c1 + I[2] * c2;
+  Ii[0] = c0 / det;
+  Ii[1] = (I[2] * I[7] - I[1] * I[8]) / det;
+  Ii[2] = (I[1] * I[5] - I[2] * I[4]) / det;
+  Ii[3] = c1 / det;
+  Ii[4] = (I[0] * I[8] - I[2] * I[6]) / det;
+  Ii[5] = (I[2] * I[3] - I[0] * I[5]) / det;
+  Ii[6] = c2 / det;
+  Ii[7] = (I[1] * I[6] - I[0] * I[7]) / det;
+  Ii[8] = (I[0] * I[4] - I[1] * I[3]) / det;
 }
 
 hlbm_status check_flags(Ctx& c) {
@@ -376,6 +404,146 @@ hlbm_status hlbm_bind_populations(hlbm_ctx* h, void* a, void* b, size_t bytes) {
   return HLBM_OK;
 }
 
+// A convex polyhedron type from vertices and faces (counter-clockwise seen
+// from outside).  Checks a closed, consistently oriented surface (each
+// directed edge once, its reverse once, V - E + F = 2), positive volume,
+// planar faces and convexity; re-centres the solid at its centroid
+// (tetrahedra of each face fan with the origin) and takes its second moment
+// J = int p p^T dV there (per tetrahedron V/20 (sum v v^T + (sum v)(sum v)^T)).
+// Face planes: Newell's normal through the face's vertex mean.
+hlbm_status hlbm_define_polyhedron(hlbm_ctx* h, int type, int nv, const double* v,
+                                   int nf, const int* fsize, const int* fidx) {
+  if (!h) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (c.particles_ready)
+    return fail(c, HLBM_E_STATE, "define polyhedra before init_particles");
+  if (type < 0 || type >= MAXPOLY) return fail(c, HLBM_E_ARG, "polyhedron type must be 0..%d", MAXPOLY - 1);
+  if (!v || !fsize || !fidx || nv < 4 || nv > PV || nf < 4 || nf > PF)
+    return fail(c, HLBM_E_ARG, "polyhedron: 4..%d vertices and 4..%d faces", PV, PF);
+  Ctx::PolyHost P;
+  PolyDev& D = P.dev;
+  memset(&D, 0, sizeof D);
+  D.nv = nv;
+  D.nf = nf;
+  for (int i = 0; i < nv; ++i)
+    for (int k = 0; k < 3; ++k) {
+      if (!isfinite(v[3 * i + k])) return fail(c, HLBM_E_ARG, "polyhedron: non-finite vertex");
+      D.v[i][k] = v[3 * i + k];
+    }
+  int m = 0;
+  for (int f = 0; f < nf; ++f) {
+    if (fsize[f] < 3) return fail(c, HLBM_E_ARG, "polyhedron: face %d has fewer than 3 vertices", f);
+    D.fs[f] = m;
+    for (int j = 0; j < fsize[f]; ++j) {
+      if (m >= PFV) return fail(c, HLBM_E_ARG, "polyhedron: more than %d face-vertex entries", PFV);
+      if (fidx[m] < 0 || fidx[m] >= nv) return fail(c, HLBM_E_ARG, "polyhedron: vertex index out of range");
+      D.fv[m] = fidx[m];
+      ++m;
+    }
+  }
+  D.fs[nf] = m;
+  auto fvert = [&](int f, int j) {
+    const int cnt = D.fs[f + 1] - D.fs[f];
+    return D.fv[D.fs[f] + j % cnt];
+  };
+  for (int f = 0; f < nf; ++f) {
+    const int cnt = D.fs[f + 1] - D.fs[f];
+    for (int j = 0; j < cnt; ++j) {
+      const int a = fvert(f, j), b = fvert(f, j + 1);
+      if (a == b) return fail(c, HLBM_E_ARG, "polyhedron: repeated vertex in face %d", f);
+      int same = 0, rev = 0;
+      for (int g = 0; g < nf; ++g) {
+        const int cg = D.fs[g + 1] - D.fs[g];
+        for (int t = 0; t < cg; ++t) {
+          const int x = fvert(g, t), y = fvert(g, t + 1);
+          same += (x == a && y == b);
+          rev += (x == b && y == a);
+        }
+      }
+      if (same != 1 || rev != 1)
+        return fail(c, HLBM_E_ARG, "polyhedron: surface not closed or not consistently oriented");
+      if (a < b) {
+        if (D.ne >= PE) return fail(c, HLBM_E_ARG, "polyhedron: more than %d edges", PE);
+        D.e[D.ne][0] = a;
+        D.e[D.ne][1] = b;
+        ++D.ne;
+      }
+    }
+  }
+  if (nv - D.ne + nf != 2) return fail(c, HLBM_E_ARG, "polyhedron: Euler characteristic is not 2");
+  // signed volume of the tetrahedron (0, a, b, d)
+  auto tet = [](const double* a, const double* b, const double* d) {
+    return (a[0] * (b[1] * d[2] - b[2] * d[1]) - a[1] * (b[0] * d[2] - b[2] * d[0]) +
+            a[2] * (b[0] * d[1] - b[1] * d[0])) / 6.0;
+  };
+  double vol = 0.0, cen[3] = {0.0, 0.0, 0.0};
+  for (int f = 0; f < nf; ++f) {
+    const int cnt = D.fs[f + 1] - D.fs[f];
+    const double* a = D.v[fvert(f, 0)];
+    for (int j = 1; j + 1 < cnt; ++j) {
+      const double *b = D.v[fvert(f, j)], *d = D.v[fvert(f, j + 1)];
+      const double t = tet(a, b, d);
+      vol += t;
+      for (int k = 0; k < 3; ++k) cen[k] += t * (a[k] + b[k] + d[k]) / 4.0;
+    }
+  }
+  if (!(vol > 0.0))
+    return fail(c, HLBM_E_ARG, "polyhedron: faces must run counter-clockwise seen from outside");
+  for (int k = 0; k < 3; ++k) cen[k] /= vol;
+  for (int i = 0; i < nv; ++i)
+    for (int k = 0; k < 3; ++k) D.v[i][k] -= cen[k];
+  P.vol = vol;
+  for (int f = 0; f < nf; ++f) {
+    const int cnt = D.fs[f + 1] - D.fs[f];
+    const double* a = D.v[fvert(f, 0)];
+    for (int j = 1; j + 1 < cnt; ++j) {
+      const double *b = D.v[fvert(f, j)], *d = D.v[fvert(f, j + 1)];
+      const double t = tet(a, b, d);
+      for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) {
+          const double sv = a[r] + b[r] + d[r], sw = a[q] + b[q] + d[q];
+          P.J[3 * r + q] += t / 20.0 * (a[r] * a[q] + b[r] * b[q] + d[r] * d[q] + sv * sw);
+        }
+    }
+  }
+  double scale = 0.0;
+  for (int i = 0; i < nv; ++i) {
+    const double r = sqrt(D.v[i][0] * D.v[i][0] + D.v[i][1] * D.v[i][1] + D.v[i][2] * D.v[i][2]);
+    scale = r > scale ? r : scale;
+  }
+  D.rc = scale;
+  for (int f = 0; f < nf; ++f) {
+    const int cnt = D.fs[f + 1] - D.fs[f];
+    double nn[3] = {0.0, 0.0, 0.0}, mean[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < cnt; ++j) {
+      const double *a = D.v[fvert(f, j)], *b = D.v[fvert(f, j + 1)];
+      nn[0] += (a[1] - b[1]) * (a[2] + b[2]);
+      nn[1] += (a[2] - b[2]) * (a[0] + b[0]);
+      nn[2] += (a[0] - b[0]) * (a[1] + b[1]);
+      for (int k = 0; k < 3; ++k) mean[k] += a[k] / cnt;
+    }
+    const double len = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+    if (!(len > 0.0)) return fail(c, HLBM_E_ARG, "polyhedron: degenerate face %d", f);
+    for (int k = 0; k < 3; ++k) D.pl[f][k] = nn[k] / len;
+    D.pl[f][3] = D.pl[f][0] * mean[0] + D.pl[f][1] * mean[1] + D.pl[f][2] * mean[2];
+    for (int i = 0; i < nv; ++i) {
+      const double sd = D.pl[f][0] * D.v[i][0] + D.pl[f][1] * D.v[i][1] + D.pl[f][2] * D.v[i][2] - D.pl[f][3];
+      if (sd > 1e-9 * scale)
+        return fail(c, HLBM_E_ARG, "polyhedron: not convex (a vertex lies outside face %d)", f);
+    }
+    for (int j = 0; j < cnt; ++j) {
+      const double* a = D.v[fvert(f, j)];
+      const double sd = D.pl[f][0] * a[0] + D.pl[f][1] * a[1] + D.pl[f][2] * a[2] - D.pl[f][3];
+      if (fabs(sd) > 1e-9 * scale) return fail(c, HLBM_E_ARG, "polyhedron: face %d not planar", f);
+    }
+  }
+  P.ok = true;
+  if (!c.poly_dev) HIPCHECK(hipMalloc(&c.poly_dev, sizeof(PolyDev) * MAXPOLY));
+  HIPCHECK(hipMemcpy(c.poly_dev + type, &D, sizeof(PolyDev), hipMemcpyHostToDevice));
+  c.poly_host[type] = P;
+  return HLBM_OK;
+}
+
 hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const double* size,
                                 const double* density, const double* X, const double* q,
                                 const double* U, const double* omega) {
@@ -388,17 +556,20 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
   const double margin = margin_of(c);
   std::vector<int> sh(n > 0 ? n : 1);
   std::vector<double> sz(n), ds(n), vol(n), mass(n), inert(n), Xh(3 * n), qh(4 * n),
-      Uh(3 * n), Wh(3 * n);
+      Uh(3 * n), Wh(3 * n), iinv(9 * (size_t)n, 0.0);
   for (int i = 0; i < n; ++i) {
-    if (shape[i] < 0 || shape[i] > 2)
+    const bool poly = shape[i] >= POLY0 && shape[i] < POLY0 + MAXPOLY &&
+                      c.poly_host[shape[i] - POLY0].ok;
+    if (!poly && (shape[i] < 0 || shape[i] > 2))
       return fail(c, HLBM_E_ARG,
-                  "particle %d: shape must be 0 (sphere), 1 (cube) or 2 (octahedron)", i);
+                  "particle %d: shape must be 0 (sphere), 1 (cube), 2 (octahedron) or a "
+                  "defined polyhedron type (3 + k)", i);
     if (!(size[i] > 0.0) || !(density[i] > 0.0) || !isfinite(size[i]) || !isfinite(density[i]))
       return fail(c, HLBM_E_ARG, "particle %d: size and density must be positive", i);
     sh[i] = shape[i];
     sz[i] = size[i];
     ds[i] = density[i];
-    const double circ = shape[i] == 1 ? 0.5 * size[i] * sqrt(3.0) : size[i];
+    const double circ = circumradius(c, shape[i], size[i]);
     for (int k = 0; k < 3; ++k) {
       if (per[k] && !(L[k] > 2.0 * (circ + margin)))
         return fail(c, HLBM_E_ARG,
@@ -425,7 +596,16 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
       for (int k = 0; k < 4; ++k) qh[4 * i + k] = q[4 * i + k] / sqrt(nq);
     // volume and (isotropic) moment of inertia: sphere 4 pi a^3 / 3,
     // 2 m a^2 / 5; cube a^3, m a^2 / 6; octahedron 4 a^3 / 3, m a^2 / 5
+    // polyhedra: V = V_1 s^3 and the inverse inertia tensor (eq. (3))
     const double a = size[i];
+    if (poly) {
+      const Ctx::PolyHost& P = c.poly_host[shape[i] - POLY0];
+      vol[i] = P.vol * a * a * a;
+      mass[i] = density[i] * vol[i];
+      inert[i] = 1.0;
+      poly_inverse_inertia(P, a, density[i], &iinv[9 * (size_t)i]);
+      continue;
+    }
     vol[i] = shape[i] == 0 ? 4.0 / 3.0 * PI * a * a * a
                            : (shape[i] == 2 ? 4.0 / 3.0 * a * a * a : a * a * a);
     mass[i] = density[i] * vol[i];
@@ -437,8 +617,9 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
   const size_t nn = n > 0 ? n : 1;
   // layout of the one particle allocation (doubles, then ints)
   // 5 scalars, X 3, q 4, U 3, W 3, R 9, Fh 3, Th 3, Fc 3, Tc 3
-  // (plus 6 doubles' room for the 12 FP32 screening values)
-  const size_t nd = nn * (5 + 3 + 4 + 3 + 3 + 9 + 3 + 3 + 3 + 3 + 6);
+  // (plus 6 doubles' room for the 12 FP32 screening values), inverse
+  // inertia 9
+  const size_t nd = nn * (5 + 3 + 4 + 3 + 3 + 9 + 3 + 3 + 3 + 3 + 6 + 9);
   const size_t bytes = nd * sizeof(double) + nn * sizeof(int);
   c.part_bytes = bytes;
   HIPCHECK(hipMalloc(&c.part_block, bytes));
@@ -452,6 +633,11 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
   c.part.XR32 = (float*)take(6);
   c.Fh = take(3); c.Th = take(3);
   c.Fc = take(3); c.Tc = take(3);
+  double* diinv = take(9);
+  c.part.Iinv = diinv;
+  c.part.poly = c.poly_dev;
+  c.has_poly = false;
+  for (int i = 0; i < n; ++i) c.has_poly = c.has_poly || sh[i] >= POLY0;
   int* dsh = (int*)d;
   c.part.n = n;
   c.part.shape = dsh; c.part.size = dsz; c.part.dens = dds; c.part.vol = dvol;
@@ -461,7 +647,7 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
   {
     double emax = 0.0;
     for (int i = 0; i < n; ++i)
-      emax = fmax(emax, sh[i] == 1 ? 0.5 * sz[i] * sqrt(3.0) : sz[i]);
+      emax = fmax(emax, circumradius(c, sh[i], sz[i]));
     const double span = 2.0 * (emax + margin) + 3.0;
     const int ts[3] = {LX, LY, LZ}, nt[3] = {c.g.ltx, c.g.lty, c.g.ltz};
     long long me = 1;
@@ -494,6 +680,7 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
     HIPCHECK(hipMemcpyAsync(dvol, vol.data(), sizeof(double) * n, hipMemcpyHostToDevice, c.stream));
     HIPCHECK(hipMemcpyAsync(dmass, mass.data(), sizeof(double) * n, hipMemcpyHostToDevice, c.stream));
     HIPCHECK(hipMemcpyAsync(dinert, inert.data(), sizeof(double) * n, hipMemcpyHostToDevice, c.stream));
+    HIPCHECK(hipMemcpyAsync(diinv, iinv.data(), sizeof(double) * 9 * n, hipMemcpyHostToDevice, c.stream));
     HIPCHECK(hipMemcpyAsync(c.part.X, Xh.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c.stream));
     HIPCHECK(hipMemcpyAsync(c.part.q, qh.data(), sizeof(double) * 4 * n, hipMemcpyHostToDevice, c.stream));
     HIPCHECK(hipMemcpyAsync(c.part.U, Uh.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c.stream));
@@ -945,6 +1132,15 @@ hlbm_status hlbm_adjoint_record(hlbm_ctx* h, int ksteps, int ckpt_every) {
   if (c.n_sub != 1) return fail(c, HLBM_E_ARG, "the adjoint runs without contact sub-steps");
   if (c.ph.bal_mode == 2)
     return fail(c, HLBM_E_ARG, "the adjoint supports balance modes 0 and 1 only");
+  {
+    std::vector<int> sh(c.np > 0 ? c.np : 1);
+    if (c.np > 0) {
+      HIPCHECK(hipMemcpy(sh.data(), c.part.shape, sizeof(int) * c.np, hipMemcpyDeviceToHost));
+      for (int i = 0; i < c.np; ++i)
+        if (sh[i] >= POLY0)
+          return fail(c, HLBM_E_ARG, "the adjoint supports spheres, cubes and octahedra only");
+    }
+  }
   if (c.timing) return fail(c, HLBM_E_STATE, "finish the timing window first");
   if (ksteps < 1 || ckpt_every < 1)
     return fail(c, HLBM_E_ARG, "ksteps and ckpt_every must be >= 1");
@@ -1087,6 +1283,7 @@ void hlbm_destroy(hlbm_ctx* h) {
   if (c.tile_block) hipFree(c.tile_block);
   if (c.counters) hipFree(c.counters);
   if (c.bal_part) hipFree(c.bal_part);
+  if (c.poly_dev) hipFree(c.poly_dev);
   if (c.scratch) hipFree(c.scratch);
   for (int k = 0; k < 2; ++k) {
     if (c.tab[k].keys) hipFree(c.tab[k].keys);

@@ -177,6 +177,15 @@ struct Ctx {
   void* part_sums;        // allocation holding nent, part, ovf
   // contacts
   PairTable tab[2];
+  // convex polyhedron types: host records (volume, second moment about the
+  // centroid, circumradius at unit scale) and the device table
+  struct PolyHost {
+    bool ok = false;
+    PolyDev dev;
+    double vol = 0.0, J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  } poly_host[MAXPOLY];
+  PolyDev* poly_dev = nullptr;
+  bool has_poly = false;  // some particle is a polyhedron: kernels with that path
   int tcur;               // tab[tcur] = current contact list
   Counters* counters;     // device
   double* scratch;        // [ncell] FP64 staging for host conversions

@@ -54,10 +54,26 @@ __host__ __device__ constexpr double wgt(int i) {
 }
 
 // Particle record in device memory (structure of arrays, FP64).
+// Convex polyhedron type (shape POLY0 + k): vertices re-centred at the
+// solid's centroid, face planes n . p <= h (n, h per face), face vertex
+// lists (fs[f] .. fs[f+1] into fv, counter-clockwise seen from outside),
+// undirected edges, circumradius; all at unit scale.
+constexpr int POLY0 = 3, MAXPOLY = 8;
+constexpr int PV = 64, PF = 64, PFV = 384, PE = 128;
+struct PolyDev {
+  int nv, nf, ne, pad;
+  double rc;
+  double v[PV][3];
+  double pl[PF][4];
+  int fs[PF + 1];
+  int fv[PFV];
+  int e[PE][2];
+};
+
 struct Particles {
   int n;
-  const int* shape;     // 0 sphere, 1 cube
-  const double* size;   // radius or edge
+  const int* shape;     // 0 sphere, 1 cube, 2 octahedron, POLY0 + k polyhedron
+  const double* size;   // radius, edge, vertex distance or scale
   const double* dens;   // density ratio s
   const double* vol;    // volume
   const double* mass;   // s * V
@@ -68,6 +84,8 @@ struct Particles {
   double* W;            // [n][3] angular velocity
   double* R;            // [n][9] rotation (body -> world), row-major
   float* XR32;          // [n][12] X (3) and R (9) rounded to FP32, for screening
+  const double* Iinv;   // [n][9] inverse body inertia tensor (polyhedra)
+  const PolyDev* poly;  // [MAXPOLY] polyhedron types
 };
 
 // Rotation matrix of q = (w, x, y, z).
@@ -159,11 +177,106 @@ __device__ inline T octa_q(T a, T q0, T q1, T q2) {
   return octa_q<T>(a, q0, q1, q2, g0, g1, g2);
 }
 
+// Signed distance of a unit-scale polyhedron at body point p (T = double or
+// float) and, if gb is given, its body-frame gradient.  Inside (every plane
+// distance <= 0): the largest plane distance, gradient the normal of the
+// first face attaining it.  Outside: the smallest of the distances to face
+// interiors (faces the point is above whose polygon contains its
+// projection) and to the edges, first face then edges in order on ties;
+// gradient the face normal or (p - closest point) / d.  With far < inf an
+// outside point whose largest plane distance exceeds far returns that
+// lower bound (screening: such a point is beyond every threshold).
+template <typename T>
+__device__ inline T poly_sdf_unit(const PolyDev* P, const T* p, T* gb, T far) {
+  const int nf = P->nf;
+  T best = (T)-1e30;
+  int fm = 0;
+  for (int f = 0; f < nf; ++f) {
+    const double* pl = P->pl[f];
+    const T d = ((T)pl[0] * p[0] + (T)pl[1] * p[1]) + (T)pl[2] * p[2] - (T)pl[3];
+    if (d > best) {
+      best = d;
+      fm = f;
+    }
+  }
+  if (best <= (T)0) {
+    if (gb)
+      for (int k = 0; k < 3; ++k) gb[k] = (T)P->pl[fm][k];
+    return best;
+  }
+  if (best > far) return best;
+  T dmin2 = (T)1e30, c0 = (T)0, c1 = (T)0, c2 = (T)0;
+  int face_hit = -1;
+  for (int f = 0; f < nf; ++f) {
+    const double* pl = P->pl[f];
+    const T n0 = (T)pl[0], n1 = (T)pl[1], n2 = (T)pl[2];
+    const T d = (n0 * p[0] + n1 * p[1]) + n2 * p[2] - (T)pl[3];
+    if (d <= (T)0) continue;
+    const T q0 = p[0] - d * n0, q1 = p[1] - d * n1, q2 = p[2] - d * n2;
+    const int b0 = P->fs[f], cnt = P->fs[f + 1] - b0;
+    bool inside = true;
+    for (int j = 0; j < cnt && inside; ++j) {
+      const double* a = P->v[P->fv[b0 + j]];
+      const double* b = P->v[P->fv[b0 + (j + 1 == cnt ? 0 : j + 1)]];
+      const T e0 = (T)b[0] - (T)a[0], e1 = (T)b[1] - (T)a[1], e2 = (T)b[2] - (T)a[2];
+      const T w0 = q0 - (T)a[0], w1 = q1 - (T)a[1], w2 = q2 - (T)a[2];
+      const T x0 = e1 * w2 - e2 * w1, x1 = e2 * w0 - e0 * w2, x2 = e0 * w1 - e1 * w0;
+      if ((x0 * n0 + x1 * n1) + x2 * n2 < (T)0) inside = false;
+    }
+    if (inside && d * d < dmin2) {
+      dmin2 = d * d;
+      face_hit = f;
+      c0 = q0;
+      c1 = q1;
+      c2 = q2;
+    }
+  }
+  const int ne = P->ne;
+  for (int i = 0; i < ne; ++i) {
+    const double* a = P->v[P->e[i][0]];
+    const double* b = P->v[P->e[i][1]];
+    const T e0 = (T)b[0] - (T)a[0], e1 = (T)b[1] - (T)a[1], e2 = (T)b[2] - (T)a[2];
+    const T w0 = p[0] - (T)a[0], w1 = p[1] - (T)a[1], w2 = p[2] - (T)a[2];
+    const T ee = (e0 * e0 + e1 * e1) + e2 * e2;
+    T t = ((w0 * e0 + w1 * e1) + w2 * e2) / ee;
+    t = t < (T)0 ? (T)0 : (t > (T)1 ? (T)1 : t);
+    const T x0 = (T)a[0] + t * e0, x1 = (T)a[1] + t * e1, x2 = (T)a[2] + t * e2;
+    const T dx = p[0] - x0, dy = p[1] - x1, dz = p[2] - x2;
+    const T d2 = (dx * dx + dy * dy) + dz * dz;
+    if (d2 < dmin2) {
+      dmin2 = d2;
+      face_hit = -1;
+      c0 = x0;
+      c1 = x1;
+      c2 = x2;
+    }
+  }
+  const T d = sqrt(dmin2);
+  if (gb) {
+    if (face_hit >= 0) {
+      for (int k = 0; k < 3; ++k) gb[k] = (T)P->pl[face_hit][k];
+    } else {
+      gb[0] = (p[0] - c0) / d;
+      gb[1] = (p[1] - c1) / d;
+      gb[2] = (p[2] - c2) / d;
+    }
+  }
+  return d;
+}
+
 // Exact signed distance (negative inside) at world offset r from the centre.
 // sphere: |r| - radius.  cube (edge a): body offset p = R^T r,
 // q_k = |p_k| - a/2, d = |max(q, 0)| + min(max_k q_k, 0).
 __device__ inline double sdf(int shape, double size, const double* R,
-                             double r0, double r1, double r2) {
+                             double r0, double r1, double r2,
+                             const PolyDev* poly) {
+  if (poly && shape >= POLY0) {
+    double p[3];
+    p[0] = (R[0] * r0 + R[3] * r1 + R[6] * r2) / size;
+    p[1] = (R[1] * r0 + R[4] * r1 + R[7] * r2) / size;
+    p[2] = (R[2] * r0 + R[5] * r1 + R[8] * r2) / size;
+    return size * poly_sdf_unit<double>(poly + (shape - POLY0), p, nullptr, 1e300);
+  }
   if (shape == 2) {
     const double p0 = R[0] * r0 + R[3] * r1 + R[6] * r2;
     const double p1 = R[1] * r0 + R[4] * r1 + R[7] * r2;
@@ -190,8 +303,16 @@ __device__ inline double sdf(int shape, double size, const double* R,
 // conservative screening against thresholds: its error is below
 // 1e-6 (|r|_1 + size) plus a few units in the last place.
 __device__ inline float sdf32(int shape, float size, const double* R, float r0,
-                              float r1, float r2) {
+                              float r1, float r2, const PolyDev* poly) {
   if (shape == 0) return sqrtf(r0 * r0 + r1 * r1 + r2 * r2) - size;
+  if (poly && shape >= POLY0) {
+    // beyond 1.5 cells outside only the sign of d - eps/2 matters here
+    float p[3];
+    p[0] = ((float)R[0] * r0 + (float)R[3] * r1 + (float)R[6] * r2) / size;
+    p[1] = ((float)R[1] * r0 + (float)R[4] * r1 + (float)R[7] * r2) / size;
+    p[2] = ((float)R[2] * r0 + (float)R[5] * r1 + (float)R[8] * r2) / size;
+    return size * poly_sdf_unit<float>(poly + (shape - POLY0), p, nullptr, 1.5f / size);
+  }
   const float h = 0.5f * size;
   const float p0 = (float)R[0] * r0 + (float)R[3] * r1 + (float)R[6] * r2;
   const float p1 = (float)R[1] * r0 + (float)R[4] * r1 + (float)R[7] * r2;
@@ -205,8 +326,16 @@ __device__ inline float sdf32(int shape, float size, const double* R, float r0,
 // As sdf32, with the rotation already in FP32 and the hardware square root
 // (within 1 ulp; used for screening against an error bound).
 __device__ inline float sdf32_r(int shape, float size, const float* R, float r0,
-                                float r1, float r2) {
+                                float r1, float r2, const PolyDev* poly) {
   if (shape == 0) return __builtin_amdgcn_sqrtf(r0 * r0 + r1 * r1 + r2 * r2) - size;
+  if (poly && shape >= POLY0) {
+    // beyond 1.5 cells outside the lower bound settles both thresholds
+    float p[3];
+    p[0] = (R[0] * r0 + R[3] * r1 + R[6] * r2) / size;
+    p[1] = (R[1] * r0 + R[4] * r1 + R[7] * r2) / size;
+    p[2] = (R[2] * r0 + R[5] * r1 + R[8] * r2) / size;
+    return size * poly_sdf_unit<float>(poly + (shape - POLY0), p, nullptr, 1.5f / size);
+  }
   const float h = 0.5f * size;
   const float p0 = R[0] * r0 + R[3] * r1 + R[6] * r2;
   const float p1 = R[1] * r0 + R[4] * r1 + R[7] * r2;
@@ -222,7 +351,17 @@ __device__ inline float sdf32_r(int shape, float size, const float* R, float r0,
 // gradient is the normal of the nearest face (ties to the lowest axis);
 // at a sphere's centre it is zero.
 __device__ inline double sdf_grad(int shape, double size, const double* R,
-                                  const double* r, double* g) {
+                                  const double* r, double* g, const PolyDev* poly) {
+  if (poly && shape >= POLY0) {
+    double p[3], gb[3];
+    #pragma unroll
+    for (int k = 0; k < 3; ++k) p[k] = (R[0 + k] * r[0] + R[3 + k] * r[1] + R[6 + k] * r[2]) / size;
+    const double d = size * poly_sdf_unit<double>(poly + (shape - POLY0), p, gb, 1e300);
+    #pragma unroll
+    for (int k = 0; k < 3; ++k)
+      g[k] = R[3 * k + 0] * gb[0] + R[3 * k + 1] * gb[1] + R[3 * k + 2] * gb[2];
+    return d;
+  }
   if (shape == 2) {
     const double p0 = R[0] * r[0] + R[3] * r[1] + R[6] * r[2];
     const double p1 = R[1] * r[0] + R[4] * r[1] + R[7] * r[2];

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(
     if (o >= 0) {
       pr = prec + (size_t)PREC_N * o;
       lever(g, x, y, z, rec_X(pr), r);
-      const double d = sdf_grad(P.shape[o], P.size[o], rec_R(pr), r, nrm);
+      const double d = sdf_grad(P.shape[o], P.size[o], rec_R(pr), r, nrm, nullptr);
       B = weight(d, ph.eps);
       if (d > -0.5 * ph.eps && d < 0.5 * ph.eps)
         Bp = -(PI / (2.0 * ph.eps)) * sin(PI * (d + 0.5 * ph.eps) / ph.eps);

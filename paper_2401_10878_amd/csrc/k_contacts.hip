@@ -93,12 +93,13 @@ __global__ void k_keep(PairTable from, PairTable to, Counters* ctr) {
 struct Body {
   int shape;
   double size, X[3], R[9];
+  const PolyDev* poly;
 };
 
 __device__ inline double body_sdf(const Body& b, const double* y, double* g) {
   const double r[3] = {y[0] - b.X[0], y[1] - b.X[1], y[2] - b.X[2]};
-  if (g) return sdf_grad(b.shape, b.size, b.R, r, g);
-  return sdf(b.shape, b.size, b.R, r[0], r[1], r[2]);
+  if (g) return sdf_grad(b.shape, b.size, b.R, r, g, b.poly);
+  return sdf(b.shape, b.size, b.R, r[0], r[1], r[2], b.poly);
 }
 
 // enlarged distance of member b (particle, or wall -1 bottom / -2 top)
@@ -135,6 +136,7 @@ __device__ void add_contact(Tiles tl, Counters* ctr, int p, int other,
   }
 }
 
+template <bool POLY>
 __global__ __launch_bounds__(256) void k_treat(PairTable t, Particles P, Geom g,
                                                Phys ph, Tiles tl, Counters* ctr) {
   const int lane = threadIdx.x % WAVE;
@@ -151,6 +153,7 @@ __global__ __launch_bounds__(256) void k_treat(PairTable t, Particles P, Geom g,
   const double delta = ph.delta_c;
 
   Body A, Bb;
+  A.poly = Bb.poly = POLY ? P.poly : nullptr;
   A.shape = P.shape[a];
   A.size = P.size[a];
   for (int k = 0; k < 3; ++k) A.X[k] = P.X[3 * a + k];
@@ -358,7 +361,11 @@ hipError_t launch_keep(Ctx& c, PairTable from, PairTable to) {
 }
 
 hipError_t launch_treat(Ctx& c, PairTable t) {
-  hipLaunchKernelGGL(k_treat, dim3((unsigned)((t.cap + 3) / 4)), dim3(256), 0,
+  if (c.has_poly)
+    hipLaunchKernelGGL(k_treat<true>, dim3((unsigned)((t.cap + 3) / 4)), dim3(256), 0,
+                     c.stream, t, c.part, c.g, c.ph, c.tl, c.counters);
+  else
+    hipLaunchKernelGGL(k_treat<false>, dim3((unsigned)((t.cap + 3) / 4)), dim3(256), 0,
                      c.stream, t, c.part, c.g, c.ph, c.tl, c.counters);
   return hipGetLastError();
 }

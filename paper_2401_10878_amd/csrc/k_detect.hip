@@ -59,6 +59,7 @@ __device__ void commit_pair(PairTable t, Counters* ctr, int a, int b,
   }
 }
 
+template <bool POLY>
 __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
                                                 Tiles tl, int* __restrict__ owner,
                                                 PairTable tab, Counters* ctr) {
@@ -120,8 +121,9 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
     const float f0 = minimg_f(fxf - xr[0], Lxf, true);
     const float f1 = minimg_f(fyf - xr[1], Lyf, true);
     const float f2 = minimg_f(fzf - xr[2], Lzf, perz);
-    const float d = sdf32_r(shape, size, xr + 3, f0, f1, f2);
-    const float rc = shape == 1 ? 0.8660254f * size : size;
+    const float d = sdf32_r(shape, size, xr + 3, f0, f1, f2, POLY ? P.poly : nullptr);
+    const float rc = POLY && shape >= POLY0 ? (float)P.poly[shape - POLY0].rc * size
+                                    : (shape == 1 ? 0.8660254f * size : size);
     const float tol = 1e-3f + 1e-5f * (1.7320508f * (rc + 2.0f) + size);
     const uint64_t bit = 1ull << c;
     if (d < ot + tol) {
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
         const double r0 = minimg(fx - X0, Lx, true);
         const double r1 = minimg(fy - X1, Ly, true);
         const double r2 = minimg(fz - X2, Lz, perz);
-        const double d = sdf(P.shape[p], P.size[p], R, r0, r1, r2);
+        const double d = sdf(P.shape[p], P.size[p], R, r0, r1, r2, POLY ? P.poly : nullptr);
         if (own_open && ((pown >> c) & 1ull) && d < own_t &&
             (d < bd || (d == bd && p < ep))) {
           bd = d;
@@ -220,7 +222,11 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
 hipError_t launch_detect(Ctx& c, PairTable to) {
   const long long ntiles = (long long)c.g.dtx * c.g.dty * c.g.dtz;
   const unsigned blocks = (unsigned)((ntiles + 3) / 4);
-  hipLaunchKernelGGL(k_detect, dim3(blocks), dim3(256), 0, c.stream, c.part,
+  if (c.has_poly)
+    hipLaunchKernelGGL(k_detect<true>, dim3(blocks), dim3(256), 0, c.stream, c.part,
+                     c.g, c.ph, c.tl, c.owner, to, c.counters);
+  else
+    hipLaunchKernelGGL(k_detect<false>, dim3(blocks), dim3(256), 0, c.stream, c.part,
                      c.g, c.ph, c.tl, c.owner, to, c.counters);
   return hipGetLastError();
 }

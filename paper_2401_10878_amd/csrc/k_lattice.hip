@@ -198,8 +198,11 @@ __device__ inline Nbr neighbours(const Geom& g, int x, int y, int z) {
   return nb;
 }
 
-// At most 128 VGPRs (four wavefronts per SIMD) without spills.
-template <typename S>
+// At most 128 VGPRs (four wavefronts per SIMD) without spills.  POLY: built
+// with the polyhedron signed distance (scenes without polyhedra run the
+// form without it, which needs fewer registers).  BAL: with the block sums
+// and device acceleration of the zero-net-flux balance force.
+template <typename S, bool POLY, bool BAL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_lattice(const S* __restrict__ src,
                                                  S* __restrict__ dst,
                                                  const int* __restrict__ owner,
@@ -280,10 +283,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const C r2 = (C)minimg((double)z - X2, (double)g.nz, perz);
     C d;
     if constexpr (Store<S>::shifted) {
-      d = sdf32(shape, (float)size, Ro, r0, r1, r2);
+      d = sdf32(shape, (float)size, Ro, r0, r1, r2, POLY ? P.poly : nullptr);
       B = weight32(d, (float)ph.eps);
     } else {
-      d = sdf(shape, size, Ro, r0, r1, r2);
+      d = sdf(shape, size, Ro, r0, r1, r2, POLY ? P.poly : nullptr);
       B = weight(d, ph.eps);
     }
     const C w0 = (C)W0, w1 = (C)W1, w2 = (C)W2;
@@ -293,7 +296,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   }
   // uniform fluid acceleration: fixed, or the zero-net-flux controller's
   double ax = ph.a_ext[0], ay = ph.a_ext[1], az = ph.a_ext[2];
-  if (ph.bal_mode == 2) {
+  if (BAL) {
     ax = ctr->bal_a[0];
     ay = ctr->bal_a[1];
     az = ctr->bal_a[2];
@@ -329,7 +332,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 #pragma unroll
     for (int i = 0; i < Q; ++i) Store<S>::st(dst, i * n + self, f[i]);
   }
-  if (ph.bal_mode == 2) {
+  if (BAL) {
     // mass and momentum of the collided populations, per block in fixed
     // order, for the zero-net-flux balance controller
     C m = 0, j0 = 0, j1 = 0, j2 = 0;
@@ -551,9 +554,11 @@ static unsigned tile_blocks(const Geom& g) {
 
 template <typename S>
 static void run_lattice(Ctx& c, const void* src, void* dst) {
-  hipLaunchKernelGGL(k_lattice<S>, dim3(tile_blocks(c.g)), dim3(256), 0,
-                     c.stream, (const S*)src, (S*)dst, c.owner, c.part, c.g,
-                     c.ph, c.counters, c.bal_part);
+  const bool bal = c.ph.bal_mode == 2;
+  auto k = c.has_poly ? (bal ? k_lattice<S, true, true> : k_lattice<S, true, false>)
+                      : (bal ? k_lattice<S, false, true> : k_lattice<S, false, false>);
+  hipLaunchKernelGGL(k, dim3(tile_blocks(c.g)), dim3(256), 0, c.stream, (const S*)src,
+                     (S*)dst, c.owner, c.part, c.g, c.ph, c.counters, c.bal_part);
 }
 
 hipError_t launch_lattice(Ctx& c, const void* src, void* dst) {

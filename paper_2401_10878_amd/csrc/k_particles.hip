@@ -130,17 +130,30 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
     const double V = P.vol[ip], m = P.mass[ip], I = P.inert[ip];
     const double s = P.dens[ip];
     const double dt = ph.dt_sub;
+    double Tt[3];
     for (int k = 0; k < 3; ++k) {
       const double Fg = (s - 1.0) * V * ph.gravity[k];
       const double Ft = F[k] + Fcp[k] + Fg;
-      const double Tt = T[k] + Tcp[k];
+      Tt[k] = T[k] + Tcp[k];
       U[k] += Ft / m * dt;
       X[k] += U[k] * dt;
       if (per[k]) {
         if (X[k] >= L[k]) X[k] -= L[k];
         else if (X[k] < 0.0) X[k] += L[k];
       }
-      W[k] += Tt / I * dt;
+    }
+    if (P.shape[ip] >= POLY0) {
+      // eq. (3) with the world-frame tensor at the current orientation:
+      // w += R I_b^-1 R^T T dt
+      double Rc[9], tb[3], wb[3];
+      quat_to_rot(q, Rc);
+      const double* Ii = P.Iinv + 9 * ip;
+      for (int k = 0; k < 3; ++k) tb[k] = (Rc[0 + k] * Tt[0] + Rc[3 + k] * Tt[1]) + Rc[6 + k] * Tt[2];
+      for (int k = 0; k < 3; ++k) wb[k] = (Ii[3 * k] * tb[0] + Ii[3 * k + 1] * tb[1]) + Ii[3 * k + 2] * tb[2];
+      for (int k = 0; k < 3; ++k)
+        W[k] += ((Rc[3 * k] * wb[0] + Rc[3 * k + 1] * wb[1]) + Rc[3 * k + 2] * wb[2]) * dt;
+    } else {
+      for (int k = 0; k < 3; ++k) W[k] += Tt[k] / I * dt;
     }
     // orientation: exact rotation through |w| dt about w, q <- dq (x) q
     const double th = sqrt(W[0] * W[0] + W[1] * W[1] + W[2] * W[2]) * dt;
@@ -180,10 +193,9 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
   }
 
   // 3. Reach box: axis-aligned half extent of the body plus the largest
-  // distance at which a node can be owned by it (eps/2), receive a momentum
-  // exchange term through a link of a node it owns (eps/2 + sqrt 2), or be
-  // flagged by the rough detection (sqrt(0.75) + enlargement).
-  const double margin = fmax(0.5 * ph.eps + 1.4142135623730951, DETECT + ph.delta_c) + 0.25;
+  // distance at which a node can be owned by it (eps/2) or flagged by the
+  // rough detection (sqrt(0.75) + enlargement).
+  const double margin = fmax(0.5 * ph.eps, DETECT + ph.delta_c) + 0.25;
   const int shape = P.shape[ip];
   const double size = P.size[ip];
   const int n3[3] = {g.nx, g.ny, g.nz};
@@ -192,6 +204,17 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
     ext[k] = size;
     if (shape == 1)
       ext[k] = 0.5 * size * (fabs(R[3 * k]) + fabs(R[3 * k + 1]) + fabs(R[3 * k + 2])) ;
+    if (shape >= POLY0) {
+      // largest |world coordinate| of a vertex along axis k
+      const PolyDev* pd = P.poly + (shape - POLY0);
+      double e = 0.0;
+      for (int i = 0; i < pd->nv; ++i) {
+        const double c = fabs((R[3 * k] * pd->v[i][0] + R[3 * k + 1] * pd->v[i][1]) +
+                              R[3 * k + 2] * pd->v[i][2]);
+        e = c > e ? c : e;
+      }
+      ext[k] = size * e;
+    }
     ext[k] += margin;
   }
   // detection tiles
@@ -215,7 +238,7 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
       const double rc[3] = {minimg(tx * DX + 0.5 * (DX - 1) - X[0], L[0], true),
                             minimg(ty * DY + 0.5 * (DY - 1) - X[1], L[1], true),
                             minimg(tz * DZ + 0.5 * (DZ - 1) - X[2], L[2], per[2])};
-      if (sdf(shape, size, R, rc[0], rc[1], rc[2]) > reach) continue;
+      if (sdf(shape, size, R, rc[0], rc[1], rc[2], P.poly) > reach) continue;
       const long long tile = tx + (long long)g.dtx * (ty + (long long)g.dty * tz);
       const int slot = atomicAdd(&tl.dcount[tile], 1);
       if (slot < g.tile_cap) tl.dlist[tile * g.tile_cap + slot] = ip;

@@ -82,6 +82,7 @@ def load():
     L.hlbm_create.argtypes = [P(Params), v, P(v)]
     L.hlbm_bind_populations.argtypes = [v, v, v, C.c_size_t]
     L.hlbm_init_particles.argtypes = [v, i, P(i), P(d), P(d), P(d), P(d), P(d), P(d)]
+    L.hlbm_define_polyhedron.argtypes = [v, i, i, P(d), i, P(i), P(i)]
     L.hlbm_init_fluid_equilibrium.argtypes = [v, d, P(d)]
     L.hlbm_set_populations.argtypes = [v, P(d)]
     L.hlbm_step.argtypes = [v, i]
@@ -141,12 +142,14 @@ def make_params(p) -> Params:
 class Simulation:
     """One coupled HLBM + contact simulation on one GPU.
 
-    params: workloads.Params; scene: workloads.Scene.  The two population
-    buffers are torch device tensors lent to the library; the library runs on
-    a dedicated torch stream (default priority).
+    params: workloads.Params; scene: workloads.Scene; polyhedra: optional
+    {type k: workloads.Polyhedron} for particles of shape POLY0 + k.  The two
+    population buffers are torch device tensors lent to the library; the
+    library runs on a dedicated torch stream (default priority).
     """
 
-    def __init__(self, params, scene, device="cuda:0", graph=False):
+    def __init__(self, params, scene, device="cuda:0", graph=False,
+                 polyhedra=None):
         import torch
         self.torch = torch
         self.L = load()
@@ -171,6 +174,12 @@ class Simulation:
         self._check(self.L.hlbm_bind_populations(
             self.h, C.c_void_p(self.fa.data_ptr()), C.c_void_p(self.fb.data_ptr()),
             nbytes))
+        for k, poly in (polyhedra or {}).items():
+            v = np.ascontiguousarray(poly.vertices, np.float64).reshape(-1)
+            fs = np.array([len(f) for f in poly.faces], np.int32)
+            fi = np.array([j for f in poly.faces for j in f], np.int32)
+            self._check(self.L.hlbm_define_polyhedron(
+                self.h, int(k), v.size // 3, _dp(v), len(poly.faces), _ip(fs), _ip(fi)))
         sh = np.ascontiguousarray(scene.shape, np.int32)
         arrs = [np.ascontiguousarray(a, np.float64) for a in
                 (scene.size, scene.density, scene.X, scene.q, scene.U, scene.omega)]

@@ -507,9 +507,11 @@ def c5_adjoint_cubes(seed: int = 5) -> Workload:
 
 def random_small_scene(seed: int, dims, n_particles: int, periodic_z=1,
                        size_range=(2.0, 4.5), gap=-0.3, speed=0.01,
-                       spin=0.004, shapes=(SPHERE, CUBE)) -> Scene:
-    """Mixed convex bodies (spheres, cubes and, if asked, octahedra) in a
-    small box; neighbours may nearly touch.
+                       spin=0.004, shapes=(SPHERE, CUBE),
+                       poly_rc=None) -> Scene:
+    """Mixed convex bodies (spheres, cubes and, if asked, octahedra or
+    polyhedron types POLY0 + k with unit circumradius poly_rc[POLY0 + k]) in
+    a small box; neighbours may nearly touch.
 
     `gap` is the allowed surface gap between bounding spheres (negative
     values let bounding spheres interpenetrate, so that corners and
@@ -528,6 +530,10 @@ def random_small_scene(seed: int, dims, n_particles: int, periodic_z=1,
         elif shape[i] == OCTAHEDRON:
             size[i] = 1.3 * rng.uniform(*size_range)
             rb[i] = size[i]
+        elif shape[i] >= POLY0:
+            rc = poly_rc[int(shape[i])]
+            size[i] = 1.2 * rng.uniform(*size_range) / rc
+            rb[i] = size[i] * rc
         else:
             size[i] = 2.0 * rng.uniform(*size_range) / math.sqrt(3.0) * 1.4
             rb[i] = 0.5 * size[i] * math.sqrt(3.0)
