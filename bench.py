@@ -28,6 +28,7 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PREC = {"fp64": 0, "fp32": 1, "fp16s": 2}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f16-storage/f32-compute"}
 VALUE_BYTES = {0: 8, 1: 4, 2: 2}
+W_POLY0 = 3                    # shape code of the first polyhedron type
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lattice_k_mea_c3_traffic.json")
 LATTICE_SRC = os.path.join(ROOT, "paper_2401_10878_amd", "csrc", "k_lattice.hip")
 
@@ -55,7 +56,8 @@ def run_gpu(wl, prec, steps, warmup, graph):
     import torch
     from paper_2401_10878_amd import hlbm
     p = wl.params.replace(precision=PREC[prec])
-    sim = hlbm.Simulation(p, wl.scene, device="cuda:0", graph=graph)
+    sim = hlbm.Simulation(p, wl.scene, device="cuda:0", graph=graph,
+                          polyhedra=wl.polyhedra)
     sim.init_equilibrium()
     sim.step(warmup)
     sim.sync()
@@ -94,7 +96,7 @@ def graph_ms_per_step(wl, prec, steps, warmup):
     import torch
     from paper_2401_10878_amd import hlbm
     sim = hlbm.Simulation(wl.params.replace(precision=PREC[prec]), wl.scene,
-                          device="cuda:0", graph=True)
+                          device="cuda:0", graph=True, polyhedra=wl.polyhedra)
     sim.init_equilibrium()
     sim.step(warmup)
     sim.sync()
@@ -116,7 +118,16 @@ def error_vs_fp64(wl, res, ref):
     max(|F|, (s - 1) V |g|)) and particle velocity."""
     import numpy as np
     sc, g = wl.scene, abs(wl.params.gravity[2])
-    V = np.where(sc.shape == 1, sc.size ** 3, 4.0 / 3.0 * np.pi * sc.size ** 3)
+    V = np.where(sc.shape == 0, 4.0 / 3.0 * np.pi * sc.size ** 3,
+                 np.where(sc.shape == 2, 4.0 / 3.0, 1.0) * sc.size ** 3)
+    for k, P in (wl.polyhedra or {}).items():
+        # a normalising scale only: the volume of the polyhedron by the
+        # divergence theorem over its faces, fanned into triangles
+        v = P.vertices
+        vol = sum(np.dot(v[f[0]], np.cross(v[f[j]], v[f[j + 1]]))
+                  for f in P.faces for j in range(1, len(f) - 1)) / 6.0
+        m = sc.shape == W_POLY0 + k
+        V[m] = vol * sc.size[m] ** 3
     Fref = ((sc.density - 1.0) * V).max() * g
     U, U64 = res["final"]["U"], ref["final"]["U"]
     F, F64 = res["final"]["Fh"], ref["final"]["Fh"]
@@ -130,6 +141,8 @@ def error_vs_fp64(wl, res, ref):
 def cpu_baseline(wl, steps):
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
+    for k, P in (wl.polyhedra or {}).items():
+        O.define_polyhedron(k, P.vertices, P.faces)
     s = O.OracleSim(wl.params, wl.scene)
     s.init_equilibrium()
     t0 = time.perf_counter()
@@ -165,7 +178,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", default="fp32", choices=sorted(PREC))
-    ap.add_argument("--workload", default="C3", choices=["C1", "C2", "C3", "C4", "C5"])
+    ap.add_argument("--workload", default="C3", choices=["C1", "C2", "C3", "C3B", "C4", "C5"])
     ap.add_argument("--graph", action="store_true",
                     help="replay the step as a captured HIP graph")
     ap.add_argument("--other-precisions", type=int, default=1,
@@ -176,8 +189,8 @@ def main():
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU "
-              "path (see DESIGN.md for how it would shard).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU "
+              "path.", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()

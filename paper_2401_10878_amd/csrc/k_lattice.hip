@@ -19,7 +19,7 @@
 // owns (eqs. (17)-(18)), summed per lattice block without atomics.
 //
 // Storage is a template parameter: FP64, FP32, or binary16 deviations
-// h_i = f_i - w_i (FP32 arithmetic).  The momentum exchange is FP64.
+// h_i = f_i - w_i (FP32 arithmetic).
 #include <hip/hip_fp16.h>
 
 #include "context.h"
@@ -357,7 +357,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 //   S(x) = sum_i (c_i - u_p(x)) f_i*(x) + (c_i + u_p(x)) f_opp(i)(x)
 //        = sum_{i>=1} (c_i - u_p(x)) d_i,   d_i = f_i*(x) - f_i(x)
 // (d_0 = 0).  Shifted storage: both terms of d_i carry the same rest weight,
-// so d_i is the difference of two stored values.  Each lane takes one node;
+// so d_i is the difference of two stored values.  d_i and the node sums are
+// formed in the compute precision C of the storage (FP64 for FP64 storage,
+// FP32 for the shifted forms, whose stored values are small deviations);
+// u_p, S, r x S and every reduction are FP64.  Each lane takes one node;
 // the wavefront sums -S and -r x S per particle into its LDS row of the
 // block's candidate slots, and every (block, particle) slot is stored once.
 // Blocks with no candidate particle have no owned node and exit at once.
@@ -399,14 +402,14 @@ __global__ __launch_bounds__(256) void k_mea(const S* __restrict__ fs,
     const double X0 = P.X[3 * o], X1 = P.X[3 * o + 1], X2 = P.X[3 * o + 2];
     const double U0 = P.U[3 * o], U1 = P.U[3 * o + 1], U2 = P.U[3 * o + 2];
     const double W0 = P.W[3 * o], W1 = P.W[3 * o + 1], W2 = P.W[3 * o + 2];
-    double dD = 0.0, dJ0 = 0.0, dJ1 = 0.0, dJ2 = 0.0;
+    C dD = 0, dJ0 = 0, dJ1 = 0, dJ2 = 0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       const int bw = nb.beyond(-cz(i));
-      double d = (double)fo[i] - (double)(bw ? fo[opp(i)] : fi[i]);
+      C d = fo[i] - (bw ? fo[opp(i)] : fi[i]);
       if (bw) {
         const double* uw = ph.wall_u[bw - 1];
-        d -= 6.0 * wgt(i) * (cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2]);
+        d -= (C)(6.0 * wgt(i) * (cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2]));
       }
       dD += d;
       if (cx(i)) dJ0 += cx(i) > 0 ? d : -d;
@@ -419,9 +422,9 @@ __global__ __launch_bounds__(256) void k_mea(const S* __restrict__ fs,
     const double up0 = U0 + (W1 * r2 - W2 * r1);
     const double up1 = U1 + (W2 * r0 - W0 * r2);
     const double up2 = U2 + (W0 * r1 - W1 * r0);
-    s[0] = dJ0 - up0 * dD;
-    s[1] = dJ1 - up1 * dD;
-    s[2] = dJ2 - up2 * dD;
+    s[0] = (double)dJ0 - up0 * (double)dD;
+    s[1] = (double)dJ1 - up1 * (double)dD;
+    s[2] = (double)dJ2 - up2 * (double)dD;
     t[0] = r1 * s[2] - r2 * s[1];
     t[1] = r2 * s[0] - r0 * s[2];
     t[2] = r0 * s[1] - r1 * s[0];

@@ -226,10 +226,10 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
     const int cxn = sp[0].count(), cyn = sp[1].count(), czn = sp[2].count();
     const int total = cxn * cyn * czn;
     // A tile whose centre lies farther from the body than the widest test of
-    // the node pass (a possibly owned link neighbour, eps/2 + sqrt 2, or
-    // detection, sqrt(0.75) + delta_c) plus the tile's radius has no node
-    // inside either bound (signed distances are 1-Lipschitz): skip it.
-    const double reach = fmax(0.5 * ph.eps + 1.4142135623730951, DETECT + ph.delta_c) +
+    // the node pass (ownership, eps/2, or detection, sqrt(0.75) + delta_c)
+    // plus the tile's radius has no node inside either bound (signed
+    // distances are 1-Lipschitz): skip it.
+    const double reach = fmax(0.5 * ph.eps, DETECT + ph.delta_c) +
                          0.5 * sqrt((double)(DX - 1) * (DX - 1) + (DY - 1) * (DY - 1) +
                                     (DZ - 1) * (DZ - 1)) + 0.01;
     for (int t = lane; t < total; t += WAVE) {

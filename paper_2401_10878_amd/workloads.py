@@ -110,6 +110,7 @@ class Workload:
     scene: Scene
     steps: int
     note: str = ""
+    polyhedra: Optional[dict] = None   # {type k: Polyhedron} for shape POLY0 + k
 
 
 # --------------------------------------------------------------------------
@@ -309,6 +310,48 @@ def rsa_centres(rng, n, dims, min_dist, periodic, lo_margin=None,
     return pts
 
 
+def box_orientations(rng, X, half, dims, periodic, margin=0.3,
+                     max_draws=10_000) -> np.ndarray:
+    """Random orientations such that no two boxes of half extents `half`
+    (grown by margin) overlap; the separating-axis test of
+    cube_orientations with unequal half extents."""
+    n = X.shape[0]
+    dims = np.asarray(dims, float)
+    periodic = np.asarray(periodic, bool)
+    h = np.asarray(half, float) + margin
+    rc = float(np.linalg.norm(h))
+    q = np.zeros((n, 4))
+    R = np.zeros((n, 3, 3))
+    done = np.zeros(n, bool)
+
+    def overlap(Ra, Rb, t):
+        axes = [Ra[:, i] for i in range(3)] + [Rb[:, i] for i in range(3)]
+        for i in range(3):
+            for j in range(3):
+                c = np.cross(Ra[:, i], Rb[:, j])
+                nn = np.linalg.norm(c)
+                if nn > 1e-9:
+                    axes.append(c / nn)
+        for ax in axes:
+            if abs(t @ ax) > (h * np.abs(Ra.T @ ax)).sum() + (h * np.abs(Rb.T @ ax)).sum():
+                return False
+        return True
+
+    for i in range(n):
+        d = _minimg(X - X[i], dims, periodic)
+        dist2 = (d * d).sum(1)
+        near = np.nonzero(done & (dist2 < (2 * rc) ** 2))[0]
+        for draw in range(max_draws):
+            qi = random_quaternions(rng, 1)
+            Ri = _rotation_matrices(qi)[0]
+            if not any(overlap(Ri, R[j], d[j]) for j in near):
+                break
+        else:
+            raise RuntimeError(f"orientation draws stalled at box {i}")
+        q[i], R[i], done[i] = qi[0], Ri, True
+    return q
+
+
 def cube_orientations(rng, X, edge, dims, periodic, margin=0.3,
                       max_draws=10_000) -> np.ndarray:
     """Random orientations such that no two cubes (grown by margin) overlap.
@@ -432,6 +475,30 @@ def c3_dense_cubes(seed: int = 3, L: int = 256, phi: float = 0.30,
         max_pairs=max(1024, 8 * n), tile_capacity=48, precision=1)
     return Workload("C3", p, sc, 1000,
                     f"{L}^3 periodic, {n} cubes a={edge:g}, phi~{phi}, s=1.5, Ar=1000")
+
+
+def c3_dense_boxes(seed: int = 3, L: int = 256, phi: float = 0.30,
+                   edge: float = 14.0) -> Workload:
+    """C3 with the cubes replaced by boxes of edge ratio 1 : 1.25 : 1.6 and
+    the same volume, given as a convex polyhedron type (anisotropic
+    inertia, the general polyhedron signed distance)."""
+    s, ar, tau = 1.5, 1000.0, 0.55
+    dsph = cube_equiv_diameter(edge)
+    lu = lattice_units(dsph, s, ar, tau)
+    n = round(phi * L ** 3 / edge ** 3)
+    a = (edge ** 3 / 2.0) ** (1.0 / 3.0)
+    dims3 = np.array([a, 1.25 * a, 1.6 * a])
+    X = _dense_centres(seed, L, n, dsph)
+    rng = np.random.default_rng(seed + 2000)
+    q = box_orientations(rng, X, 0.5 * dims3, (L, L, L), (True, True, True))
+    sc = Scene(np.full(n, POLY0, np.int32), np.ones(n), np.full(n, s), X,
+               q, np.zeros((n, 3)), np.zeros((n, 3)))
+    p = _base_params((L, L, L), 1, tau, lu, 1).replace(
+        max_pairs=max(1024, 8 * n), tile_capacity=48, precision=1)
+    return Workload("C3B", p, sc, 1000,
+                    f"{L}^3 periodic, {n} boxes {dims3[0]:.2f} x {dims3[1]:.2f} x "
+                    f"{dims3[2]:.2f} (polyhedra), phi~{phi}, s=1.5, Ar=1000",
+                    polyhedra={0: polyhedron_cuboid(*dims3)})
 
 
 def c4_dense_spheres(seed: int = 3, L: int = 256, phi: float = 0.30,
@@ -585,6 +652,7 @@ WORKLOADS = {
     "C1": c1_two_spheres,
     "C2": c2_settling_walls,
     "C3": c3_dense_cubes,
+    "C3B": c3_dense_boxes,
     "C4": c4_dense_spheres,
     "C5": c5_adjoint_cubes,
 }
