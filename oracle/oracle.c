@@ -264,6 +264,16 @@ int orc_define_polyhedron(int type, int nv, const double *v, int nf,
         if (r > scale) scale = r;
     }
     P.rc = scale;
+    /* two distinct vertex indices at the same point make an edge of no length */
+    for (int f = 0; f < nf; ++f) {
+        int c = P.fs[f + 1] - P.fs[f];
+        for (int j = 0; j < c; ++j) {
+            const double *a = P.v[P.fv[P.fs[f] + j]], *b = P.v[P.fv[P.fs[f] + (j + 1) % c]];
+            double e2 = (b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]) +
+                        (b[2] - a[2]) * (b[2] - a[2]);
+            if (!(sqrt(e2) > 1e-9 * scale)) return poly_fail("zero-length edge");
+        }
+    }
     for (int f = 0; f < nf; ++f) {
         int c = P.fs[f + 1] - P.fs[f];
         double nn[3] = {0.0, 0.0, 0.0}, mean[3] = {0.0, 0.0, 0.0};

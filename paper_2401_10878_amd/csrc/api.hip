@@ -537,6 +537,33 @@ hlbm_status hlbm_define_polyhedron(hlbm_ctx* h, int type, int nv, const double* 
       if (fabs(sd) > 1e-9 * scale) return fail(c, HLBM_E_ARG, "polyhedron: face %d not planar", f);
     }
   }
+  for (int i = 0; i < nv; ++i)
+    for (int k = 0; k < 3; ++k) D.vf[i][k] = (float)D.v[i][k];
+  for (int f = 0; f < nf; ++f)
+    for (int k = 0; k < 4; ++k) D.plf[f][k] = (float)D.pl[f][k];
+  for (int f = 0; f < nf; ++f) {
+    const int cnt = D.fs[f + 1] - D.fs[f];
+    for (int j = 0; j < cnt; ++j) {
+      const int m = D.fs[f] + j;
+      const double* a = D.v[fvert(f, j)];
+      const double* b = D.v[fvert(f, j + 1)];
+      for (int k = 0; k < 3; ++k) D.ed[m][k] = b[k] - a[k];
+      const double ee = D.ed[m][0] * D.ed[m][0] + D.ed[m][1] * D.ed[m][1] + D.ed[m][2] * D.ed[m][2];
+      if (!(sqrt(ee) > 1e-9 * scale))
+        return fail(c, HLBM_E_ARG, "polyhedron: zero-length edge in face %d", f);
+      D.ed[m][3] = 1.0 / ee;
+      const double* n = D.pl[f];
+      const double* e = D.ed[m];
+      D.sd[m][0] = n[1] * e[2] - n[2] * e[1];
+      D.sd[m][1] = n[2] * e[0] - n[0] * e[2];
+      D.sd[m][2] = n[0] * e[1] - n[1] * e[0];
+      D.sd[m][3] = D.sd[m][0] * a[0] + D.sd[m][1] * a[1] + D.sd[m][2] * a[2];
+      for (int k = 0; k < 4; ++k) {
+        D.ef[m][k] = (float)D.ed[m][k];
+        D.sf[m][k] = (float)D.sd[m][k];
+      }
+    }
+  }
   P.ok = true;
   if (!c.poly_dev) HIPCHECK(hipMalloc(&c.poly_dev, sizeof(PolyDev) * MAXPOLY));
   HIPCHECK(hipMemcpy(c.poly_dev + type, &D, sizeof(PolyDev), hipMemcpyHostToDevice));

@@ -68,7 +68,30 @@ struct PolyDev {
   int fs[PF + 1];
   int fv[PFV];
   int e[PE][2];
+  double ed[PFV][4];     // boundary edge of slot m: fv[m] -> next vertex of
+                        // its face, as (b - a, 1 / |b - a|^2)
+  double sd[PFV][4];     // side plane of slot m: s = n x (b - a), s . a; a
+                        // point projects into the face when s . p >= s . a
+                        // for each of its slots
+  float vf[PV][3];      // v, pl, ed and sd rounded to FP32 (the FP32 forms)
+  float plf[PF][4];
+  float ef[PFV][4];
+  float sf[PFV][4];
 };
+
+// Polyhedron tables are read through the constant address space: they do
+// not change while a kernel runs, so loads from a wave-uniform type become
+// scalar loads.
+#define HLBM_CONST __attribute__((address_space(4)))
+typedef const HLBM_CONST PolyDev CPoly;
+__device__ inline const HLBM_CONST double* poly_vert(CPoly* P, int i, double) { return P->v[i]; }
+__device__ inline const HLBM_CONST float* poly_vert(CPoly* P, int i, float) { return P->vf[i]; }
+__device__ inline const HLBM_CONST double* poly_plane(CPoly* P, int f, double) { return P->pl[f]; }
+__device__ inline const HLBM_CONST float* poly_plane(CPoly* P, int f, float) { return P->plf[f]; }
+__device__ inline const HLBM_CONST double* poly_edge(CPoly* P, int m, double) { return P->ed[m]; }
+__device__ inline const HLBM_CONST float* poly_edge(CPoly* P, int m, float) { return P->ef[m]; }
+__device__ inline const HLBM_CONST double* poly_side(CPoly* P, int m, double) { return P->sd[m]; }
+__device__ inline const HLBM_CONST float* poly_side(CPoly* P, int m, float) { return P->sf[m]; }
 
 struct Particles {
   int n;
@@ -178,83 +201,101 @@ __device__ inline T octa_q(T a, T q0, T q1, T q2) {
 }
 
 // Signed distance of a unit-scale polyhedron at body point p (T = double or
-// float) and, if gb is given, its body-frame gradient.  Inside (every plane
-// distance <= 0): the largest plane distance, gradient the normal of the
-// first face attaining it.  Outside: the smallest of the distances to face
-// interiors (faces the point is above whose polygon contains its
-// projection) and to the edges, first face then edges in order on ties;
-// gradient the face normal or (p - closest point) / d.  With far < inf an
-// outside point whose largest plane distance exceeds far returns that
-// lower bound (screening: such a point is beyond every threshold).
+// float, data in the same precision) and, if gb is given, its body-frame
+// gradient.  Inside (every plane distance <= 0): the largest plane distance,
+// gradient the normal of the first face attaining it.  Outside: the distance
+// to the nearest boundary point, which is unique for a convex body.  When
+// the projection onto the face of the largest plane distance lies in that
+// face, that plane distance (a lower bound of the distance) is attained and
+// is the result.  Otherwise the nearest point lies on a face the point is
+// above (positive plane distance) or on the boundary of such a face: at a
+// nearest point c, p - c is a non-negative combination of the normals of
+// the faces through c, so (p - c) . n > 0 for one of them.  Those faces'
+// interiors and boundary edges are searched; gradient the face normal or
+// (p - c) / d.  With far < inf an outside point whose largest plane
+// distance exceeds far returns that lower bound (screening: such a point is
+// beyond every threshold).
+// Whether body point p projects into face f: (b - a) x (p - a) . n >= 0,
+// i.e. (n x (b - a)) . p >= (n x (b - a)) . a, along every boundary edge
+// a -> b (counter-clockwise seen from outside; the offset along n drops out
+// of the triple product).
 template <typename T>
-__device__ inline T poly_sdf_unit(const PolyDev* P, const T* p, T* gb, T far) {
+__device__ inline bool poly_face_contains(CPoly* P, int f, const T* p) {
+  const int b0 = P->fs[f], cnt = P->fs[f + 1] - b0;
+  bool inside = true;
+  for (int j = 0; j < cnt; ++j) {
+    const HLBM_CONST T* sp = poly_side(P, b0 + j, T());
+    inside = inside && ((sp[0] * p[0] + sp[1] * p[1]) + sp[2] * p[2] >= sp[3]);
+  }
+  return inside;
+}
+
+template <typename T>
+__device__ inline T poly_sdf_unit(CPoly* P, const T* p, T* gb, T far) {
   const int nf = P->nf;
   T best = (T)-1e30;
   int fm = 0;
   for (int f = 0; f < nf; ++f) {
-    const double* pl = P->pl[f];
-    const T d = ((T)pl[0] * p[0] + (T)pl[1] * p[1]) + (T)pl[2] * p[2] - (T)pl[3];
+    const HLBM_CONST T* pl = poly_plane(P, f, T());
+    const T d = (pl[0] * p[0] + pl[1] * p[1]) + pl[2] * p[2] - pl[3];
     if (d > best) {
       best = d;
       fm = f;
     }
   }
-  if (best <= (T)0) {
+  if (best <= (T)0 || best > far) {
     if (gb)
-      for (int k = 0; k < 3; ++k) gb[k] = (T)P->pl[fm][k];
+      for (int k = 0; k < 3; ++k) gb[k] = poly_plane(P, fm, T())[k];
     return best;
   }
-  if (best > far) return best;
-  T dmin2 = (T)1e30, c0 = (T)0, c1 = (T)0, c2 = (T)0;
+  {
+    // the face test with per-lane face data (a pass per distinct face of the
+    // wavefront with the face in scalar registers was slower)
+    if (poly_face_contains<T>(P, fm, p)) {
+      if (gb)
+        for (int k = 0; k < 3; ++k) gb[k] = poly_plane(P, fm, T())[k];
+      return best;
+    }
+  }
+  T dmin2 = (T)1e30, c0 = (T)0, c1 = (T)0, c2 = (T)0, dface = (T)0;
   int face_hit = -1;
   for (int f = 0; f < nf; ++f) {
-    const double* pl = P->pl[f];
-    const T n0 = (T)pl[0], n1 = (T)pl[1], n2 = (T)pl[2];
-    const T d = (n0 * p[0] + n1 * p[1]) + n2 * p[2] - (T)pl[3];
+    const HLBM_CONST T* n = poly_plane(P, f, T());
+    const T d = (n[0] * p[0] + n[1] * p[1]) + n[2] * p[2] - n[3];
     if (d <= (T)0) continue;
-    const T q0 = p[0] - d * n0, q1 = p[1] - d * n1, q2 = p[2] - d * n2;
     const int b0 = P->fs[f], cnt = P->fs[f + 1] - b0;
     bool inside = true;
-    for (int j = 0; j < cnt && inside; ++j) {
-      const double* a = P->v[P->fv[b0 + j]];
-      const double* b = P->v[P->fv[b0 + (j + 1 == cnt ? 0 : j + 1)]];
-      const T e0 = (T)b[0] - (T)a[0], e1 = (T)b[1] - (T)a[1], e2 = (T)b[2] - (T)a[2];
-      const T w0 = q0 - (T)a[0], w1 = q1 - (T)a[1], w2 = q2 - (T)a[2];
-      const T x0 = e1 * w2 - e2 * w1, x1 = e2 * w0 - e0 * w2, x2 = e0 * w1 - e1 * w0;
-      if ((x0 * n0 + x1 * n1) + x2 * n2 < (T)0) inside = false;
+    for (int j = 0; j < cnt; ++j) {
+      const HLBM_CONST T* a = poly_vert(P, P->fv[b0 + j], T());
+      const HLBM_CONST T* e = poly_edge(P, b0 + j, T());
+      const HLBM_CONST T* sp = poly_side(P, b0 + j, T());
+      const T e0 = e[0], e1 = e[1], e2 = e[2];
+      const T w0 = p[0] - a[0], w1 = p[1] - a[1], w2 = p[2] - a[2];
+      inside = inside && ((sp[0] * p[0] + sp[1] * p[1]) + sp[2] * p[2] >= sp[3]);
+      // nearest point of the segment a -> a + e
+      T t = ((w0 * e0 + w1 * e1) + w2 * e2) * e[3];
+      t = t < (T)0 ? (T)0 : (t > (T)1 ? (T)1 : t);
+      const T y0 = a[0] + t * e0, y1 = a[1] + t * e1, y2 = a[2] + t * e2;
+      const T dx = p[0] - y0, dy = p[1] - y1, dz = p[2] - y2;
+      const T d2 = (dx * dx + dy * dy) + dz * dz;
+      if (d2 < dmin2) {
+        dmin2 = d2;
+        face_hit = -1;
+        c0 = y0;
+        c1 = y1;
+        c2 = y2;
+      }
     }
     if (inside && d * d < dmin2) {
       dmin2 = d * d;
+      dface = d;
       face_hit = f;
-      c0 = q0;
-      c1 = q1;
-      c2 = q2;
     }
   }
-  const int ne = P->ne;
-  for (int i = 0; i < ne; ++i) {
-    const double* a = P->v[P->e[i][0]];
-    const double* b = P->v[P->e[i][1]];
-    const T e0 = (T)b[0] - (T)a[0], e1 = (T)b[1] - (T)a[1], e2 = (T)b[2] - (T)a[2];
-    const T w0 = p[0] - (T)a[0], w1 = p[1] - (T)a[1], w2 = p[2] - (T)a[2];
-    const T ee = (e0 * e0 + e1 * e1) + e2 * e2;
-    T t = ((w0 * e0 + w1 * e1) + w2 * e2) / ee;
-    t = t < (T)0 ? (T)0 : (t > (T)1 ? (T)1 : t);
-    const T x0 = (T)a[0] + t * e0, x1 = (T)a[1] + t * e1, x2 = (T)a[2] + t * e2;
-    const T dx = p[0] - x0, dy = p[1] - x1, dz = p[2] - x2;
-    const T d2 = (dx * dx + dy * dy) + dz * dz;
-    if (d2 < dmin2) {
-      dmin2 = d2;
-      face_hit = -1;
-      c0 = x0;
-      c1 = x1;
-      c2 = x2;
-    }
-  }
-  const T d = sqrt(dmin2);
+  const T d = face_hit >= 0 ? dface : sqrt(dmin2);
   if (gb) {
     if (face_hit >= 0) {
-      for (int k = 0; k < 3; ++k) gb[k] = (T)P->pl[face_hit][k];
+      for (int k = 0; k < 3; ++k) gb[k] = poly_plane(P, face_hit, T())[k];
     } else {
       gb[0] = (p[0] - c0) / d;
       gb[1] = (p[1] - c1) / d;
@@ -264,6 +305,16 @@ __device__ inline T poly_sdf_unit(const PolyDev* P, const T* p, T* gb, T far) {
   return d;
 }
 
+// poly_sdf_unit for polyhedron type t of the table: when every active lane
+// of the wavefront asks for the same type, the table address is uniform.
+template <typename T>
+__device__ inline T poly_sdf(const PolyDev* table, int t, const T* p, T* gb, T far) {
+  CPoly* base = (CPoly*)table;
+  const int t0 = __builtin_amdgcn_readfirstlane(t);
+  if (__ballot(t != t0) == 0) return poly_sdf_unit<T>(base + t0, p, gb, far);
+  return poly_sdf_unit<T>(base + t, p, gb, far);
+}
+
 // Exact signed distance (negative inside) at world offset r from the centre.
 // sphere: |r| - radius.  cube (edge a): body offset p = R^T r,
 // q_k = |p_k| - a/2, d = |max(q, 0)| + min(max_k q_k, 0).
@@ -271,11 +322,12 @@ __device__ inline double sdf(int shape, double size, const double* R,
                              double r0, double r1, double r2,
                              const PolyDev* poly) {
   if (poly && shape >= POLY0) {
+    const double is = 1.0 / size;
     double p[3];
-    p[0] = (R[0] * r0 + R[3] * r1 + R[6] * r2) / size;
-    p[1] = (R[1] * r0 + R[4] * r1 + R[7] * r2) / size;
-    p[2] = (R[2] * r0 + R[5] * r1 + R[8] * r2) / size;
-    return size * poly_sdf_unit<double>(poly + (shape - POLY0), p, nullptr, 1e300);
+    p[0] = (R[0] * r0 + R[3] * r1 + R[6] * r2) * is;
+    p[1] = (R[1] * r0 + R[4] * r1 + R[7] * r2) * is;
+    p[2] = (R[2] * r0 + R[5] * r1 + R[8] * r2) * is;
+    return size * poly_sdf<double>(poly, shape - POLY0, p, nullptr, 1e300);
   }
   if (shape == 2) {
     const double p0 = R[0] * r0 + R[3] * r1 + R[6] * r2;
@@ -307,11 +359,12 @@ __device__ inline float sdf32(int shape, float size, const double* R, float r0,
   if (shape == 0) return sqrtf(r0 * r0 + r1 * r1 + r2 * r2) - size;
   if (poly && shape >= POLY0) {
     // beyond 1.5 cells outside only the sign of d - eps/2 matters here
+    const float is = 1.0f / size;
     float p[3];
-    p[0] = ((float)R[0] * r0 + (float)R[3] * r1 + (float)R[6] * r2) / size;
-    p[1] = ((float)R[1] * r0 + (float)R[4] * r1 + (float)R[7] * r2) / size;
-    p[2] = ((float)R[2] * r0 + (float)R[5] * r1 + (float)R[8] * r2) / size;
-    return size * poly_sdf_unit<float>(poly + (shape - POLY0), p, nullptr, 1.5f / size);
+    p[0] = ((float)R[0] * r0 + (float)R[3] * r1 + (float)R[6] * r2) * is;
+    p[1] = ((float)R[1] * r0 + (float)R[4] * r1 + (float)R[7] * r2) * is;
+    p[2] = ((float)R[2] * r0 + (float)R[5] * r1 + (float)R[8] * r2) * is;
+    return size * poly_sdf<float>(poly, shape - POLY0, p, nullptr, 1.5f * is);
   }
   const float h = 0.5f * size;
   const float p0 = (float)R[0] * r0 + (float)R[3] * r1 + (float)R[6] * r2;
@@ -326,15 +379,16 @@ __device__ inline float sdf32(int shape, float size, const double* R, float r0,
 // As sdf32, with the rotation already in FP32 and the hardware square root
 // (within 1 ulp; used for screening against an error bound).
 __device__ inline float sdf32_r(int shape, float size, const float* R, float r0,
-                                float r1, float r2, const PolyDev* poly) {
+                                float r1, float r2, const PolyDev* poly, float far) {
   if (shape == 0) return __builtin_amdgcn_sqrtf(r0 * r0 + r1 * r1 + r2 * r2) - size;
   if (poly && shape >= POLY0) {
-    // beyond 1.5 cells outside the lower bound settles both thresholds
+    // beyond far cells outside the plane lower bound is returned
+    const float is = 1.0f / size;
     float p[3];
-    p[0] = (R[0] * r0 + R[3] * r1 + R[6] * r2) / size;
-    p[1] = (R[1] * r0 + R[4] * r1 + R[7] * r2) / size;
-    p[2] = (R[2] * r0 + R[5] * r1 + R[8] * r2) / size;
-    return size * poly_sdf_unit<float>(poly + (shape - POLY0), p, nullptr, 1.5f / size);
+    p[0] = (R[0] * r0 + R[3] * r1 + R[6] * r2) * is;
+    p[1] = (R[1] * r0 + R[4] * r1 + R[7] * r2) * is;
+    p[2] = (R[2] * r0 + R[5] * r1 + R[8] * r2) * is;
+    return size * poly_sdf<float>(poly, shape - POLY0, p, nullptr, far * is);
   }
   const float h = 0.5f * size;
   const float p0 = R[0] * r0 + R[3] * r1 + R[6] * r2;
@@ -353,10 +407,11 @@ __device__ inline float sdf32_r(int shape, float size, const float* R, float r0,
 __device__ inline double sdf_grad(int shape, double size, const double* R,
                                   const double* r, double* g, const PolyDev* poly) {
   if (poly && shape >= POLY0) {
+    const double is = 1.0 / size;
     double p[3], gb[3];
     #pragma unroll
-    for (int k = 0; k < 3; ++k) p[k] = (R[0 + k] * r[0] + R[3 + k] * r[1] + R[6 + k] * r[2]) / size;
-    const double d = size * poly_sdf_unit<double>(poly + (shape - POLY0), p, gb, 1e300);
+    for (int k = 0; k < 3; ++k) p[k] = (R[0 + k] * r[0] + R[3 + k] * r[1] + R[6 + k] * r[2]) * is;
+    const double d = size * poly_sdf<double>(poly, shape - POLY0, p, gb, 1e300);
     #pragma unroll
     for (int k = 0; k < 3; ++k)
       g[k] = R[3 * k + 0] * gb[0] + R[3 * k + 1] * gb[1] + R[3 * k + 2] * gb[2];

@@ -121,10 +121,12 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
     const float f0 = minimg_f(fxf - xr[0], Lxf, true);
     const float f1 = minimg_f(fyf - xr[1], Lyf, true);
     const float f2 = minimg_f(fzf - xr[2], Lzf, perz);
-    const float d = sdf32_r(shape, size, xr + 3, f0, f1, f2, POLY ? P.poly : nullptr);
     const float rc = POLY && shape >= POLY0 ? (float)P.poly[shape - POLY0].rc * size
                                     : (shape == 1 ? 0.8660254f * size : size);
     const float tol = 1e-3f + 1e-5f * (1.7320508f * (rc + 2.0f) + size);
+    // a polyhedron's plane lower bound beyond both thresholds ends its search
+    const float d = sdf32_r(shape, size, xr + 3, f0, f1, f2, POLY ? P.poly : nullptr,
+                            fmaxf(ot, dt) + tol);
     const uint64_t bit = 1ull << c;
     if (d < ot + tol) {
       pown |= bit;

@@ -206,7 +206,7 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
       ext[k] = 0.5 * size * (fabs(R[3 * k]) + fabs(R[3 * k + 1]) + fabs(R[3 * k + 2])) ;
     if (shape >= POLY0) {
       // largest |world coordinate| of a vertex along axis k
-      const PolyDev* pd = P.poly + (shape - POLY0);
+      CPoly* pd = (CPoly*)P.poly + (shape - POLY0);
       double e = 0.0;
       for (int i = 0; i < pd->nv; ++i) {
         const double c = fabs((R[3 * k] * pd->v[i][0] + R[3 * k + 1] * pd->v[i][1]) +
@@ -238,7 +238,21 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
       const double rc[3] = {minimg(tx * DX + 0.5 * (DX - 1) - X[0], L[0], true),
                             minimg(ty * DY + 0.5 * (DY - 1) - X[1], L[1], true),
                             minimg(tz * DZ + 0.5 * (DZ - 1) - X[2], L[2], per[2])};
-      if (sdf(shape, size, R, rc[0], rc[1], rc[2], P.poly) > reach) continue;
+      if (shape >= POLY0) {
+        // FP32 with its error bound (as in the detection's screening), the
+        // plane lower bound ending the search beyond reach
+        const float is = 1.0f / (float)size;
+        float pb[3];
+        for (int k = 0; k < 3; ++k)
+          pb[k] = ((float)R[k] * (float)rc[0] + (float)R[3 + k] * (float)rc[1] +
+                   (float)R[6 + k] * (float)rc[2]) * is;
+        const float d = (float)size * poly_sdf<float>(P.poly, shape - POLY0, pb, nullptr,
+                                                      (float)reach * is);
+        const double tol = 1e-3 + 1e-5 * (fabs(rc[0]) + fabs(rc[1]) + fabs(rc[2]) + size);
+        if ((double)d > reach + tol) continue;
+      } else if (sdf(shape, size, R, rc[0], rc[1], rc[2], P.poly) > reach) {
+        continue;
+      }
       const long long tile = tx + (long long)g.dtx * (ty + (long long)g.dty * tz);
       const int slot = atomicAdd(&tl.dcount[tile], 1);
       if (slot < g.tile_cap) tl.dlist[tile * g.tile_cap + slot] = ip;
