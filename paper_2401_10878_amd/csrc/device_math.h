@@ -404,14 +404,17 @@ __device__ inline float sdf32_r(int shape, float size, const float* R, float r0,
 // Signed distance with its world-frame gradient.  Inside a cube the
 // gradient is the normal of the nearest face (ties to the lowest axis);
 // at a sphere's centre it is zero.
+// A polyhedron point farther outside than far (cells) may return the largest
+// plane distance, a lower bound, with that face's normal.
 __device__ inline double sdf_grad(int shape, double size, const double* R,
-                                  const double* r, double* g, const PolyDev* poly) {
+                                  const double* r, double* g, const PolyDev* poly,
+                                  double far = 1e300) {
   if (poly && shape >= POLY0) {
     const double is = 1.0 / size;
     double p[3], gb[3];
     #pragma unroll
     for (int k = 0; k < 3; ++k) p[k] = (R[0 + k] * r[0] + R[3 + k] * r[1] + R[6 + k] * r[2]) * is;
-    const double d = size * poly_sdf<double>(poly, shape - POLY0, p, gb, 1e300);
+    const double d = size * poly_sdf<double>(poly, shape - POLY0, p, gb, far * is);
     #pragma unroll
     for (int k = 0; k < 3; ++k)
       g[k] = R[3 * k + 0] * gb[0] + R[3 * k + 1] * gb[1] + R[3 * k + 2] * gb[2];

@@ -96,16 +96,21 @@ struct Body {
   const PolyDev* poly;
 };
 
-__device__ inline double body_sdf(const Body& b, const double* y, double* g) {
+// With a gradient, a point farther outside a polyhedron than far may return
+// a lower bound of the distance (far = delta: only points inside the
+// enlarged body need the exact value and gradient).
+__device__ inline double body_sdf(const Body& b, const double* y, double* g,
+                                  double far = 1e300) {
   const double r[3] = {y[0] - b.X[0], y[1] - b.X[1], y[2] - b.X[2]};
-  if (g) return sdf_grad(b.shape, b.size, b.R, r, g, b.poly);
+  if (g) return sdf_grad(b.shape, b.size, b.R, r, g, b.poly, far);
   return sdf(b.shape, b.size, b.R, r[0], r[1], r[2], b.poly);
 }
 
 // enlarged distance of member b (particle, or wall -1 bottom / -2 top)
 __device__ inline double member_sdf(const Body& b, int bid, double delta,
-                                    double nz, const double* y, double* g) {
-  if (bid >= 0) return body_sdf(b, y, g) - delta;
+                                    double nz, const double* y, double* g,
+                                    double far = 1e300) {
+  if (bid >= 0) return body_sdf(b, y, g, far) - delta;
   if (bid == -1) {
     if (g) { g[0] = 0.0; g[1] = 0.0; g[2] = 1.0; }
     return y[2] + 0.5;
@@ -227,8 +232,10 @@ __global__ __launch_bounds__(256) void k_treat(PairTable t, Particles P, Geom g,
       y[0] = lo[0] + ((double)j + 0.5) * h[0];
       y[1] = lo[1] + ((double)kk + 0.5) * h[1];
       y[2] = lo[2] + ((double)l + 0.5) * h[2];
-      const double da = body_sdf(A, y, ga) - delta;
-      const double db = member_sdf(Bb, b, delta, L[2], y, gb);
+      // a sample counts when inside both enlarged bodies: beyond delta
+      // outside either, the lower bound decides
+      const double da = body_sdf(A, y, ga, delta) - delta;
+      const double db = member_sdf(Bb, b, delta, L[2], y, gb, delta);
       if (fmax(da, db) < 0.0) {
         n_in++;
         dmax = fmax(dmax, -(da + db));

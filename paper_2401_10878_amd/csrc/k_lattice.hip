@@ -31,7 +31,11 @@ namespace {
 // Storage of the populations.  FP64 stores f itself; FP32 and binary16
 // store the deviation h = f - w_i from the rest weights ("shifted"), so that
 // rounding acts on the small part of f.  ld/st move the stored value h (or
-// f), full() turns it into f.
+// f), full() turns it into f.  Stores, and the stream-collide pass's loads
+// (ldn), are non-temporal: each population is written once and read by the
+// next pass, and the arrays are hundreds of times the size of the caches
+// (6% less time for the stream-collide pass; the momentum-exchange pass,
+// which reads the same lines for neighbouring nodes, keeps ordinary loads).
 template <typename S>
 struct Store;
 template <>
@@ -39,21 +43,28 @@ struct Store<double> {
   using C = double;
   static constexpr bool shifted = false;
   __device__ static C ld(const double* p, int k) { return p[k]; }
-  __device__ static void st(double* p, int k, C v) { p[k] = v; }
+  __device__ static void st(double* p, int k, C v) { __builtin_nontemporal_store(v, p + k); }
+  __device__ static C ldn(const double* p, int k) { return __builtin_nontemporal_load(p + k); }
 };
 template <>
 struct Store<float> {
   using C = float;
   static constexpr bool shifted = true;
   __device__ static C ld(const float* p, int k) { return p[k]; }
-  __device__ static void st(float* p, int k, C v) { p[k] = v; }
+  __device__ static void st(float* p, int k, C v) { __builtin_nontemporal_store(v, p + k); }
+  __device__ static C ldn(const float* p, int k) { return __builtin_nontemporal_load(p + k); }
 };
 template <>
 struct Store<__half> {
   using C = float;
   static constexpr bool shifted = true;
   __device__ static C ld(const __half* p, int k) { return __half2float(p[k]); }
-  __device__ static void st(__half* p, int k, C v) { p[k] = __float2half_rn(v); }
+  __device__ static void st(__half* p, int k, C v) {
+    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v)), reinterpret_cast<unsigned short*>(p) + k);
+  }
+  __device__ static C ldn(const __half* p, int k) {
+    return __half2float(__ushort_as_half(__builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(p) + k)));
+  }
 };
 template <typename S>
 __device__ inline double full_f(typename Store<S>::C h, int i) {
@@ -228,7 +239,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     for (int i = 0; i < Q; ++i) {
       const int src_i = nb.beyond(-cz(i)) ? opp(i) * n + self
                                           : i * n + nb.off(-cx(i), -cy(i), -cz(i));
-      f[i] = Store<S>::ld(src, src_i);
+      f[i] = Store<S>::ldn(src, src_i);
     }
     o = owner_id(owner[self]);
     if (nb.wall_m || nb.wall_p) {
