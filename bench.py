@@ -145,14 +145,20 @@ def cpu_baseline(wl, steps):
         O.define_polyhedron(k, P.vertices, P.faces)
     s = O.OracleSim(wl.params, wl.scene)
     s.init_equilibrium()
-    t0 = time.perf_counter()
-    s.step(steps)
-    t1 = time.perf_counter()
+    # one step per call, so that the flagged contact cells of each step can
+    # be read between the timed calls
+    wall, cells = 0.0, 0
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        s.step(1)
+        wall += time.perf_counter() - t0
+        cells += s.counters()[1]
     ncell = wl.params.nx * wl.params.ny * wl.params.nz
-    res = dict(value=round(ncell * steps / (t1 - t0) / 1e6, 3), unit="MLUPS",
+    res = dict(value=round(ncell * steps / wall / 1e6, 3), unit="MLUPS",
                cores=O.threads(), kind="oracle",
+               contact_cells_per_s=round(cells / wall, 1),
                sample=f"{wl.name}: {steps} coupled FP64 steps after the prologue "
-                      f"({ncell} nodes, {wl.scene.n} particles), {t1 - t0:.1f} s")
+                      f"({ncell} nodes, {wl.scene.n} particles), {wall:.1f} s")
     s.close()
     return res
 
@@ -222,7 +228,9 @@ def main():
                 unit="GB/s", frac=round(achieved / PEAK_HBM_GBS, 4),
                 traffic=traffic, kernel="k_lattice",
                 bytes_per_launch=main_res["bytes_alg"],
-                avg_launch_ms=round(lat_ms, 5))
+                avg_launch_ms=round(lat_ms, 5),
+                # measured HBM bytes (rocprofv3 counters) over the same time
+                traffic_gbs=None if traffic is None else round(traffic / (lat_ms * 1e6), 1))
     mea_ms = main_res["kernel_ms_per_step"]["mea"]
     mea_read = traffic_for(args.precision, "mea_per_precision", "read_bytes")
     mea = dict(kernel="k_mea", avg_launch_ms=round(mea_ms, 5),
@@ -242,6 +250,13 @@ def main():
                     graph=bool(args.graph)),
         contact_cells_per_s=round(main_res["contact_cells_per_s"], 1),
         detected_pairs=main_res["pairs"], overlap_cells=main_res["overlap_cells"],
+        # the contact treatment alone: its kernel time, and midpoint samples
+        # (6 n_c^2 box-correction + n_c^3 integration per pair, two bodies
+        # each) per second at the last step's pair count
+        contact_kernel_ms_per_step=round(main_res["kernel_ms_per_step"]["treat"], 5),
+        contact_samples_per_s=round(
+            main_res["pairs"] * (6 * p.n_c ** 2 + p.n_c ** 3)
+            / (main_res["kernel_ms_per_step"]["treat"] * 1e-3), 1),
         kernel_ms_per_step={k: round(v, 5) for k, v in
                             main_res["kernel_ms_per_step"].items()},
         graph_ms_per_step=None if graph_ms is None else round(graph_ms, 4),
