@@ -358,13 +358,14 @@ __device__ inline float sdf32(int shape, float size, const double* R, float r0,
                               float r1, float r2, const PolyDev* poly) {
   if (shape == 0) return sqrtf(r0 * r0 + r1 * r1 + r2 * r2) - size;
   if (poly && shape >= POLY0) {
-    // beyond 1.5 cells outside only the sign of d - eps/2 matters here
+    // exact at every distance (its callers evaluate nodes already known to
+    // lie within eps/2 of the body)
     const float is = 1.0f / size;
     float p[3];
     p[0] = ((float)R[0] * r0 + (float)R[3] * r1 + (float)R[6] * r2) * is;
     p[1] = ((float)R[1] * r0 + (float)R[4] * r1 + (float)R[7] * r2) * is;
     p[2] = ((float)R[2] * r0 + (float)R[5] * r1 + (float)R[8] * r2) * is;
-    return size * poly_sdf<float>(poly, shape - POLY0, p, nullptr, 1.5f * is);
+    return size * poly_sdf<float>(poly, shape - POLY0, p, nullptr, 1e30f);
   }
   const float h = 0.5f * size;
   const float p0 = (float)R[0] * r0 + (float)R[3] * r1 + (float)R[6] * r2;

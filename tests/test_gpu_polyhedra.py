@@ -42,20 +42,22 @@ def _rel(a, b, floor):
     return np.abs(a - b).max() / max(np.abs(b).max(), floor) if b.size else 0.0
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_polyhedra_parity(O, W, H, prec):
+@pytest.mark.parametrize("prec,eps", [(0, 1.0), (1, 1.0), (0, 3.5), (1, 3.5)])
+def test_polyhedra_parity(O, W, H, prec, eps):
+    """eps = 3.5: a coupling band reaching 1.75 cells out, beyond which
+    screening forms may stop at the plane lower bound."""
     seed, dims, n = 43, (30, 26, 22), 9
     polys, sc = _scene(O, W, seed, dims, n)
     assert (sc.shape >= W.POLY0).sum() >= 5
     p = W.Params(nx=dims[0], ny=dims[1], nz=dims[2], periodic_z=1, tau=0.7,
                  gravity=(0.0, 0.0, -2e-4), balance=1, young=0.4, u_k=3e-4,
-                 max_pairs=256, tile_capacity=16, precision=prec)
+                 max_pairs=256, tile_capacity=16, precision=prec, eps_b=eps)
     f0 = W.perturbed_populations(seed, dims, O.feq(1.0, [0.003, 0.002, -0.001]), amp=0.01)
     o = O.OracleSim(p.replace(precision=0), sc)
     g = H.Simulation(p, sc, polyhedra=polys)
     o.set_populations(f0)
     g.set_populations(f0)
-    _say("polyhedra precision", prec)
+    _say("polyhedra precision", prec, "eps", eps)
     assert np.array_equal(g.fields()["owner"], o.fields()["owner"])
     oc = o.contacts()
     assert any(sc.shape[c["a"]] >= W.POLY0 for c in oc)
