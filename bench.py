@@ -30,11 +30,16 @@ DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f16-storage/f32-compute"}
 VALUE_BYTES = {0: 8, 1: 4, 2: 2}
 W_POLY0 = 3                    # shape code of the first polyhedron type
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lattice_k_mea_c3_traffic.json")
-LATTICE_SRC = os.path.join(ROOT, "paper_2401_10878_amd", "csrc", "k_lattice.hip")
+# the sources the stream-collide and momentum-exchange kernels are built from
+LATTICE_SRC = [os.path.join(ROOT, "paper_2401_10878_amd", "csrc", f)
+               for f in ("k_lattice.hip", "device_math.h", "context.h")]
 
 
 def lattice_source_hash():
-    return hashlib.sha256(open(LATTICE_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in LATTICE_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_for(prec_name, section="per_precision", field="bytes_per_launch"):

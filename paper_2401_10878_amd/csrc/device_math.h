@@ -126,17 +126,19 @@ __device__ inline void quat_to_rot(const double* q, double* R) {
 }
 
 // Minimal image of a coordinate difference on an axis of length L.
+// (selects rather than branches: per-lane branches here cost exec-mask
+// bookkeeping on every axis of every candidate)
 __device__ inline double minimg(double v, double L, bool periodic) {
-  if (!periodic) return v;
-  if (v >= 0.5 * L) return v - L;
-  if (v < -0.5 * L) return v + L;
-  return v;
+  const double lo = v + L, hi = v - L;
+  double r = (periodic && v >= 0.5 * L) ? hi : v;
+  r = (periodic && v < -0.5 * L) ? lo : r;
+  return r;
 }
 __device__ inline float minimg_f(float v, float L, bool periodic) {
-  if (!periodic) return v;
-  if (v >= 0.5f * L) return v - L;
-  if (v < -0.5f * L) return v + L;
-  return v;
+  const float lo = v + L, hi = v - L;
+  float r = (periodic && v >= 0.5f * L) ? hi : v;
+  r = (periodic && v < -0.5f * L) ? lo : r;
+  return r;
 }
 __device__ inline int image_shift(double v, double L, bool periodic) {
   if (!periodic) return 0;
