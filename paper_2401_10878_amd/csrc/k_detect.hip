@@ -127,16 +127,14 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
     // a polyhedron's plane lower bound beyond both thresholds ends its search
     const float d = sdf32_r(shape, size, xr + 3, f0, f1, f2, POLY ? P.poly : nullptr,
                             fmaxf(ot, dt) + tol);
+    // (selects, not branches: the bookkeeping runs for every candidate)
     const uint64_t bit = 1ull << c;
-    if (d < ot + tol) {
-      pown |= bit;
-      bp = p;
-      if (d > ot - tol) near_own = true;
-    }
-    if (d < dt + tol) {
-      mask |= bit;
-      if (d > dt - tol) dun |= bit;
-    }
+    const bool may_own = d < ot + tol, may_det = d < dt + tol;
+    pown |= may_own ? bit : 0ull;
+    bp = may_own ? p : bp;
+    near_own = near_own || (may_own && d > ot - tol);
+    mask |= may_det ? bit : 0ull;
+    dun |= (may_det && d > dt - tol) ? bit : 0ull;
   }
   // Pass 2, FP64, only where pass 1 did not settle: the owner when two or
   // more candidates may own the node or one lies within tol of eps/2
