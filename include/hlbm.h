@@ -175,7 +175,12 @@ hlbm_status hlbm_set_populations(hlbm_ctx *ctx, const double *f);
 /* Advance nsteps coupled time steps (asynchronous on the context stream).
    Order per step (Algorithm 1, one sub-step): contact treatment, gravity and
    Newton-Euler update, particle-to-fluid coupling with rough detection,
-   collide-and-stream with the fluid-to-particle momentum exchange. */
+   collide-and-stream with the fluid-to-particle momentum exchange.  With one
+   contact sub-step, and neither a graph nor timing in use, the contact
+   treatment of every step after the first of a call runs on a second stream
+   of the context beside the previous step's lattice passes (it reads nothing
+   they write); the call ends with no such work pending, and the results are
+   those of strictly ordered steps, bit for bit. */
 hlbm_status hlbm_step(hlbm_ctx *ctx, int nsteps);
 
 /* Use (1) or stop using (0) a captured HIP graph for hlbm_step. */
@@ -185,8 +190,8 @@ hlbm_status hlbm_use_graph(hlbm_ctx *ctx, int on);
    context stream around each of its seven kernel launches (bookkeeping
    clear, contact treatment, particle motion + tile binning, contact
    carry-over, coupling map + rough detection, stream-collide lattice pass,
-   momentum exchange) for up to max_steps steps (graphs are bypassed
-   meanwhile).  hlbm_timing_end synchronises and returns the summed
+   momentum exchange) for up to max_steps steps (graphs and the overlapped
+   contact treatment are bypassed meanwhile).  hlbm_timing_end synchronises and returns the summed
    milliseconds per kernel in that order, kernel_ms[7], and the number of
    timed steps. */
 hlbm_status hlbm_timing_begin(hlbm_ctx *ctx, int max_steps);

@@ -122,7 +122,7 @@ hlbm_status prologue(Ctx& c) {
   drop_graphs(c);
   const int p = c.tcur;
   const size_t nb = sizeof(double) * 3 * (c.np > 0 ? c.np : 1);
-  HIPCHECK(launch_clear_step(c, c.tab[p]));
+  HIPCHECK(launch_clear_step(c, c.tab[p], CLEAR_CONTACT | CLEAR_TILES, c.stream));
   HIPCHECK(hipMemsetAsync(c.Fh, 0, nb, c.stream));
   HIPCHECK(hipMemsetAsync(c.Th, 0, nb, c.stream));
   HIPCHECK(hipMemsetAsync(c.tl.ovf, 0, 2 * nb, c.stream));
@@ -138,7 +138,15 @@ hlbm_status prologue(Ctx& c) {
 // The launch sequence of one time step with population parity p (buffers
 // p -> 1-p) starting from contact table t; the table parity flips once per
 // sub-step.  ev (optional): 3 + 5 n_sub events recorded around the launches.
-hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev) {
+// Overlap (one sub-step only): the contact treatment of a step reads the
+// particle state and the pair table the previous step's detection left, and
+// nothing that the stream-collide or momentum-exchange pass writes, so it
+// can run beside them on the side stream.  pre & PRE_DONE: this step's
+// treatment already ran there (wait for it, then clear the tile counts the
+// previous momentum-exchange pass read); pre & PRE_NEXT: after detection,
+// start the next step's treatment on the side stream.
+constexpr int PRE_DONE = 1, PRE_NEXT = 2;
+hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev, int pre) {
   hipError_t e;
   int m = 0;
   auto mark = [&]() -> hipError_t {
@@ -146,9 +154,16 @@ hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev) {
   };
   if ((e = mark())) return e;
   for (int s = 0; s < c.n_sub; ++s) {
-    if ((e = launch_clear_step(c, c.tab[1 - t]))) return e;
-    if ((e = mark())) return e;
-    if ((e = launch_treat(c, c.tab[t]))) return e;
+    if (s == 0 && (pre & PRE_DONE)) {
+      if ((e = hipStreamWaitEvent(c.stream, c.ev_treat, 0))) return e;
+      if ((e = launch_clear_step(c, c.tab[1 - t], CLEAR_TILES, c.stream))) return e;
+      if ((e = mark())) return e;
+    } else {
+      if ((e = launch_clear_step(c, c.tab[1 - t], CLEAR_CONTACT | CLEAR_TILES, c.stream)))
+        return e;
+      if ((e = mark())) return e;
+      if ((e = launch_treat(c, c.tab[t], c.stream))) return e;
+    }
     if ((e = mark())) return e;
     if ((e = launch_particles(c, s == 0 ? 1 : 2))) return e;
     if ((e = mark())) return e;
@@ -158,6 +173,15 @@ hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev) {
     if ((e = mark())) return e;
     t = 1 - t;
   }
+  if (pre & PRE_NEXT) {
+    // the next step's clear of its contact state and its treatment of
+    // table t (the one detection just filled)
+    if ((e = hipEventRecord(c.ev_det, c.stream))) return e;
+    if ((e = hipStreamWaitEvent(c.side, c.ev_det, 0))) return e;
+    if ((e = launch_clear_step(c, c.tab[1 - t], CLEAR_CONTACT, c.side))) return e;
+    if ((e = launch_treat(c, c.tab[t], c.side))) return e;
+    if ((e = hipEventRecord(c.ev_treat, c.side))) return e;
+  }
   if ((e = launch_lattice(c, c.fbuf[p], c.fbuf[1 - p]))) return e;
   if (c.ph.bal_mode == 2 && (e = launch_balance(c, nullptr, 0))) return e;
   if ((e = mark())) return e;
@@ -166,8 +190,8 @@ hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev) {
 }
 
 // the step that the next hlbm_step would run, and the parities after it
-hipError_t run_step(Ctx& c, hipEvent_t* ev) {
-  hipError_t e = enqueue_step(c, c.cur, c.tcur, ev);
+hipError_t run_step(Ctx& c, hipEvent_t* ev, int pre = 0) {
+  hipError_t e = enqueue_step(c, c.cur, c.tcur, ev, pre);
   c.cur = 1 - c.cur;
   c.tcur = (c.n_sub & 1) ? 1 - c.tcur : c.tcur;
   c.step++;
@@ -340,6 +364,15 @@ hlbm_status hlbm_create(const hlbm_params* params, void* stream, hlbm_ctx** out)
       return HLBM_E_DEVICE;
     }
     c.own_stream = true;
+  }
+  if (hipStreamCreate(&c.side) != hipSuccess ||
+      hipEventCreateWithFlags(&c.ev_det, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c.ev_treat, hipEventDisableTiming) != hipSuccess) {
+    if (c.side) hipStreamDestroy(c.side);
+    if (c.ev_det) hipEventDestroy(c.ev_det);
+    if (c.own_stream) hipStreamDestroy(c.stream);
+    delete h;
+    return HLBM_E_DEVICE;
   }
   const long long ndt = (long long)c.g.dtx * c.g.dty * c.g.dtz;
   const long long nlt = (long long)c.g.ltx * c.g.lty * c.g.ltz;
@@ -779,7 +812,7 @@ hlbm_status hlbm_step(hlbm_ctx* h, int nsteps) {
       if (!c.graph_ready[key]) {
         hipGraph_t gr;
         HIPCHECK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue_step(c, c.cur, c.tcur, nullptr);
+        hipError_t e = enqueue_step(c, c.cur, c.tcur, nullptr, 0);
         hipError_t e2 = hipStreamEndCapture(c.stream, &gr);
         if (e != hipSuccess || e2 != hipSuccess)
           return fail(c, HLBM_E_DEVICE, "graph capture: %s",
@@ -795,7 +828,12 @@ hlbm_status hlbm_step(hlbm_ctx* h, int nsteps) {
       c.tcur = (c.n_sub & 1) ? 1 - c.tcur : c.tcur;
       c.step++;
     } else {
-      HIPCHECK(run_step(c, nullptr));
+      // steps of one call after the first overlap their contact treatment
+      // with the previous step's lattice passes; the last step leaves none
+      // pending, so the state after the call is that of whole steps
+      const bool ovl = c.n_sub == 1 && c.side != nullptr;
+      const int pre = (ovl && s > 0 ? PRE_DONE : 0) | (ovl && s + 1 < nsteps ? PRE_NEXT : 0);
+      HIPCHECK(run_step(c, nullptr, pre));
     }
   }
   return HLBM_OK;
@@ -1316,6 +1354,12 @@ void hlbm_destroy(hlbm_ctx* h) {
     if (c.tab[k].keys) hipFree(c.tab[k].keys);
     if (c.tab[k].rec) hipFree(c.tab[k].rec);
   }
+  if (c.side) {
+    hipStreamSynchronize(c.side);
+    hipStreamDestroy(c.side);
+  }
+  if (c.ev_det) hipEventDestroy(c.ev_det);
+  if (c.ev_treat) hipEventDestroy(c.ev_treat);
   if (c.own_stream && c.stream) hipStreamDestroy(c.stream);
   delete h;
 }

@@ -156,6 +156,11 @@ struct Ctx {
   Phys ph;
   hipStream_t stream;
   bool own_stream;
+  // second stream for the next step's contact treatment, which overlaps the
+  // stream-collide and momentum-exchange passes (ev_det: detection done on
+  // `stream`; ev_treat: treatment done on `side`)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_det = nullptr, ev_treat = nullptr;
   int precision;
   size_t bytes_per_value;
   // populations (two buffers, ping-pong); fbuf[cur] holds f* of the last step
@@ -210,7 +215,10 @@ struct Ctx {
 };
 
 // ---- launch wrappers (kernels live in the .hip files) --------------------
-hipError_t launch_clear_step(Ctx& c, PairTable next);
+// what: CLEAR_CONTACT (next pair table, contact forces and slots, detection
+// counters) and/or CLEAR_TILES (detection-tile and lattice-block counts)
+constexpr int CLEAR_CONTACT = 1, CLEAR_TILES = 2;
+hipError_t launch_clear_step(Ctx& c, PairTable next, int what, hipStream_t s);
 // move: 0 bin only, 1 gather the hydrodynamic force and move, 2 move with
 // the stored hydrodynamic force (later sub-steps)
 hipError_t launch_particles(Ctx& c, int move);
@@ -223,7 +231,7 @@ hipError_t launch_mea(Ctx& c, const void* fstar);
 // balance mode 2: lattice mass and momentum of f at the start (init = 1), or
 // the controller update after a collision from the lattice pass's block sums
 hipError_t launch_balance(Ctx& c, const void* f, int init);
-hipError_t launch_treat(Ctx& c, PairTable t);
+hipError_t launch_treat(Ctx& c, PairTable t, hipStream_t s);
 hipError_t launch_fill_equilibrium(Ctx& c, void* f, double rho,
                                    const double u[3]);
 hipError_t launch_store_direction(Ctx& c, void* f, int i, const double* src);

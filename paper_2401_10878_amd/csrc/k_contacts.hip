@@ -25,9 +25,14 @@ namespace {
 
 __global__ void k_clear_step(PairTable next, double* Fc, double* Tc, int np,
                              int* dcount, long long ndt, int* lcount,
-                             long long nlt, int* ccount, Counters* ctr) {
+                             long long nlt, int* ccount, Counters* ctr, int what) {
   const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long stride = (long long)gridDim.x * blockDim.x;
+  if (what & CLEAR_TILES) {
+    for (long long i = tid; i < ndt; i += stride) dcount[i] = 0;
+    for (long long i = tid; i < nlt; i += stride) lcount[i] = 0;
+  }
+  if (!(what & CLEAR_CONTACT)) return;
   for (long long i = tid; i < next.cap; i += stride) {
     next.keys[i] = EMPTY_KEY;
     PairRec r = {};
@@ -37,8 +42,6 @@ __global__ void k_clear_step(PairTable next, double* Fc, double* Tc, int np,
     }
     next.rec[i] = r;
   }
-  for (long long i = tid; i < ndt; i += stride) dcount[i] = 0;
-  for (long long i = tid; i < nlt; i += stride) lcount[i] = 0;
   for (long long i = tid; i < 3LL * np; i += stride) {
     Fc[i] = 0.0;
     Tc[i] = 0.0;
@@ -347,7 +350,7 @@ __global__ __launch_bounds__(256) void k_treat(PairTable t, Particles P, Geom g,
 
 }  // namespace
 
-hipError_t launch_clear_step(Ctx& c, PairTable next) {
+hipError_t launch_clear_step(Ctx& c, PairTable next, int what, hipStream_t s) {
   const long long ndt = (long long)c.g.dtx * c.g.dty * c.g.dtz;
   const long long nlt = (long long)c.g.ltx * c.g.lty * c.g.ltz;
   long long work = next.cap;
@@ -356,8 +359,8 @@ hipError_t launch_clear_step(Ctx& c, PairTable next) {
   long long blocks = (work + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_clear_step, dim3((unsigned)blocks), dim3(256), 0,
-                     c.stream, next, c.Fc, c.Tc, c.np, c.tl.dcount, ndt,
-                     c.tl.lcount, nlt, c.tl.ccount, c.counters);
+                     s, next, c.Fc, c.Tc, c.np, c.tl.dcount, ndt,
+                     c.tl.lcount, nlt, c.tl.ccount, c.counters, what);
   return hipGetLastError();
 }
 
@@ -367,13 +370,13 @@ hipError_t launch_keep(Ctx& c, PairTable from, PairTable to) {
   return hipGetLastError();
 }
 
-hipError_t launch_treat(Ctx& c, PairTable t) {
+hipError_t launch_treat(Ctx& c, PairTable t, hipStream_t s) {
   if (c.has_poly)
     hipLaunchKernelGGL(k_treat<true>, dim3((unsigned)((t.cap + 3) / 4)), dim3(256), 0,
-                     c.stream, t, c.part, c.g, c.ph, c.tl, c.counters);
+                     s, t, c.part, c.g, c.ph, c.tl, c.counters);
   else
     hipLaunchKernelGGL(k_treat<false>, dim3((unsigned)((t.cap + 3) / 4)), dim3(256), 0,
-                     c.stream, t, c.part, c.g, c.ph, c.tl, c.counters);
+                     s, t, c.part, c.g, c.ph, c.tl, c.counters);
   return hipGetLastError();
 }
 

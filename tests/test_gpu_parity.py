@@ -180,6 +180,40 @@ def test_graph_matches_stream(W, H):
         assert np.array_equal(a.fields()["owner"], b.fields()["owner"])
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_overlapped_treatment_matches_ordered_steps(W, H, prec):
+    """One call of n steps (the contact treatment of steps 2..n on the side
+    stream, beside the previous step's lattice passes) leaves the same bits
+    as n calls of one step (strictly ordered)."""
+    sc = W.random_small_scene(29, (26, 22, 20), 9, size_range=(1.8, 3.0),
+                              gap=-0.7, speed=0.01, spin=0.004)
+    p = W.Params(nx=26, ny=22, nz=20, tau=0.7, young=0.4, u_k=3e-4,
+                 gravity=(0.0, 0.0, -1e-4), balance=1,
+                 max_pairs=256, tile_capacity=16, precision=prec)
+    a = H.Simulation(p, sc)
+    b = H.Simulation(p, sc)
+    a.init_equilibrium(u=(0.002, -0.001, 0))
+    b.init_equilibrium(u=(0.002, -0.001, 0))
+    assert len(a.contacts()) > 0
+    for _ in range(3):
+        for _ in range(6):
+            a.step(1)
+        b.step(6)
+        a.sync()
+        b.sync()
+        assert np.array_equal(a.populations(), b.populations())
+        pa, pb = a.particles(), b.particles()
+        for k in pa:
+            assert np.array_equal(pa[k], pb[k]), k
+        fa, fb = a.forces(), b.forces()
+        for k in fa:
+            assert np.array_equal(fa[k], fb[k]), k
+        ca, cb = a.contacts(), b.contacts()
+        assert [_key(c) for c in ca] == [_key(c) for c in cb]
+        assert [c["count"] for c in ca] == [c["count"] for c in cb]
+        assert a.counters() == b.counters()
+
+
 def test_capacity_overflow_reported(W, H):
     """Too small a tile capacity is reported, not silently truncated."""
     sc = W.random_small_scene(3, (16, 16, 16), 6, size_range=(2.0, 3.0), gap=-0.5)
