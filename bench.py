@@ -42,16 +42,19 @@ def lattice_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(prec_name, section="per_precision", field="bytes_per_launch"):
+def traffic_for(prec_name, section="per_precision", field="bytes_per_launch",
+                workload="C3"):
     """HBM bytes per launch of the stream-collide pass (section
     per_precision) or the momentum-exchange pass (mea_per_precision) from the
     committed rocprofv3 counters, or None if the counters were taken on
-    another version of the kernels."""
+    another workload or another version of the kernels."""
     try:
         d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_sha256_16") != lattice_source_hash():
+        return None
+    if str(d.get("workload", "")).split(":")[0] != workload:
         return None
     e = d.get(section, {}).get(prec_name)
     return e.get(field) if e else None
@@ -233,7 +236,7 @@ def main():
         wl, args.precision, args.steps, args.warmup)
     lat_ms = main_res["kernel_ms_per_step"]["lattice"]
     achieved = main_res["lattice_gbs"]
-    traffic = traffic_for(args.precision)
+    traffic = traffic_for(args.precision, workload=wl.name)
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS,
                 unit="GB/s", frac=round(achieved / PEAK_HBM_GBS, 4),
                 traffic=traffic, kernel="k_lattice",
@@ -242,7 +245,7 @@ def main():
                 # measured HBM bytes (rocprofv3 counters) over the same time
                 traffic_gbs=None if traffic is None else round(traffic / (lat_ms * 1e6), 1))
     mea_ms = main_res["kernel_ms_per_step"]["mea"]
-    mea_read = traffic_for(args.precision, "mea_per_precision", "read_bytes")
+    mea_read = traffic_for(args.precision, "mea_per_precision", "read_bytes", wl.name)
     mea = dict(kernel="k_mea", avg_launch_ms=round(mea_ms, 5),
                hbm_read_bytes=mea_read,
                read_gbs=None if mea_read is None else round(mea_read / (mea_ms * 1e6), 1))

@@ -14,6 +14,14 @@ namespace hlbm {
 
 namespace {
 
+// The FP64 value of lane j (j uniform over the wavefront).
+__device__ inline double readlane_f64(double v, int j) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), j);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // A set of at most two disjoint tile intervals on one axis.
 struct TileSpan {
   int lo[2], hi[2], n;
@@ -113,15 +121,18 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
       int nc = tl.ccount[ip];
       nc = nc < MAXC ? nc : MAXC;
       const size_t e0 = (size_t)ip * MAXC;
+      // every slot's values are loaded at once (lane k: slot k) and then
+      // read from registers in rank order
       const int key = lane < nc ? tl.ckey[e0 + lane] : 0x7fffffff;
+      double cv[6];
+      for (int m = 0; m < 6; ++m) cv[m] = lane < nc ? tl.cval[6 * (e0 + lane) + m] : 0.0;
       int rank = 0;
       for (int j = 0; j < nc; ++j) rank += __builtin_amdgcn_readlane(key, j) < key ? 1 : 0;
       for (int r = 0; r < nc; ++r) {
         const int j = __ffsll((long long)__ballot(lane < nc && rank == r)) - 1;
-        const double* cv = tl.cval + 6 * (e0 + j);
         for (int m = 0; m < 3; ++m) {
-          Fcp[m] += cv[m];
-          Tcp[m] += cv[3 + m];
+          Fcp[m] += readlane_f64(cv[m], j);
+          Tcp[m] += readlane_f64(cv[3 + m], j);
         }
       }
     }
