@@ -6,13 +6,18 @@ edge 14 (phi = 0.30, s = 1.5, Ar = 1000), populations in FP32, synthetic
 seeded scene.  A step is the whole time step: contact treatment, particle
 motion and tile binning, contact carry-over, coupling map with rough
 detection, the stream-collide pass with the coupling, and the momentum
-exchange over the populations it wrote.
+exchange over the populations it wrote.  The timed steps are replayed as
+captured HIP graphs (8 steps per graph, the contact treatment of each step
+on a second stream beside the previous step's lattice passes); --stream
+times plain stream launches instead, and the line reports the other mode's
+time beside the value.
 
 Prints ONE JSON line with the metric, the roofline of the dominant kernel
 (the stream-collide pass, HBM-bound) and the FP64 CPU oracle timed on a
 bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--precision fp32|fp64|fp16s]
+                    [--workload C1|C2|C3|C3B|C4|C5] [--stream]
 """
 import argparse
 import hashlib
@@ -104,12 +109,13 @@ def run_gpu(wl, prec, steps, warmup, graph):
     return out
 
 
-def graph_ms_per_step(wl, prec, steps, warmup):
-    """Wall time per step when the step is replayed as a captured HIP graph."""
+def other_ms_per_step(wl, prec, steps, warmup, graph):
+    """Wall time per step of the other launch mode: captured HIP graphs
+    (graph=True) or stream launches."""
     import torch
     from paper_2401_10878_amd import hlbm
     sim = hlbm.Simulation(wl.params.replace(precision=PREC[prec]), wl.scene,
-                          device="cuda:0", graph=True, polyhedra=wl.polyhedra)
+                          device="cuda:0", graph=graph, polyhedra=wl.polyhedra)
     sim.init_equilibrium()
     sim.step(warmup)
     sim.sync()
@@ -198,8 +204,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", default="fp32", choices=sorted(PREC))
     ap.add_argument("--workload", default="C3", choices=["C1", "C2", "C3", "C3B", "C4", "C5"])
-    ap.add_argument("--graph", action="store_true",
-                    help="replay the step as a captured HIP graph")
+    ap.add_argument("--stream", action="store_true",
+                    help="time stream launches instead of captured HIP graphs")
     ap.add_argument("--other-precisions", type=int, default=1,
                     help="also time the other two storage precisions")
     ap.add_argument("--cpu-steps", type=int, default=10,
@@ -217,12 +223,13 @@ def main():
 
     from paper_2401_10878_amd import workloads as W
     wl = W.WORKLOADS[args.workload]()
-    main_res = run_gpu(wl, args.precision, args.steps, args.warmup, args.graph)
+    graph = not args.stream
+    main_res = run_gpu(wl, args.precision, args.steps, args.warmup, graph)
     runs = {args.precision: main_res}
     if args.other_precisions:
         for pr in PREC:
             if pr != args.precision:
-                runs[pr] = run_gpu(wl, pr, args.steps, args.warmup, args.graph)
+                runs[pr] = run_gpu(wl, pr, args.steps, args.warmup, graph)
     others = {}
     for pr, r in runs.items():
         others[pr] = dict(mlups=round(r["mlups"], 1),
@@ -232,8 +239,8 @@ def main():
             others[pr]["error_vs_fp64"] = {
                 k: float(f"{v:.3e}") for k, v in
                 error_vs_fp64(wl, r, runs["fp64"]).items()}
-    graph_ms = None if args.graph else graph_ms_per_step(
-        wl, args.precision, args.steps, args.warmup)
+    other_ms = other_ms_per_step(wl, args.precision, args.steps, args.warmup,
+                                 not graph)
     lat_ms = main_res["kernel_ms_per_step"]["lattice"]
     achieved = main_res["lattice_gbs"]
     traffic = traffic_for(args.precision, workload=wl.name)
@@ -260,7 +267,7 @@ def main():
         dtype=DTYPE[args.precision], data="synthetic",
         config=dict(workload=f"{wl.name}: {wl.note}", lattice=[p.nx, p.ny, p.nz],
                     particles=wl.scene.n, precision=args.precision,
-                    graph=bool(args.graph)),
+                    graph=graph),
         contact_cells_per_s=round(main_res["contact_cells_per_s"], 1),
         detected_pairs=main_res["pairs"], overlap_cells=main_res["overlap_cells"],
         # the contact treatment alone: its kernel time, and midpoint samples
@@ -272,7 +279,8 @@ def main():
             / (main_res["kernel_ms_per_step"]["treat"] * 1e-3), 1),
         kernel_ms_per_step={k: round(v, 5) for k, v in
                             main_res["kernel_ms_per_step"].items()},
-        graph_ms_per_step=None if graph_ms is None else round(graph_ms, 4),
+        # the other launch mode of the same workload and precision
+        **{("stream_ms_per_step" if graph else "graph_ms_per_step"): round(other_ms, 4)},
         precisions=others,
         roofline=roof,
         mea_pass=mea,

@@ -176,14 +176,18 @@ hlbm_status hlbm_set_populations(hlbm_ctx *ctx, const double *f);
    Order per step (Algorithm 1, one sub-step): contact treatment, gravity and
    Newton-Euler update, particle-to-fluid coupling with rough detection,
    collide-and-stream with the fluid-to-particle momentum exchange.  With one
-   contact sub-step, and neither a graph nor timing in use, the contact
-   treatment of every step after the first of a call runs on a second stream
-   of the context beside the previous step's lattice passes (it reads nothing
-   they write); the call ends with no such work pending, and the results are
-   those of strictly ordered steps, bit for bit. */
+   contact sub-step and no timing in use, the contact treatment of every step
+   after the first of a call runs on a second stream of the context beside
+   the previous step's lattice passes (it reads nothing they write); the call
+   ends with no such work pending, and the results are those of strictly
+   ordered steps, bit for bit. */
 hlbm_status hlbm_step(hlbm_ctx *ctx, int nsteps);
 
-/* Use (1) or stop using (0) a captured HIP graph for hlbm_step. */
+/* Use (1) or stop using (0) captured HIP graphs for hlbm_step: with one
+   contact sub-step, calls replay 8-step graphs (the overlapped contact
+   treatment captured inside) while at least 8 steps remain, and single-step
+   graphs for the rest; graphs are captured at first use per parity of the
+   population buffers and the contact tables. */
 hlbm_status hlbm_use_graph(hlbm_ctx *ctx, int on);
 
 /* Per-kernel timing of the next steps: hlbm_step records HIP events on the

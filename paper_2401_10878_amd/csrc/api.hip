@@ -112,8 +112,14 @@ void drop_graphs(Ctx& c) {
   for (int k = 0; k < 4; ++k) {
     if (c.graph_ready[k]) hipGraphExecDestroy(c.gexec[k]);
     c.graph_ready[k] = false;
+    if (c.graph_n_ready[k]) hipGraphExecDestroy(c.gexec_n[k]);
+    c.graph_n_ready[k] = false;
   }
 }
+
+// steps per multi-step graph (even: the population and table parities come
+// back to their starting values)
+constexpr int GRAPH_STEPS = 8;
 
 // Coupling and detection at the current particle state with the current
 // populations as f*: ownership map, initial contact list, and the
@@ -807,6 +813,31 @@ hlbm_status hlbm_step(hlbm_ctx* h, int nsteps) {
         return fail(c, HLBM_E_CAPACITY, "timing window of %d steps is full", c.tcap);
       HIPCHECK(run_step(c, c.tev + (size_t)c.tused * c.ev_per_step));
       c.tused++;
+    } else if (c.use_graph && c.n_sub == 1 && nsteps - s >= GRAPH_STEPS && c.side) {
+      // GRAPH_STEPS steps in one graph; the side stream joins the capture at
+      // the first fork and is joined back by the last step
+      const int key = 2 * c.cur + c.tcur;
+      if (!c.graph_n_ready[key]) {
+        hipGraph_t gr;
+        HIPCHECK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int j = 0; j < GRAPH_STEPS && e == hipSuccess; ++j) {
+          const int pre = (j > 0 ? PRE_DONE : 0) | (j + 1 < GRAPH_STEPS ? PRE_NEXT : 0);
+          e = enqueue_step(c, c.cur ^ (j & 1), c.tcur ^ (j & 1), nullptr, pre);
+        }
+        hipError_t e2 = hipStreamEndCapture(c.stream, &gr);
+        if (e != hipSuccess || e2 != hipSuccess)
+          return fail(c, HLBM_E_DEVICE, "graph capture: %s",
+                      hipGetErrorString(e != hipSuccess ? e : e2));
+        e = hipGraphInstantiate(&c.gexec_n[key], gr, nullptr, nullptr, 0);
+        hipGraphDestroy(gr);
+        if (e != hipSuccess)
+          return fail(c, HLBM_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+        c.graph_n_ready[key] = true;
+      }
+      HIPCHECK(hipGraphLaunch(c.gexec_n[key], c.stream));
+      c.step += GRAPH_STEPS;
+      s += GRAPH_STEPS - 1;
     } else if (c.use_graph) {
       const int key = 2 * c.cur + c.tcur;
       if (!c.graph_ready[key]) {

@@ -205,10 +205,14 @@ struct Ctx {
   // sizes of the state blocks (for snapshots)
   size_t part_bytes = 0, tile_bytes = 0, psum_bytes = 0;
   Adjoint adj;
-  // graphs: one per (population parity, contact-table parity)
+  // graphs: one per (population parity, contact-table parity) for a single
+  // step, and (one contact sub-step) one for GRAPH_STEPS steps with the
+  // overlapped contact treatment inside
   bool use_graph;
   hipGraphExec_t gexec[4];
   bool graph_ready[4];
+  hipGraphExec_t gexec_n[4];
+  bool graph_n_ready[4] = {false, false, false, false};
   int n_sub;
   int ev_per_step;        // timing events per step: 2 + 5 n_sub
   std::string err;

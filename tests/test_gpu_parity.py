@@ -214,6 +214,34 @@ def test_overlapped_treatment_matches_ordered_steps(W, H, prec):
         assert a.counters() == b.counters()
 
 
+def test_multistep_graph_matches_stream(W, H):
+    """Calls of 19 steps replayed as graphs (two captured 8-step graphs with
+    the overlapped contact treatment inside, then three single-step graphs)
+    leave the same bits as the stream launches."""
+    sc = W.random_small_scene(31, (26, 22, 20), 9, size_range=(1.8, 3.0),
+                              gap=-0.7, speed=0.01, spin=0.004)
+    p = W.Params(nx=26, ny=22, nz=20, tau=0.7, young=0.4, u_k=3e-4,
+                 gravity=(0.0, 0.0, -1e-4), balance=1,
+                 max_pairs=256, tile_capacity=16, precision=1)
+    a = H.Simulation(p, sc)
+    b = H.Simulation(p, sc, graph=True)
+    a.init_equilibrium(u=(0.002, -0.001, 0))
+    b.init_equilibrium(u=(0.002, -0.001, 0))
+    assert len(a.contacts()) > 0
+    for _ in range(2):
+        a.step(19)
+        b.step(19)
+        a.sync()
+        b.sync()
+        assert np.array_equal(a.populations(), b.populations())
+        pa, pb = a.particles(), b.particles()
+        for k in pa:
+            assert np.array_equal(pa[k], pb[k]), k
+        ca, cb = a.contacts(), b.contacts()
+        assert [_key(c) for c in ca] == [_key(c) for c in cb]
+        assert a.counters() == b.counters()
+
+
 def test_capacity_overflow_reported(W, H):
     """Too small a tile capacity is reported, not silently truncated."""
     sc = W.random_small_scene(3, (16, 16, 16), 6, size_range=(2.0, 3.0), gap=-0.5)
