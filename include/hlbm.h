@@ -3,8 +3,9 @@
  * homogenized lattice Boltzmann method with a discrete contact model for
  * convex particles (Marquardt, Hafen & Krause, arXiv 2401.10878).
  *
- * The library advances one time step of the paper's Algorithm 1 (a single
- * sub-step) entirely on one GPU:
+ * The library advances time steps of the paper's Algorithm 1 (one or more
+ * contact sub-steps) entirely on one GPU, for spheres, cubes, regular
+ * octahedra and convex polyhedra given by vertices and faces:
  *   - D3Q19 BGK stream-collide (Sec. 3.1, eqs. (10)-(13)) with the
  *     exact-difference velocity-shift coupling (Sec. 3.2, eqs. (14)-(15));
  *   - per-node signed-distance evaluation of the particles, which gives
