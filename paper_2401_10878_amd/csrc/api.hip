@@ -864,7 +864,12 @@ hlbm_status hlbm_step(hlbm_ctx* h, int nsteps) {
       // pending, so the state after the call is that of whole steps
       const bool ovl = c.n_sub == 1 && c.side != nullptr;
       const int pre = (ovl && s > 0 ? PRE_DONE : 0) | (ovl && s + 1 < nsteps ? PRE_NEXT : 0);
-      HIPCHECK(run_step(c, nullptr, pre));
+      const hipError_t e = run_step(c, nullptr, pre);
+      if (e != hipSuccess) {
+        // whatever the side stream has queued is joined before reporting
+        if (ovl) (void)hipStreamWaitEvent(c.stream, c.ev_treat, 0);
+        return fail(c, HLBM_E_DEVICE, "step: %s", hipGetErrorString(e));
+      }
     }
   }
   return HLBM_OK;
