@@ -125,7 +125,10 @@ typedef struct hlbm_ctx hlbm_ctx;
 /* Create a context on the current HIP device.  stream: a hipStream_t to run
    on (for example the current torch stream), or NULL for a private stream.
    Validates the parameters (lattice size, tau, capacities); allocates the
-   population buffers unless they are lent later.  *out is NULL on error. */
+   population buffers unless they are lent later.  *out is NULL on error;
+   with no context to hold it, the message of a rejected parameter goes to
+   stderr.  The context also creates a second stream (default priority) for
+   the overlapped contact treatment of hlbm_step. */
 hlbm_status hlbm_create(const hlbm_params *params, void *stream,
                         hlbm_ctx **out);
 
