@@ -20,6 +20,8 @@ Definitions (lattice units, fluid density 1, eta = nu):
       single-particle velocity with C_d = 24/Re.
 
     python -m paper_2401_10878_amd.settling --shape sphere cube --phi 0.1 0.3
+    (also octahedron, box (edges 1 : 1.25 : 1.6) and tetrahedron, all of the
+    sphere's volume)
 """
 from __future__ import annotations
 
@@ -122,8 +124,10 @@ def settling_run(wl: W.Workload, t_end: float, t_avg: float,
     down = gvec / g
     nu = (p.tau - 0.5) / 3.0
     s = float(sc.density[0])
-    # sphere diameter of the particle volume (the cubes are volume-equivalent)
-    if int(sc.shape[0]) == W.SPHERE:
+    # sphere diameter of the particle volume (every body is volume-equivalent)
+    if wl.d_equiv is not None:
+        d = float(wl.d_equiv)
+    elif int(sc.shape[0]) == W.SPHERE:
         d = 2.0 * float(sc.size[0])
     else:
         d = float(sc.size[0]) * (6.0 / math.pi) ** (1.0 / 3.0)
@@ -134,7 +138,7 @@ def settling_run(wl: W.Workload, t_end: float, t_avg: float,
     ustokes = g * d * d * (s - 1.0) / (18.0 * nu)
     re = ustar * d / nu
     ar = g * d ** 3 * (s - 1.0) / (nu * nu)
-    sim = hlbm.Simulation(p, sc, device=device, graph=graph)
+    sim = hlbm.Simulation(p, sc, device=device, graph=graph, polyhedra=wl.polyhedra)
     sim.init_equilibrium()
     ts, us = [0.0], [0.0]
     t0 = time.perf_counter()
@@ -164,6 +168,8 @@ def settling_run(wl: W.Workload, t_end: float, t_avg: float,
 
 def _phi(wl: W.Workload) -> float:
     p, sc = wl.params, wl.scene
+    if wl.d_equiv is not None:
+        return sc.n * math.pi / 6.0 * float(wl.d_equiv) ** 3 / float(p.nx * p.ny * p.nz)
     if int(sc.shape[0]) == W.SPHERE:
         v = 4.0 / 3.0 * math.pi * float(sc.size[0]) ** 3
     else:
@@ -174,7 +180,7 @@ def _phi(wl: W.Workload) -> float:
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--shape", nargs="+", default=["sphere", "cube"],
-                    choices=["sphere", "cube"])
+                    choices=["sphere", "cube", "octahedron", "box", "tetrahedron"])
     ap.add_argument("--phi", nargs="+", type=float, default=[0.1, 0.2, 0.3])
     ap.add_argument("--ar", nargs="+", type=float, default=[1000.0])
     ap.add_argument("--n-per-d", type=float, default=9.0,
@@ -192,7 +198,8 @@ def main(argv=None):
     for ar in args.ar:
         for phi in args.phi:
             for shp in args.shape:
-                shape = W.SPHERE if shp == "sphere" else W.CUBE
+                shape = {"sphere": W.SPHERE, "cube": W.CUBE,
+                         "octahedron": W.OCTAHEDRON}.get(shp, shp)
                 wl = W.settling_box(shape, phi, args.n_per_d, ar=ar,
                                     seed=args.seed, precision=prec,
                                     edge_cells=args.edge)

@@ -111,6 +111,7 @@ class Workload:
     steps: int
     note: str = ""
     polyhedra: Optional[dict] = None   # {type k: Polyhedron} for shape POLY0 + k
+    d_equiv: Optional[float] = None    # volume-equivalent sphere diameter (settling boxes)
 
 
 # --------------------------------------------------------------------------
@@ -352,6 +353,65 @@ def box_orientations(rng, X, half, dims, periodic, margin=0.3,
     return q
 
 
+def convex_orientations(rng, X, verts, faces, dims, periodic, margin=0.3,
+                        max_draws=10_000) -> np.ndarray:
+    """Random orientations such that no two copies of the convex body with
+    body-frame vertices `verts` and faces `faces` (grown by margin) overlap:
+    the separating-axis test over both bodies' face normals and the cross
+    products of their edge directions."""
+    n = X.shape[0]
+    dims = np.asarray(dims, float)
+    periodic = np.asarray(periodic, bool)
+    verts = np.asarray(verts, float)
+    normals = []
+    for f in faces:
+        a, b, c = verts[f[0]], verts[f[1]], verts[f[2]]
+        nv = np.cross(b - a, c - a)
+        normals.append(nv / np.linalg.norm(nv))
+    normals = np.array(normals)
+    edges = set()
+    for f in faces:
+        for j in range(len(f)):
+            i0, i1 = f[j], f[(j + 1) % len(f)]
+            edges.add((min(i0, i1), max(i0, i1)))
+    edirs = np.array([(verts[b] - verts[a]) / np.linalg.norm(verts[b] - verts[a])
+                      for a, b in sorted(edges)])
+    rc = float(np.linalg.norm(verts, axis=1).max()) + margin
+    q = np.zeros((n, 4))
+    R = np.zeros((n, 3, 3))
+    done = np.zeros(n, bool)
+
+    def overlap(Ra, Rb, t):
+        va, vb = verts @ Ra.T, verts @ Rb.T + t
+        axes = list(normals @ Ra.T) + list(normals @ Rb.T)
+        ea, eb = edirs @ Ra.T, edirs @ Rb.T
+        for u in ea:
+            for w in eb:
+                c = np.cross(u, w)
+                nn = np.linalg.norm(c)
+                if nn > 1e-9:
+                    axes.append(c / nn)
+        for ax in axes:
+            pa, pb = va @ ax, vb @ ax
+            if pa.max() + margin < pb.min() - margin or pb.max() + margin < pa.min() - margin:
+                return False
+        return True
+
+    for i in range(n):
+        d = _minimg(X - X[i], dims, periodic)
+        dist2 = (d * d).sum(1)
+        near = np.nonzero(done & (dist2 < (2 * rc) ** 2))[0]
+        for draw in range(max_draws):
+            qi = random_quaternions(rng, 1)
+            Ri = _rotation_matrices(qi)[0]
+            if not any(overlap(Ri, R[j], d[j]) for j in near):
+                break
+        else:
+            raise RuntimeError(f"orientation draws stalled at body {i}")
+        q[i], R[i], done[i] = qi[0], Ri, True
+    return q
+
+
 def cube_orientations(rng, X, edge, dims, periodic, margin=0.3,
                       max_draws=10_000) -> np.ndarray:
     """Random orientations such that no two cubes (grown by margin) overlap.
@@ -518,41 +578,61 @@ def c4_dense_spheres(seed: int = 3, L: int = 256, phi: float = 0.30,
                     f"{L}^3 periodic, {n} spheres D={dsph:.2f}, phi~{phi}, s=1.5, Ar=2000")
 
 
-def settling_box(shape: int, phi: float, n_per_d: float = 9.0,
+def settling_box(shape, phi: float, n_per_d: float = 9.0,
                  l_over_d: float = 12.0, ar: float = 1000.0, s: float = 3.3,
                  tau: float = 0.55, seed: int = 11, precision: int = 1,
                  edge_cells: Optional[int] = None,
                  balance: int = 2) -> Workload:
     """Periodic hindered-settling box of Sec. 5.1: spheres of diameter
-    D = n_per_d cells (or cubes of the same volume), edge L = l_over_d * D
-    (or edge_cells), n = phi L^3 / V_s particles at rest on a jittered,
-    thinned FCC lattice (cubes randomly oriented without overlap), density
-    ratio s (3.3 in the paper), gravity from the Archimedes number, balance
-    force on.  Dense cube boxes need an edge whose FCC cell count leaves the
-    cubes room to turn (e.g. L = 120 for D = 9 at phi = 0.3)."""
+    D = n_per_d cells (or other bodies of the same volume), edge
+    L = l_over_d * D (or edge_cells), n = phi L^3 / V_s particles at rest
+    on a jittered, thinned FCC lattice (non-spherical bodies randomly
+    oriented without overlap), density ratio s (3.3 in the paper), gravity
+    from the Archimedes number, balance force on.  shape: SPHERE, CUBE,
+    OCTAHEDRON, or "box" (edges 1 : 1.25 : 1.6) or "tetrahedron" (regular),
+    the last two as polyhedron type 0.  Dense boxes need an edge whose FCC
+    cell count leaves the bodies room to turn (e.g. L = 120 for D = 9 at
+    phi = 0.3)."""
     d = float(n_per_d)
     L = int(edge_cells) if edge_cells else int(round(l_over_d * d))
     vs = math.pi / 6.0 * d ** 3
     n = max(1, int(round(phi * L ** 3 / vs)))
     lu = lattice_units(d, s, ar, tau)
     X = _dense_centres(seed, L, n, d)
-    if shape == SPHERE:
-        size = 0.5 * d
+    rng = np.random.default_rng(seed + 1000)
+    per3, dims3 = (True, True, True), (L, L, L)
+    polys = None
+    if isinstance(shape, str):
+        # volume-equivalent polyhedron type 0 at unit size
+        if shape == "box":
+            a = (vs / 2.0) ** (1.0 / 3.0)
+            P = polyhedron_cuboid(a, 1.25 * a, 1.6 * a)
+        elif shape == "tetrahedron":
+            P = polyhedron_tetrahedron((6.0 * math.sqrt(2.0) * vs) ** (1.0 / 3.0))
+        else:
+            raise ValueError(f"unknown settling body {shape!r}")
+        polys = {0: P}
+        code, size, kind = POLY0, 1.0, "boxes" if shape == "box" else "tetrahedra"
+        q = convex_orientations(rng, X, P.vertices, P.faces, dims3, per3)
+    elif shape == SPHERE:
+        code, size, kind = SPHERE, 0.5 * d, "spheres"
         q = np.tile(np.array([1.0, 0.0, 0.0, 0.0]), (n, 1))
     elif shape == CUBE:
-        size = d * (math.pi / 6.0) ** (1.0 / 3.0)
-        rng = np.random.default_rng(seed + 1000)
-        q = cube_orientations(rng, X, size, (L, L, L), (True, True, True))
+        code, size, kind = CUBE, d * (math.pi / 6.0) ** (1.0 / 3.0), "cubes"
+        q = cube_orientations(rng, X, size, dims3, per3)
+    elif shape == OCTAHEDRON:
+        code, size, kind = OCTAHEDRON, (0.75 * vs) ** (1.0 / 3.0), "octahedra"
+        P = polyhedron_octahedron(size)
+        q = convex_orientations(rng, X, P.vertices, P.faces, dims3, per3)
     else:
-        raise ValueError("settling boxes hold spheres or cubes")
-    sc = Scene(np.full(n, shape, np.int32), np.full(n, size), np.full(n, s), X,
+        raise ValueError("settling boxes hold spheres, cubes, octahedra, boxes or tetrahedra")
+    sc = Scene(np.full(n, code, np.int32), np.full(n, size), np.full(n, s), X,
                q, np.zeros((n, 3)), np.zeros((n, 3)))
     p = _base_params((L, L, L), 1, tau, lu, balance).replace(
         max_pairs=max(1024, 8 * n), tile_capacity=48, precision=precision)
-    kind = "spheres" if shape == SPHERE else "cubes"
     return Workload("settling", p, sc, 0,
-                    f"{L}^3 periodic, {n} {kind}, D={d:g} cells, phi~{phi}, "
-                    f"s={s}, Ar={ar:g}")
+                    f"{L}^3 periodic, {n} {kind}, D={d:g} cells (volume-equivalent), "
+                    f"phi~{phi}, s={s}, Ar={ar:g}", polyhedra=polys, d_equiv=d)
 
 
 def c5_adjoint_cubes(seed: int = 5) -> Workload:

@@ -95,6 +95,31 @@ def test_settling_box_generator(shape, phi):
             assert not W._obb_overlap(np.zeros(3), R[i], h, d[j, i], R[j], h)
 
 
+@pytest.mark.parametrize("shape", [W.OCTAHEDRON, "box", "tetrahedron"])
+def test_settling_box_other_bodies(shape):
+    """Octahedra, 1 : 1.25 : 1.6 boxes and regular tetrahedra of the volume
+    of the sphere of diameter 9; the volume fraction from that diameter."""
+    wl = W.settling_box(shape, 0.1, 9.0, edge_cells=60, ar=1000.0)
+    sc = wl.scene
+    vs = np.pi / 6.0 * 729.0
+    if shape == W.OCTAHEDRON:
+        assert np.all(sc.shape == W.OCTAHEDRON)
+        assert 4.0 / 3.0 * sc.size[0] ** 3 == pytest.approx(vs, rel=1e-12)
+    else:
+        assert np.all(sc.shape == W.POLY0) and np.all(sc.size == 1.0)
+        v = wl.polyhedra[0].vertices
+        if shape == "box":
+            e = v.max(0) - v.min(0)
+            assert e[1] / e[0] == pytest.approx(1.25) and e[2] / e[0] == pytest.approx(1.6)
+            assert np.prod(e) == pytest.approx(vs, rel=1e-12)
+        else:
+            edge = np.linalg.norm(v[0] - v[1])
+            assert edge ** 3 / (6.0 * np.sqrt(2.0)) == pytest.approx(vs, rel=1e-12)
+    assert wl.d_equiv == 9.0
+    assert S._phi(wl) == pytest.approx(0.1, abs=5e-3)
+    assert np.allclose(np.linalg.norm(sc.q, axis=1), 1.0)
+
+
 @pytest.mark.gpu
 def test_gpu_short_settling_run():
     """A small sphere box settles: the bulk velocity along gravity grows from
