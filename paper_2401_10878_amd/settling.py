@@ -200,15 +200,14 @@ def main(argv=None):
             for shp in args.shape:
                 shape = {"sphere": W.SPHERE, "cube": W.CUBE,
                          "octahedron": W.OCTAHEDRON}.get(shp, shp)
-                wl = W.settling_box(shape, phi, args.n_per_d, ar=ar,
-                                    seed=args.seed, precision=prec,
-                                    edge_cells=args.edge)
-
                 def prog(done, steps, r, shp=shp, phi=phi, ar=ar):
                     print(f"  {shp} phi={phi} Ar={ar:g}: step {done}/{steps} "
                           f"u/u*={r:.4f}", flush=True)
 
                 try:
+                    wl = W.settling_box(shape, phi, args.n_per_d, ar=ar,
+                                        seed=args.seed, precision=prec,
+                                        edge_cells=args.edge)
                     r = settling_run(wl, args.t_end, args.t_avg,
                                      args.sample_every, progress=prog)
                 except Exception as e:  # report and go on with the next point
