@@ -121,6 +121,29 @@ def test_dense_sphere_box_full_size(dense_spheres, H, prec):
     _check(H, wl, ref, prec)
 
 
+def test_dense_cube_box_graphs_match_stream(W, H):
+    """The benchmark's launch mode at full size: 11 FP32 steps in one call
+    replayed as graphs (one captured 8-step graph with the overlapped
+    contact treatment, then three single-step graphs) leave the same bits as
+    11 stream-launched steps."""
+    wl = W.c3_dense_cubes()
+    out = []
+    for graph in (False, True):
+        g = H.Simulation(wl.params, wl.scene, graph=graph)
+        g.init_equilibrium()
+        g.step(11)
+        out.append((g.particles(), g.forces(), g.populations()[:, ::5, ::3, :].copy(),
+                    [(c["a"], c["b"], c["count"], c["fn"]) for c in g.contacts()]))
+        g.close()
+    (pa, ea, fa, ca), (pb, eb, fb, cb) = out
+    assert len(ca) > 0 and ca == cb
+    for k in pa:
+        assert np.array_equal(pa[k], pb[k]), k
+    for k in ea:
+        assert np.array_equal(ea[k], eb[k]), k
+    assert np.array_equal(fa, fb)
+
+
 def test_dense_cube_box_bitwise_reproducible(W, H):
     """Two runs of the benchmark workload (FP32, 30 steps with contacts)
     give identical bits: every reduction on the path has a fixed order."""
