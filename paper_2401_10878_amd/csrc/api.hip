@@ -716,9 +716,14 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
       emax = fmax(emax, circumradius(c, sh[i], sz[i]));
     const double span = 2.0 * (emax + margin) + 3.0;
     const int ts[3] = {LX, LY, LZ}, nt[3] = {c.g.ltx, c.g.lty, c.g.ltz};
+    const int nn3[3] = {c.g.nx, c.g.ny, c.g.nz};
+    const bool per3[3] = {true, true, c.g.periodic_z != 0};
     long long me = 1;
     for (int k = 0; k < 3; ++k) {
-      long long m = (long long)(span / ts[k]) + 2;
+      // an interval of length span touches at most span / ts + 2 whole
+      // blocks; on a periodic axis whose last block is partial, the
+      // interval can wrap through that short block and touch one more
+      long long m = (long long)(span / ts[k]) + 2 + (per3[k] && nn3[k] % ts[k] ? 1 : 0);
       if (m > nt[k]) m = nt[k];
       me *= m;
     }

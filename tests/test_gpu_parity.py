@@ -471,6 +471,32 @@ def test_no_particles_pure_fluid(O, W, H, pz):
     assert (g.fields()["owner"] == -1).all()
 
 
+def test_reach_wraps_through_partial_block(O, W, H):
+    """A particle whose reach wraps round a periodic x axis through its last,
+    partial lattice block (132 = 2 x 64 + 4 nodes) touches three blocks
+    along x; its partial-sum slots must hold them (this was reported as a
+    capacity overflow).  FP64 against the oracle over three steps."""
+    dims = (132, 24, 24)
+    sc = W.Scene(np.array([0, 1], np.int32), np.array([8.5, 7.0]), np.array([1.5, 1.5]),
+                 np.array([[125.5, 11.0, 12.0], [60.0, 12.5, 11.0]]),
+                 np.array([[1.0, 0, 0, 0], [0.9, 0.3, -0.2, 0.1]]) /
+                 np.linalg.norm([[1.0, 0, 0, 0], [0.9, 0.3, -0.2, 0.1]], axis=1)[:, None],
+                 np.array([[0.004, 0.001, 0.0], [-0.002, 0.0, 0.001]]), np.zeros((2, 3)))
+    p = W.Params(nx=dims[0], ny=dims[1], nz=dims[2], periodic_z=1, tau=0.7,
+                 gravity=(0.0, 0.0, -1e-5), young=0.4, u_k=3e-4,
+                 max_pairs=16, tile_capacity=8, precision=0)
+    f0 = W.perturbed_populations(9, dims, O.feq(1.0, [0.002, 0.0, 0.001]), amp=0.01)
+    o, g = _pair(O, H, p, sc, f0)
+    assert np.array_equal(g.fields()["owner"], o.fields()["owner"])
+    Fref = 1e-5 * 0.5 * 4.0 / 3.0 * math.pi * 8.5 ** 3
+    for _ in range(3):
+        o.step(1)
+        g.step(1)
+        eo, eg = o.forces(), g.forces()
+        assert np.abs(eg["Fh"] - eo["Fh"]).max() <= 1e-12 * max(np.abs(eo["Fh"]).max(), Fref)
+        assert np.abs(eg["Th"] - eo["Th"]).max() <= 1e-12 * max(np.abs(eo["Th"]).max(), Fref * 8.5)
+
+
 def test_pair_table_overflow_reported(W, H):
     """More contact pairs than the table holds is an error, not a silent
     truncation."""
