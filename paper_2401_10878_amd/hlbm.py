@@ -217,9 +217,15 @@ class Simulation:
         self._check(self.L.hlbm_set_populations(self.h, _dp(f)))
 
     def step(self, n=1):
+        """n coupled time steps, queued on the library stream.  Within one
+        call the contact treatment of steps 2..n runs on the context's second
+        stream beside the previous step's lattice passes; the call ends with
+        nothing pending and the same bits as n single-step calls."""
         self._check(self.L.hlbm_step(self.h, n))
 
     def use_graph(self, on=True):
+        """Replay steps as captured HIP graphs (8-step graphs while at least
+        8 steps of a call remain, single-step graphs for the rest)."""
         self._check(self.L.hlbm_use_graph(self.h, 1 if on else 0))
 
     KERNELS = ("clear", "treat", "particles", "keep", "detect", "lattice",
