@@ -1297,6 +1297,12 @@ void orc_treat_pair(const orc_params *P, const orc_particle *pa,
                       out);
 }
 
+void orc_contact_force_of(const orc_params *P, const orc_particle *pa,
+                          const orc_particle *pb, orc_contact *c)
+{
+    contact_force(P, pa, pb, pb ? pb->X : NULL, c);
+}
+
 /* Treatment of the whole contact list at the current particle state; adds
    the contact forces and torques, keeps contacts with V > 0 (sorted order is
    preserved) and returns how many were kept. */

@@ -131,6 +131,12 @@ double orc_effective_modulus(double Ea, double nua, double Eb, double nub);
 void orc_treat_pair(const orc_params *P, const orc_particle *pa,
                     const orc_particle *pb, int b_id, int npass,
                     double lo[3], double hi[3], orc_contact *out);
+/* eqs. (4)-(9) alone for a contact record whose volume, depth, centroid,
+   normal, established flag and damping factor the caller sets (pb NULL: a
+   wall partner at rest); writes fn, force_a, force_b and, at onset, the
+   damping factor. */
+void orc_contact_force_of(const orc_params *P, const orc_particle *pa,
+                          const orc_particle *pb, orc_contact *c);
 
 #ifdef __cplusplus
 }

@@ -101,6 +101,8 @@ def lib():
         L.orc_treat_pair.argtypes = [P(OrcParams), P(OrcParticle),
                                      P(OrcParticle), i, i, P(d), P(d),
                                      P(OrcContact)]
+        L.orc_contact_force_of.argtypes = [P(OrcParams), P(OrcParticle),
+                                           P(OrcParticle), P(OrcContact)]
         L.orc_threads.restype = i
         L.orc_define_polyhedron.argtypes = [i, i, P(d), i, P(i), P(i)]
         L.orc_define_polyhedron.restype = i
@@ -372,6 +374,24 @@ def treat_pair(params, pa, pb, b_id, lo, hi, npass=1):
                          C.byref(pb) if pb is not None else None, int(b_id),
                          int(npass), _dp(lo), _dp(hi), C.byref(out))
     return contacts_to_dicts([out])[0]
+
+
+def contact_force_of(params, pa, pb, volume, depth, centroid, normal,
+                     established=0, damping=0.0):
+    """eqs. (4)-(9) for a contact of the given volume, depth, centroid and
+    normal (pb None: wall partner); returns the record with fn, forces and
+    the damping factor."""
+    P = make_params(params)
+    c = OrcContact()
+    c.volume, c.depth = float(volume), float(depth)
+    for k in range(3):
+        c.centroid[k] = float(centroid[k])
+        c.normal[k] = float(normal[k])
+    c.established, c.damping = int(established), float(damping)
+    lib().orc_contact_force_of(C.byref(P), C.byref(pa),
+                               C.byref(pb) if pb is not None else None,
+                               C.byref(c))
+    return contacts_to_dicts([c])[0]
 
 
 def threads():
