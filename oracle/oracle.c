@@ -846,6 +846,28 @@ static int axis_nodes(double c, double reach, int n, int periodic, int *out)
 
 static const double DETECT = 0.8660254037844386; /* sqrt(0.75) */
 
+/* half extent along world axis k of a particle with rotation R: exact for
+   cubes and polyhedra (largest |world coordinate| of a vertex), the
+   circumradius for spheres and octahedra */
+static double half_extent(const orc_particle *pp, const double R[9], int k)
+{
+    double e = pp->size;
+    if (pp->shape == 1)
+        e = 0.5 * pp->size *
+            (fabs(R[3 * k]) + fabs(R[3 * k + 1]) + fabs(R[3 * k + 2]));
+    if (pp->shape >= ORC_POLY0) {
+        const orc_poly *Q = &g_poly[pp->shape - ORC_POLY0];
+        e = 0.0;
+        for (int i = 0; i < Q->nv; ++i) {
+            double c = fabs((R[3 * k] * Q->v[i][0] + R[3 * k + 1] * Q->v[i][1]) +
+                            R[3 * k + 2] * Q->v[i][2]);
+            if (c > e) e = c;
+        }
+        e *= pp->size;
+    }
+    return e;
+}
+
 static int couple_and_detect_nodes(orc_sim *S)
 {
     const orc_params *P = &S->P;
@@ -868,23 +890,7 @@ static int couple_and_detect_nodes(orc_sim *S)
         const orc_particle *pp = &S->p[ip];
         double R[9], reach[3];
         orc_rotation(pp->q, R);
-        for (int k = 0; k < 3; ++k) {
-            double e = pp->size;
-            if (pp->shape == 1)
-                e = 0.5 * pp->size *
-                    (fabs(R[3 * k]) + fabs(R[3 * k + 1]) + fabs(R[3 * k + 2]));
-            if (pp->shape >= ORC_POLY0) {
-                const orc_poly *Q = &g_poly[pp->shape - ORC_POLY0];
-                e = 0.0;
-                for (int i = 0; i < Q->nv; ++i) {
-                    double c = fabs((R[3 * k] * Q->v[i][0] + R[3 * k + 1] * Q->v[i][1]) +
-                                    R[3 * k + 2] * Q->v[i][2]);
-                    if (c > e) e = c;
-                }
-                e *= pp->size;
-            }
-            reach[k] = e + margin;
-        }
+        for (int k = 0; k < 3; ++k) reach[k] = half_extent(pp, R, k) + margin;
         int cnt[3];
         for (int k = 0; k < 3; ++k)
             cnt[k] = axis_nodes(pp->X[k], reach[k], dims[k], per[k], ax[k]);
@@ -1324,6 +1330,19 @@ static int treat_contacts(orc_sim *S)
         if (pb)
             for (int k = 0; k < 3; ++k)
                 Xb[k] = pa->X[k] + minimg(pb->X[k] - pa->X[k], dims[k], per[k]);
+        /* a new particle-wall pair: its flagged nodes all lie on the fluid
+           side of the wall plane, while the overlap of the enlarged body
+           with the wall's half space lies beyond it; the wall-side face of
+           the box starts at the far side of the enlarged body (its half
+           extent along z plus the enlargement), and the correction moves it
+           onto the body */
+        if (!c.carried && c.b < 0) {
+            double R[9];
+            orc_rotation(pa->q, R);
+            double ez = half_extent(pa, R, 2) + P->delta_c;
+            if (c.b == -1) c.lo[2] = fmin(c.lo[2], pa->X[2] - ez);
+            else c.hi[2] = fmax(c.hi[2], pa->X[2] + ez);
+        }
         /* the box stays in the frame of the lower-id particle: if that
            particle has wrapped since the box was made, shift the box along */
         for (int k = 0; k < 3; ++k) {

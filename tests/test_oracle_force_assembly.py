@@ -208,3 +208,39 @@ def test_cube_inertia_from_contact_couple(O, W):
         np.testing.assert_allclose(X1["U"][k] - X0["U"][k], f["Fc"][k] / m,
                                    rtol=1e-9, atol=1e-22)
         assert np.abs(f["Tc"][k]).max() > 0
+
+
+@pytest.mark.parametrize("top", [False, True])
+def test_cube_through_wall_exact_overlap(O, W, top):
+    """An axis-aligned cube (no enlargement) reaching t = 0.2 beyond the
+    bottom (or top) wall plane: the contact's box starts on the far side of
+    the body, the correction moves its faces onto the cube and the wall
+    plane, and the overlap is the exact slab: V = t a^2, depth t, normal
+    from the cube into the wall, centroid the slab centre; the force is the
+    closed form of eqs. (4)-(9) with the wall at rest."""
+    a, t, nz = 6.0, 0.2, 24
+    zc = (nz - 0.5 + t - a / 2) if top else (-0.5 - t + a / 2)
+    p = _params(W, nx=32, ny=32, nz=nz, periodic_z=0, tau=0.8, young=2.0)
+    X = np.array([16.3, 15.7, zc])
+    U, w = np.array([0.001, -0.0005, 0.002 if top else -0.002]), np.zeros(3)
+    sc = W.Scene(np.array([1], np.int32), np.array([a]), np.array([1.5]),
+                 X[None, :], np.array([[1.0, 0, 0, 0]]), U[None, :], w[None, :])
+    s = O.OracleSim(p, sc)
+    s.init_equilibrium()
+    s.step(1)
+    con, f = s.contacts(), s.forces()
+    s.close()
+    assert len(con) == 1 and con[0]["b"] == (-2 if top else -1)
+    c = con[0]
+    V = t * a * a
+    n = np.array([0.0, 0.0, 1.0 if top else -1.0])
+    plane = nz - 0.5 if top else -0.5
+    xc = np.array([X[0], X[1], plane + (t / 2 if top else -t / 2)])
+    assert abs(c["volume"] - V) <= 1e-12 * V
+    assert abs(c["depth"] - t) <= 1e-12
+    np.testing.assert_allclose(c["normal"], n, atol=1e-15)
+    np.testing.assert_allclose(c["centroid"], xc, atol=1e-12)
+    v = U + np.cross(w, xc - X)
+    fn, Fa = expected_force(p.young, V, t, n, v, onset_damping(float(v @ n)), p.u_k)
+    assert abs(c["fn"] - fn) <= 1e-12 * fn
+    np.testing.assert_allclose(f["Fc"][0], Fa, rtol=0, atol=1e-12 * fn)
