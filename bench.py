@@ -5,8 +5,8 @@ Default workload: dense settling box, 256^3 periodic lattice, 1834 cubes of
 edge 14 (phi = 0.30, s = 1.5, Ar = 1000), populations in FP32, synthetic
 seeded scene.  A step is the whole time step: contact treatment, particle
 motion and tile binning, contact carry-over, coupling map with rough
-detection, the stream-collide pass with the coupling, and the momentum
-exchange over the populations it wrote.  The timed steps are replayed as
+detection, and the stream-collide pass with the coupling, which also sums
+the momentum exchange of the populations it writes.  The timed steps are replayed as
 captured HIP graphs (8 steps per graph, the contact treatment of each step
 on a second stream beside the previous step's lattice passes); --stream
 times plain stream launches instead, and the line reports the other mode's
@@ -34,8 +34,8 @@ PREC = {"fp64": 0, "fp32": 1, "fp16s": 2}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f16-storage/f32-compute"}
 VALUE_BYTES = {0: 8, 1: 4, 2: 2}
 W_POLY0 = 3                    # shape code of the first polyhedron type
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lattice_k_mea_c3_traffic.json")
-# the sources the stream-collide and momentum-exchange kernels are built from
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lattice_c3_traffic.json")
+# the sources the stream-collide kernel is built from
 LATTICE_SRC = [os.path.join(ROOT, "paper_2401_10878_amd", "csrc", f)
                for f in ("k_lattice.hip", "device_math.h", "context.h")]
 
@@ -49,10 +49,9 @@ def lattice_source_hash():
 
 def traffic_for(prec_name, section="per_precision", field="bytes_per_launch",
                 workload="C3"):
-    """HBM bytes per launch of the stream-collide pass (section
-    per_precision) or the momentum-exchange pass (mea_per_precision) from the
-    committed rocprofv3 counters, or None if the counters were taken on
-    another workload or another version of the kernels."""
+    """HBM bytes per launch of the stream-collide pass from the committed
+    rocprofv3 counters, or None if the counters were taken on another
+    workload or another version of the kernels."""
     try:
         d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
@@ -82,7 +81,6 @@ def run_gpu(wl, prec, steps, warmup, graph):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     c1 = sim.counters()
-    final = dict(U=sim.particles()["U"], Fh=sim.forces()["Fh"])
     # per-kernel times from a second window of the same length, with HIP
     # events around every launch (those steps run their kernels one after
     # another: the contact treatment does not overlap the lattice passes)
@@ -97,7 +95,7 @@ def run_gpu(wl, prec, steps, warmup, graph):
         ms_per_step=wall * 1e3 / steps,
         contact_cells_per_s=(c1["total_cells"] - c0["total_cells"]) / wall,
         kernel_ms_per_step={k: v / n for k, v in kms.items()},
-        pairs=c1["pairs"], overlap_cells=c1["cells"], final=final,
+        pairs=c1["pairs"], overlap_cells=c1["cells"],
     )
     lat_s = kms["lattice"] / n / 1e3
     bytes_alg = 2 * 19 * VALUE_BYTES[PREC[prec]] * ncell
@@ -131,10 +129,9 @@ def other_ms_per_step(wl, prec, steps, warmup, graph):
     return (t1 - t0) * 1e3 / steps
 
 
-def error_vs_fp64(wl, res, ref):
-    """Errors of a precision form against the FP64 run of the same steps:
-    mean settling velocity, hydrodynamic force (relative to
-    max(|F|, (s - 1) V |g|)) and particle velocity."""
+def reference_force(wl):
+    """(s - 1) V |g| of the heaviest particle: the force scale of the error
+    normalisation max(|F|, F_ref)."""
     import numpy as np
     sc, g = wl.scene, abs(wl.params.gravity[2])
     V = np.where(sc.shape == 0, 4.0 / 3.0 * np.pi * sc.size ** 3,
@@ -147,17 +144,47 @@ def error_vs_fp64(wl, res, ref):
                   for f in P.faces for j in range(1, len(f) - 1)) / 6.0
         m = sc.shape == W_POLY0 + k
         V[m] = vol * sc.size[m] ** 3
-    Fref = ((sc.density - 1.0) * V).max() * g
-    U, U64 = res["final"]["U"], ref["final"]["U"]
-    F, F64 = res["final"]["Fh"], ref["final"]["Fh"]
-    uz, uz64 = U[:, 2].mean(), U64[:, 2].mean()
+    return ((sc.density - 1.0) * V).max() * g
+
+
+def state_errors(wl, got, ref):
+    """Errors of a GPU state against a reference state after the same steps:
+    mean settling velocity (mean U_z), hydrodynamic force (relative to
+    max(|F|, (s - 1) V |g|)) and particle velocity (relative to the largest
+    reference speed)."""
+    import numpy as np
+    Fref = reference_force(wl)
+    U, Ur = got["U"], ref["U"]
+    F, Fr = got["Fh"], ref["Fh"]
+    uz, uzr = U[:, 2].mean(), Ur[:, 2].mean()
     return dict(
-        mean_settling_velocity_rel=float(abs(uz - uz64) / abs(uz64)),
-        force_rel=float((np.abs(F - F64) / np.maximum(np.abs(F64), Fref)).max()),
-        velocity_rel=float(np.abs(U - U64).max() / np.abs(U64).max()))
+        mean_settling_velocity_rel=float(abs(uz - uzr) / abs(uzr)),
+        force_rel=float((np.abs(F - Fr) / np.maximum(np.abs(Fr), Fref)).max()),
+        velocity_rel=float(np.abs(U - Ur).max() / np.abs(Ur).max()))
+
+
+def gpu_short_state(wl, prec, steps):
+    """Particle velocities and hydrodynamic forces after `steps` steps from
+    the initial state (stream launches), for the comparison with the
+    oracle's run of the same steps."""
+    import torch
+    from paper_2401_10878_amd import hlbm
+    sim = hlbm.Simulation(wl.params.replace(precision=PREC[prec]), wl.scene,
+                          device="cuda:0", polyhedra=wl.polyhedra)
+    sim.init_equilibrium()
+    sim.step(steps)
+    sim.sync()
+    out = dict(U=sim.particles()["U"], Fh=sim.forces()["Fh"])
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(wl, steps):
+    """The FP64 oracle timed on the host cores over `steps` steps of the
+    workload; also returns its particle velocities and hydrodynamic forces
+    after those steps (the reference of the precision errors)."""
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
     for k, P in (wl.polyhedra or {}).items():
@@ -178,8 +205,9 @@ def cpu_baseline(wl, steps):
                contact_cells_per_s=round(cells / wall, 1),
                sample=f"{wl.name}: {steps} coupled FP64 steps after the prologue "
                       f"({ncell} nodes, {wl.scene.n} particles), {wall:.1f} s")
+    state = dict(U=s.particles()["U"], Fh=s.forces()["Fh"])
     s.close()
-    return res
+    return res, state
 
 
 def copy_calibration(nbytes=1 << 30, reps=5):
@@ -197,6 +225,100 @@ def copy_calibration(nbytes=1 << 30, reps=5):
                           launches=reps)), flush=True)
 
 
+def traffic_summary(outdir, workload_name):
+    """Write the counter file from four rocprofv3 --pmc runs (csv output)
+    under outdir: pmc_FETCH_SIZE and pmc_WRITE_SIZE of the benchmark command
+    and copy_FETCH_SIZE, copy_WRITE_SIZE of --copy-calibration.  FETCH_SIZE
+    and WRITE_SIZE (KiB per dispatch) of the stream-collide kernel are
+    scaled by what the same counters read for the plain copy of known size."""
+    import csv
+    import glob
+
+    def rows(sub):
+        files = glob.glob(os.path.join(outdir, sub, "**", "*counter_collection.csv"),
+                          recursive=True)
+        if not files:
+            raise SystemExit(f"no counter_collection.csv under {outdir}/{sub}")
+        out = []
+        for f in files:
+            with open(f) as fh:
+                out.extend(csv.DictReader(fh))
+        return out
+
+    def per_kernel(sub, counter, match):
+        vals = {}
+        for r in rows(sub):
+            if r.get("Counter_Name") != counter or match not in r.get("Kernel_Name", ""):
+                continue
+            vals.setdefault(r["Kernel_Name"], {}).setdefault(r["Dispatch_Id"], 0.0)
+            vals[r["Kernel_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+        return {k: sum(v.values()) / len(v) for k, v in vals.items()}, \
+            {k: len(v) for k, v in vals.items()}
+
+    cf, _ = per_kernel("copy_FETCH_SIZE", "FETCH_SIZE", "elementwise")
+    cw, _ = per_kernel("copy_WRITE_SIZE", "WRITE_SIZE", "elementwise")
+    nbytes = 1 << 30
+    fetch_factor = nbytes / (max(cf.values()) * 1024.0)
+    write_factor = nbytes / (max(cw.values()) * 1024.0)
+    lf, ln = per_kernel("pmc_FETCH_SIZE", "FETCH_SIZE", "k_lattice")
+    lw, _ = per_kernel("pmc_WRITE_SIZE", "WRITE_SIZE", "k_lattice")
+    mf, mn = per_kernel("pmc_FETCH_SIZE", "FETCH_SIZE", "k_mea")
+    mw, _ = per_kernel("pmc_WRITE_SIZE", "WRITE_SIZE", "k_mea")
+    kind = {"k_lattice<double": "fp64", "k_lattice<float": "fp32",
+            "k_lattice<__half": "fp16s"}
+    mkind = {"k_mea<double": "fp64", "k_mea<float": "fp32", "k_mea<__half": "fp16s"}
+    per = {}
+    for name, fkib in lf.items():
+        prec = next((v for k, v in kind.items() if k in name), None)
+        wkib = lw.get(name)
+        if prec is None or wkib is None:
+            continue
+        rd, wr = fkib * 1024.0 * fetch_factor, wkib * 1024.0 * write_factor
+        alg = 2 * 19 * VALUE_BYTES[PREC[prec]] * 256 ** 3
+        per[prec] = dict(fetch_size_kib=round(fkib, 1), write_size_kib=round(wkib, 1),
+                         read_bytes=int(rd), write_bytes=int(wr),
+                         bytes_per_launch=int(rd + wr), launches=ln[name],
+                         algorithmic_bytes=alg,
+                         traffic_over_algorithmic=round((rd + wr) / alg, 4))
+    # the separate momentum-exchange pass (binary16 storage; the initial
+    # state of every precision): measured bytes per launch
+    for name, fkib in mf.items():
+        prec = next((v for k, v in mkind.items() if k in name), None)
+        wkib = mw.get(name)
+        if prec is None or wkib is None or prec not in per:
+            continue
+        rd, wr = fkib * 1024.0 * fetch_factor, wkib * 1024.0 * write_factor
+        per[prec]["separate_mea"] = dict(read_bytes=int(rd), write_bytes=int(wr),
+                                         launches=mn[name])
+    d = dict(kernel="k_lattice", workload=workload_name,
+             note="HBM bytes per launch of the stream-collide pass (which also sums "
+                  "the momentum exchange for FP64 and FP32 storage; binary16 storage "
+                  "runs the separate pass, listed beside it), from FETCH_SIZE and "
+                  "WRITE_SIZE scaled by a plain 1 GiB copy",
+             kernel_source_sha256_16=lattice_source_hash(),
+             commands=["cd /tmp && export TMPDIR=/tmp",
+                       "rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'k_lattice|k_mea' "
+                       "--output-format csv -d <out>/pmc_FETCH_SIZE -o lat -- python3 "
+                       "bench.py --steps 4 --warmup 1 --cpu-steps 0",
+                       "rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'k_lattice|k_mea' "
+                       "--output-format csv -d <out>/pmc_WRITE_SIZE -o lat -- python3 "
+                       "bench.py --steps 4 --warmup 1 --cpu-steps 0",
+                       "rocprofv3 --pmc FETCH_SIZE --output-format csv -d "
+                       "<out>/copy_FETCH_SIZE -o copy -- python3 bench.py --copy-calibration",
+                       "rocprofv3 --pmc WRITE_SIZE --output-format csv -d "
+                       "<out>/copy_WRITE_SIZE -o copy -- python3 bench.py --copy-calibration",
+                       "python3 bench.py --traffic-summary <out>"],
+             calibration=dict(copy_bytes_read=nbytes, copy_bytes_written=nbytes,
+                              fetch_size_kib=round(max(cf.values()), 1),
+                              write_size_kib=round(max(cw.values()), 1),
+                              fetch_factor=round(fetch_factor, 4),
+                              write_factor=round(write_factor, 4)),
+             per_precision=per)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(d, f, indent=1)
+    print(json.dumps(d))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,7 +334,14 @@ def main():
                     help="oracle steps timed for the CPU baseline (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--traffic-summary", metavar="DIR",
+                    help="write the counter file from rocprofv3 --pmc output under DIR")
     args = ap.parse_args()
+    if args.traffic_summary:
+        from paper_2401_10878_amd import workloads as W
+        wl = W.WORKLOADS[args.workload]()
+        traffic_summary(args.traffic_summary, f"{wl.name}: {wl.note}")
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU "
               "path.", file=sys.stderr)
@@ -236,9 +365,8 @@ def main():
                           ms_per_step=round(r["ms_per_step"], 4),
                           lattice_gbs=round(r["lattice_gbs"], 1))
         if "fp64" in runs and pr != "fp64":
-            others[pr]["error_vs_fp64"] = {
-                k: float(f"{v:.3e}") for k, v in
-                error_vs_fp64(wl, r, runs["fp64"]).items()}
+            others[pr]["speedup_vs_fp64"] = round(runs["fp64"]["ms_per_step"]
+                                                  / r["ms_per_step"], 3)
     other_ms = other_ms_per_step(wl, args.precision, args.steps, args.warmup,
                                  not graph)
     lat_ms = main_res["kernel_ms_per_step"]["lattice"]
@@ -251,12 +379,16 @@ def main():
                 avg_launch_ms=round(lat_ms, 5),
                 # measured HBM bytes (rocprofv3 counters) over the same time
                 traffic_gbs=None if traffic is None else round(traffic / (lat_ms * 1e6), 1))
-    mea_ms = main_res["kernel_ms_per_step"]["mea"]
-    mea_read = traffic_for(args.precision, "mea_per_precision", "read_bytes", wl.name)
-    mea = dict(kernel="k_mea", avg_launch_ms=round(mea_ms, 5),
-               hbm_read_bytes=mea_read,
-               read_gbs=None if mea_read is None else round(mea_read / (mea_ms * 1e6), 1))
-    cpu = cpu_baseline(wl, args.cpu_steps) if args.cpu_steps > 0 else None
+    cpu = None
+    if args.cpu_steps > 0:
+        cpu, oracle_state = cpu_baseline(wl, args.cpu_steps)
+        # each precision against the FP64 oracle after the same steps
+        for pr in runs:
+            got = gpu_short_state(wl, pr, args.cpu_steps)
+            others[pr]["error_vs_oracle"] = dict(
+                steps=args.cpu_steps,
+                **{k: float(f"{v:.3e}") for k, v in
+                   state_errors(wl, got, oracle_state).items()})
     p = wl.params
     line = dict(
         metric="coupled-step MLUPS (+ contact cells/s)",
@@ -277,13 +409,22 @@ def main():
         contact_samples_per_s=round(
             main_res["pairs"] * (6 * p.n_c ** 2 + p.n_c ** 3)
             / (main_res["kernel_ms_per_step"]["treat"] * 1e-3), 1),
+        # the lattice pass includes the momentum exchange of the next step
+        # (FP64, FP32); binary16 storage runs it as the separate "mea" pass
         kernel_ms_per_step={k: round(v, 5) for k, v in
-                            main_res["kernel_ms_per_step"].items()},
+                            main_res["kernel_ms_per_step"].items()
+                            if k != "mea" or args.precision == "fp16s"},
         # the other launch mode of the same workload and precision
         **{("stream_ms_per_step" if graph else "graph_ms_per_step"): round(other_ms, 4)},
         precisions=others,
         roofline=roof,
-        mea_pass=mea,
+        # the whole step against the same bound: algorithmic population
+        # bytes per step over the wall time per step
+        step_roofline=dict(bytes_per_step=main_res["bytes_alg"],
+                           achieved=round(main_res["bytes_alg"] / (main_res["ms_per_step"] * 1e6), 1),
+                           peak=PEAK_HBM_GBS, unit="GB/s",
+                           frac=round(main_res["bytes_alg"] / (main_res["ms_per_step"] * 1e6)
+                                      / PEAK_HBM_GBS, 4)),
         cpu_baseline=cpu,
     )
     print(json.dumps(line), flush=True)

@@ -122,19 +122,24 @@ typedef struct {
 
 typedef struct hlbm_ctx hlbm_ctx;
 
-/* Create a context on the current HIP device.  stream: a hipStream_t to run
-   on (for example the current torch stream), or NULL for a private stream.
-   Validates the parameters (lattice size, tau, capacities); allocates the
-   population buffers unless they are lent later.  *out is NULL on error;
-   with no context to hold it, the message of a rejected parameter goes to
-   stderr.  The context also creates a second stream (default priority) for
-   the overlapped contact treatment of hlbm_step. */
+/* Create a context on the current HIP device: the lattice, its boundaries
+   and the constants of the method (the D3Q19 lattice of Sec. 3.1 with the
+   BGK relaxation time of eq. (12); the coupling band of Sec. 3.2; the
+   contact constants of eqs. (5)-(9) and the enlargement of Sec. 5.1).
+   stream: a hipStream_t to run on (for example the current torch stream),
+   or NULL for a private stream.  Validates the parameters (lattice size,
+   tau, capacities); allocates the population buffers unless they are lent
+   later.  *out is NULL on error; with no context to hold it, the message of
+   a rejected parameter goes to stderr.  The context also creates a second
+   stream (default priority) for the overlapped contact treatment of
+   hlbm_step. */
 hlbm_status hlbm_create(const hlbm_params *params, void *stream,
                         hlbm_ctx **out);
 
 /* Lend two DEVICE population buffers of `bytes` each (19 * nx*ny*nz *
-   bytes-per-value of the precision: 8, 4 or 2).  Must be called before any
-   init call.  The context never frees them. */
+   bytes-per-value of the precision: 8, 4 or 2) for the post-collision
+   populations f* of eqs. (10)-(12) and their streamed copy (ping-pong).
+   Must be called before any init call.  The context never frees them. */
 hlbm_status hlbm_bind_populations(hlbm_ctx *ctx, void *dev_a, void *dev_b,
                                   size_t bytes);
 
@@ -156,73 +161,96 @@ hlbm_status hlbm_define_polyhedron(hlbm_ctx *ctx, int type, int nv,
                                    const double *v, int nf, const int *fsize,
                                    const int *fidx);
 
-/* Upload n particles (host arrays).  shape: hlbm_shape; size = radius
-   (sphere), edge (cube), centre-to-vertex distance (octahedron) or scale
-   (polyhedron);
-   density = particle/fluid density ratio.  Positions on periodic axes are
-   wrapped into [0, n).  Periodic axes must exceed twice the particle reach
-   (circumradius + detection margin). */
+/* Upload n particles (host arrays): the state of eqs. (2)-(3), position of
+   the centre of mass, orientation, velocity and angular velocity, with
+   shape, size and density ratio (Sec. 2.1, Sec. 5.1).  shape: hlbm_shape;
+   size = radius (sphere), edge (cube), centre-to-vertex distance
+   (octahedron) or scale (polyhedron); density = particle/fluid density
+   ratio.  Quaternions are normalised (HLBM_E_ARG for zero or non-finite
+   ones).  Positions on periodic axes are wrapped into [0, n).  Periodic
+   axes must exceed twice the particle reach (circumradius + detection
+   margin). */
 hlbm_status hlbm_init_particles(hlbm_ctx *ctx, int n, const int *shape,
                                 const double *size, const double *density,
                                 const double *X, const double *q,
                                 const double *U, const double *omega);
 
-/* Set f* = f^eq(rho, u) on every node, then couple the particles to the
-   fluid at their current state: node ownership, rough contact detection
-   (the initial contact list) and the momentum-exchange force. */
+/* Set f* = f^eq(rho, u) (eq. (13)) on every node, then couple the particles
+   to the fluid at their current state, as before the first step of
+   Algorithm 1: node ownership and coupling (Sec. 3.2), rough contact
+   detection (Sec. 3.3.1; the initial contact list) and the
+   momentum-exchange force of eqs. (16)-(18). */
 hlbm_status hlbm_init_fluid_equilibrium(hlbm_ctx *ctx, double rho,
                                         const double u[3]);
 
 /* Same, from a host FP64 population field [19][nz][ny][nx]. */
 hlbm_status hlbm_set_populations(hlbm_ctx *ctx, const double *f);
 
-/* Advance nsteps coupled time steps (asynchronous on the context stream).
-   Order per step (Algorithm 1, one sub-step): contact treatment, gravity and
-   Newton-Euler update, particle-to-fluid coupling with rough detection,
-   collide-and-stream with the fluid-to-particle momentum exchange.  With one
-   contact sub-step and no timing in use, the contact treatment of every step
-   after the first of a call runs on a second stream of the context beside
-   the previous step's lattice passes (it reads nothing they write); the call
-   ends with no such work pending, and the results are those of strictly
-   ordered steps, bit for bit. */
+/* Advance nsteps coupled time steps of Algorithm 1 (Sec. 4.4; asynchronous
+   on the context stream).  Order per step (one sub-step): contact treatment
+   (Sec. 3.3.1, eqs. (4)-(9)), gravity and Newton-Euler update (eqs.
+   (2)-(3)), particle-to-fluid coupling with rough detection (Sec. 3.2,
+   Sec. 3.3.1), collide-and-stream (eqs. (10)-(15)) with the fluid-to-
+   particle momentum exchange (eqs. (16)-(18)).  With one contact sub-step
+   and no timing in use, the contact treatment of every step after the
+   first of a call runs on a second stream of the context beside the
+   previous step's lattice pass (it reads nothing that pass writes); the
+   call ends with no such work pending, and the results are those of
+   strictly ordered steps, bit for bit. */
 hlbm_status hlbm_step(hlbm_ctx *ctx, int nsteps);
 
-/* Use (1) or stop using (0) captured HIP graphs for hlbm_step: with one
-   contact sub-step, calls replay 8-step graphs (the overlapped contact
-   treatment captured inside) while at least 8 steps remain, and single-step
-   graphs for the rest; graphs are captured at first use per parity of the
-   population buffers and the contact tables. */
+/* Use (1) or stop using (0) captured HIP graphs for hlbm_step (the step of
+   Algorithm 1 as one launch): with one contact sub-step, calls replay
+   8-step graphs (the overlapped contact treatment captured inside) while
+   at least 8 steps remain, and single-step graphs for the rest.  The graphs
+   of the parities the next steps can reach are captured (not run) when
+   graphs are switched on, at initialisation and after hlbm_set_state, so
+   that later hlbm_step calls only launch them. */
 hlbm_status hlbm_use_graph(hlbm_ctx *ctx, int on);
 
-/* Per-kernel timing of the next steps: hlbm_step records HIP events on the
-   context stream around each of its seven kernel launches (bookkeeping
-   clear, contact treatment, particle motion + tile binning, contact
-   carry-over, coupling map + rough detection, stream-collide lattice pass,
-   momentum exchange) for up to max_steps steps (graphs and the overlapped
-   contact treatment are bypassed meanwhile).  hlbm_timing_end synchronises and returns the summed
-   milliseconds per kernel in that order, kernel_ms[7], and the number of
-   timed steps. */
+/* Per-kernel timing of the next steps (measurement, no paper passage):
+   hlbm_step records HIP events on the context stream around each of its
+   kernel launches (bookkeeping clear, contact treatment, particle motion +
+   tile binning, contact carry-over, coupling map + rough detection,
+   stream-collide lattice pass (with the momentum exchange for FP64 and
+   FP32 storage), and the separate momentum-exchange pass, which runs for
+   binary16 storage only and is zero otherwise) for up to max_steps steps (graphs and the
+   overlapped contact treatment are bypassed meanwhile).  hlbm_timing_end
+   synchronises and returns the summed milliseconds per kernel in that
+   order, kernel_ms[7], and the number of timed steps. */
 hlbm_status hlbm_timing_begin(hlbm_ctx *ctx, int max_steps);
 hlbm_status hlbm_timing_end(hlbm_ctx *ctx, double *kernel_ms, int *nsteps);
 
 /* Wait for queued work; raise device-side error flags. */
 hlbm_status hlbm_sync(hlbm_ctx *ctx);
 
-/* Hydrodynamic and contact force/torque that moved the particles in the
-   last step ([n][3] each; any pointer may be NULL). */
+/* Forces and torques that moved the particles in the last step ([n][3]
+   each, FP64; any pointer may be NULL): hydrodynamic F_h, T_h of eqs.
+   (16)-(18) and contact F_c, T_c summed over the particle's contacts,
+   eqs. (4)-(9). */
 hlbm_status hlbm_read_forces(hlbm_ctx *ctx, double *Fh, double *Th,
                              double *Fc, double *Tc);
 
+/* Particle state after the last step (eqs. (2)-(3)): centre of mass X
+   [n][3], unit quaternion q [n][4], velocity U and angular velocity omega
+   [n][3]; NULL skips. */
 hlbm_status hlbm_read_particles(hlbm_ctx *ctx, double *X, double *q,
                                 double *U, double *omega);
 
-/* Current contact list, sorted by (a, b); *n_out = number of records (may
-   exceed capacity, in which case only `capacity` are written). */
+/* Current contact list, sorted by (a, b): per pair the rough-detection
+   count and node box, the corrected box, and the results of the latest
+   treatment (Sec. 3.3.1: overlap volume, contact point, normal, depth; eqs.
+   (4)-(6): damping factor fixed at onset, normal force, force on a and b).
+   *n_out = number of records (may exceed capacity, in which case only
+   `capacity` are written). */
 hlbm_status hlbm_read_contacts(hlbm_ctx *ctx, int capacity,
                                hlbm_contact *out, int *n_out);
 
-/* Density and velocity moments of the stored post-collision field, and the
-   node owner (-1 = fluid) at the current particle state.  NULL skips. */
+/* Density and velocity moments (eq. (11)) of the stored post-collision
+   field, and the node owner (-1 = fluid) at the current particle state
+   (Sec. 3.2, the particle whose signed distance is smallest).  NULL skips.
+   The coupling weight B and particle velocity u_p of the owner come from
+   hlbm_read_coupling. */
 hlbm_status hlbm_read_fields(hlbm_ctx *ctx, double *rho, double *u,
                              int *owner);
 
@@ -235,28 +263,34 @@ hlbm_status hlbm_read_populations(hlbm_ctx *ctx, double *f);
    node.  FP64, host arrays of N and 3N values; NULL skips. */
 hlbm_status hlbm_read_coupling(hlbm_ctx *ctx, double *B, double *up);
 
-/* Latest detection: pairs with count > 0 and the sum of their counts
-   (overlap node count); totals accumulated over all steps so far. */
+/* Rough contact detection (Sec. 3.3.1) and treatment counts: pairs with a
+   flagged node in the latest detection and the sum of their flagged-node
+   counts; that sum accumulated over all detections so far; steps taken;
+   midpoint samples of the latest treatment (6 N_c^2 for the box correction
+   and N_c^3 for the overlap integration per treated pair, each evaluating
+   both members' signed distances).  NULL skips. */
 hlbm_status hlbm_counters(hlbm_ctx *ctx, long long *pairs,
                           long long *cells, long long *total_cells,
-                          long long *steps);
+                          long long *steps, long long *samples);
 
-/* The context's stream (hipStream_t) and precision. */
+/* The context's stream (hipStream_t). */
 void *hlbm_stream(const hlbm_ctx *ctx);
 
-/* The uniform fluid acceleration the next collision uses (fluid_accel +
-   balance force; with balance mode 2 read from the device). */
+/* The uniform fluid acceleration the next collision uses in eq. (15)
+   (fluid_accel + the balance force of Sec. 5.1; with balance mode 2 read
+   from the device). */
 hlbm_status hlbm_fluid_acceleration(hlbm_ctx *ctx, double a[3]);
 
-/* Checkpoint and resume.  hlbm_get_state copies the whole step state
-   (populations in their storage precision, particle records, candidate
-   lists and momentum-exchange partial sums, both contact tables, owner map,
-   counters, step count) into a caller-owned host buffer; with blob = NULL it
-   only sets *bytes to the size needed.  hlbm_set_state restores such a blob
-   into a context created with the same parameters and initialised with the
-   same particle set (count and shapes); the next hlbm_step continues exactly
-   where the saved context stood.  E_ARG for a blob of another
-   configuration. */
+/* Checkpoint and resume of the state between two steps of Algorithm 1.
+   hlbm_get_state copies the whole step state (populations in their
+   storage precision, particle records, candidate lists and
+   momentum-exchange partial sums, both contact tables, owner map,
+   counters, step count) into a caller-owned host buffer; with blob = NULL
+   it only sets *bytes to the size needed.  hlbm_set_state restores such a
+   blob into a context created with the same parameters and initialised
+   with the same particle set (count and shapes); the next hlbm_step
+   continues exactly where the saved context stood.  E_ARG for a blob of
+   another configuration. */
 hlbm_status hlbm_get_state(hlbm_ctx *ctx, void *blob, size_t *bytes);
 hlbm_status hlbm_set_state(hlbm_ctx *ctx, const void *blob, size_t bytes);
 
@@ -267,8 +301,8 @@ hlbm_status hlbm_set_state(hlbm_ctx *ctx, const void *blob, size_t bytes);
    (eqs. (16)-(18)) and the Newton-Euler update (eqs. (2)-(3)).  The owner
    of every node and the contact forces (eqs. (4)-(9)) of the recorded
    forward run are held fixed: the discrete decisions of the forward pass are
-   not differentiated.  FP64 form and fully periodic boxes only (E_ARG
-   otherwise).
+   not differentiated.  FP64 form, fully periodic boxes, balance modes 0 and
+   1, spheres, cubes and octahedra only (E_ARG otherwise).
 
    hlbm_adjoint_record: from the current state, runs `ksteps` steps and keeps
    a device snapshot of the whole state every `ckpt_every` steps (plus the
@@ -284,20 +318,36 @@ hlbm_status hlbm_set_state(hlbm_ctx *ctx, const void *blob, size_t bytes);
                       inertia, gravity-buoyancy, and the balance acceleration
                       of a balanced box);
      dJ_dtheta0[3n]   derivative by a world-frame rotation of each particle's
-                      initial orientation, q -> exp(theta/2) (x) q;
-     dJ_dq0[4n]       the same as a quaternion gradient tangent to |q| = 1,
-                      2 (0, dJ_dtheta0) (x) q;
-     dJ_dX0, dJ_dU0, dJ_domega0 [3n]  derivatives by the initial position,
-                      velocity and angular velocity.
+                      orientation at the start of the window,
+                      q -> exp(theta/2) (x) q;
+     dJ_dq0[4n]       the same as a quaternion gradient tangent to |q| = 1 at
+                      that (unit) orientation, 2 (0, dJ_dtheta0) (x) q;
+     dJ_dX0, dJ_dU0, dJ_domega0 [3n]  derivatives by the position, velocity
+                      and angular velocity at the start of the window.
    The context is left at the end of the recorded window.  Reductions use
-   FP64 atomics, so results can differ from run to run in the last bits. */
+   FP64 atomics, so results can differ from run to run in the last bits.
+
+   hlbm_adjoint: record and gradient in one call (the form of the
+   autograd wrapper): ksteps steps from the current state with checkpoints
+   every ckpt_every steps, then dJ_ds and dJ_dq0 of
+   J = sum_p dJ_dU[p] . U_p. */
 hlbm_status hlbm_adjoint_record(hlbm_ctx *ctx, int ksteps, int ckpt_every);
 hlbm_status hlbm_adjoint_gradient(hlbm_ctx *ctx, const double *dJ_dU,
                                   double *dJ_ds, double *dJ_dtheta0,
                                   double *dJ_dq0, double *dJ_dX0,
                                   double *dJ_dU0, double *dJ_domega0);
+hlbm_status hlbm_adjoint(hlbm_ctx *ctx, int ksteps, int ckpt_every,
+                         const double *dJ_dU, double *dJ_ds, double *dJ_dq0);
 
+/* Hash of the sources the library was built from (16 hex digits: SHA-256
+   over the kernel sources and this header); the Python binding refuses a
+   library whose hash differs from the sources beside it. */
+const char *hlbm_build_hash(void);
+
+/* Message of the context's last error (or of a null context). */
 const char *hlbm_last_error(const hlbm_ctx *ctx);
+
+/* Release the context and the device memory it owns. */
 void hlbm_destroy(hlbm_ctx *ctx);
 
 #ifdef __cplusplus

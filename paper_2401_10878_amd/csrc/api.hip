@@ -121,6 +121,8 @@ void drop_graphs(Ctx& c) {
 // back to their starting values)
 constexpr int GRAPH_STEPS = 8;
 
+hlbm_status prepare_graphs(Ctx& c);
+
 // Coupling and detection at the current particle state with the current
 // populations as f*: ownership map, initial contact list, and the
 // momentum-exchange force that moves the particles in the first step.
@@ -138,7 +140,8 @@ hlbm_status prologue(Ctx& c) {
   if (c.ph.bal_mode == 2) HIPCHECK(launch_balance(c, c.fbuf[c.cur], 1));
   c.step = 0;
   c.fluid_ready = true;
-  return check_flags(c);
+  const hlbm_status st = check_flags(c);
+  return st != HLBM_OK ? st : prepare_graphs(c);
 }
 
 // The launch sequence of one time step with population parity p (buffers
@@ -188,11 +191,66 @@ hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev, int pre) {
     if ((e = launch_treat(c, c.tab[t], c.side))) return e;
     if ((e = hipEventRecord(c.ev_treat, c.side))) return e;
   }
+  // the lattice pass also sums the momentum exchange of the next step for
+  // FP64 and FP32 storage (the last timing slot stays empty); for binary16
+  // storage the separate pass does, over the populations just stored
   if ((e = launch_lattice(c, c.fbuf[p], c.fbuf[1 - p]))) return e;
   if (c.ph.bal_mode == 2 && (e = launch_balance(c, nullptr, 0))) return e;
   if ((e = mark())) return e;
-  if ((e = launch_mea(c, c.fbuf[1 - p]))) return e;
+  if (c.precision == HLBM_FP16S && (e = launch_mea(c, c.fbuf[1 - p]))) return e;
   return mark();
+}
+
+// Capture and instantiate the graph of one step (multi = false) or of
+// GRAPH_STEPS steps with the overlapped contact treatment (multi = true)
+// starting from population parity key / 2 and table parity key % 2.
+// Capturing runs nothing.
+hlbm_status capture_graph(Ctx& c, int key, bool multi) {
+  const int p = key / 2, t = key % 2;
+  hipGraph_t gr;
+  HIPCHECK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  if (multi) {
+    for (int j = 0; j < GRAPH_STEPS && e == hipSuccess; ++j) {
+      const int pre = (j > 0 ? PRE_DONE : 0) | (j + 1 < GRAPH_STEPS ? PRE_NEXT : 0);
+      e = enqueue_step(c, p ^ (j & 1), t ^ (j & 1), nullptr, pre);
+    }
+  } else {
+    e = enqueue_step(c, p, t, nullptr, 0);
+  }
+  hipError_t e2 = hipStreamEndCapture(c.stream, &gr);
+  if (e != hipSuccess || e2 != hipSuccess)
+    return fail(c, HLBM_E_DEVICE, "graph capture: %s",
+                hipGetErrorString(e != hipSuccess ? e : e2));
+  hipGraphExec_t* slot = multi ? &c.gexec_n[key] : &c.gexec[key];
+  e = hipGraphInstantiate(slot, gr, nullptr, nullptr, 0);
+  hipGraphDestroy(gr);
+  if (e != hipSuccess)
+    return fail(c, HLBM_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+  (multi ? c.graph_n_ready : c.graph_ready)[key] = true;
+  return HLBM_OK;
+}
+
+// Capture every graph that steps from the current parities can replay: the
+// single-step graphs of the current (population, table) parity and of the
+// one after a step, and, with one contact sub-step, the multi-step graphs of
+// both (a multi-step graph returns to its starting parities).  A timed window
+// of hlbm_step calls then launches graphs only.
+hlbm_status prepare_graphs(Ctx& c) {
+  if (!c.use_graph || !c.fluid_ready) return HLBM_OK;
+  const int k0 = 2 * c.cur + c.tcur;
+  const int k1 = 2 * (1 - c.cur) + ((c.n_sub & 1) ? 1 - c.tcur : c.tcur);
+  for (int key : {k0, k1}) {
+    if (!c.graph_ready[key]) {
+      const hlbm_status st = capture_graph(c, key, false);
+      if (st != HLBM_OK) return st;
+    }
+    if (c.n_sub == 1 && c.side && !c.graph_n_ready[key]) {
+      const hlbm_status st = capture_graph(c, key, true);
+      if (st != HLBM_OK) return st;
+    }
+  }
+  return HLBM_OK;
 }
 
 // the step that the next hlbm_step would run, and the parities after it
@@ -391,7 +449,7 @@ hlbm_status hlbm_create(const hlbm_params* params, void* stream, hlbm_ctx** out)
              hipMalloc(&c.counters, sizeof(Counters)) == hipSuccess &&
              hipMalloc(&c.scratch, sizeof(double) * ncell) == hipSuccess &&
              (P.balance != 2 ||
-              hipMalloc(&c.bal_part, sizeof(double) * 4 * (size_t)nlt) == hipSuccess);
+              hipMalloc(&c.bal_part, sizeof(double) * 4 * ((size_t)nlt + BAL_PARTS)) == hipSuccess);
   for (int k = 0; k < 2 && okm; ++k) {
     c.tab[k].cap = cap;
     okm = hipMalloc(&c.tab[k].keys, sizeof(uint64_t) * cap) == hipSuccess &&
@@ -714,7 +772,8 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
     double emax = 0.0;
     for (int i = 0; i < n; ++i)
       emax = fmax(emax, circumradius(c, sh[i], sz[i]));
-    const double span = 2.0 * (emax + margin) + 3.0;
+    // the lattice-block reach (see k_particles): eps/2 + 1 node beyond the body
+    const double span = 2.0 * (emax + fmax(margin, 0.5 * c.ph.eps + 1.25)) + 3.0;
     const int ts[3] = {LX, LY, LZ}, nt[3] = {c.g.ltx, c.g.lty, c.g.ltz};
     const int nn3[3] = {c.g.nx, c.g.ny, c.g.nz};
     const bool per3[3] = {true, true, c.g.periodic_z != 0};
@@ -823,22 +882,8 @@ hlbm_status hlbm_step(hlbm_ctx* h, int nsteps) {
       // the first fork and is joined back by the last step
       const int key = 2 * c.cur + c.tcur;
       if (!c.graph_n_ready[key]) {
-        hipGraph_t gr;
-        HIPCHECK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = hipSuccess;
-        for (int j = 0; j < GRAPH_STEPS && e == hipSuccess; ++j) {
-          const int pre = (j > 0 ? PRE_DONE : 0) | (j + 1 < GRAPH_STEPS ? PRE_NEXT : 0);
-          e = enqueue_step(c, c.cur ^ (j & 1), c.tcur ^ (j & 1), nullptr, pre);
-        }
-        hipError_t e2 = hipStreamEndCapture(c.stream, &gr);
-        if (e != hipSuccess || e2 != hipSuccess)
-          return fail(c, HLBM_E_DEVICE, "graph capture: %s",
-                      hipGetErrorString(e != hipSuccess ? e : e2));
-        e = hipGraphInstantiate(&c.gexec_n[key], gr, nullptr, nullptr, 0);
-        hipGraphDestroy(gr);
-        if (e != hipSuccess)
-          return fail(c, HLBM_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
-        c.graph_n_ready[key] = true;
+        const hlbm_status st = capture_graph(c, key, true);
+        if (st != HLBM_OK) return st;
       }
       HIPCHECK(hipGraphLaunch(c.gexec_n[key], c.stream));
       c.step += GRAPH_STEPS;
@@ -846,18 +891,8 @@ hlbm_status hlbm_step(hlbm_ctx* h, int nsteps) {
     } else if (c.use_graph) {
       const int key = 2 * c.cur + c.tcur;
       if (!c.graph_ready[key]) {
-        hipGraph_t gr;
-        HIPCHECK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue_step(c, c.cur, c.tcur, nullptr, 0);
-        hipError_t e2 = hipStreamEndCapture(c.stream, &gr);
-        if (e != hipSuccess || e2 != hipSuccess)
-          return fail(c, HLBM_E_DEVICE, "graph capture: %s",
-                      hipGetErrorString(e != hipSuccess ? e : e2));
-        e = hipGraphInstantiate(&c.gexec[key], gr, nullptr, nullptr, 0);
-        hipGraphDestroy(gr);
-        if (e != hipSuccess)
-          return fail(c, HLBM_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
-        c.graph_ready[key] = true;
+        const hlbm_status st = capture_graph(c, key, false);
+        if (st != HLBM_OK) return st;
       }
       HIPCHECK(hipGraphLaunch(c.gexec[key], c.stream));
       c.cur = 1 - c.cur;
@@ -883,7 +918,7 @@ hlbm_status hlbm_step(hlbm_ctx* h, int nsteps) {
 hlbm_status hlbm_use_graph(hlbm_ctx* h, int on) {
   if (!h) return HLBM_E_ARG;
   h->c.use_graph = on != 0;
-  return HLBM_OK;
+  return prepare_graphs(h->c);
 }
 
 hlbm_status hlbm_timing_begin(hlbm_ctx* h, int max_steps) {
@@ -1083,7 +1118,8 @@ hlbm_status hlbm_read_populations(hlbm_ctx* h, double* f) {
 }
 
 hlbm_status hlbm_counters(hlbm_ctx* h, long long* pairs, long long* cells,
-                          long long* total_cells, long long* steps) {
+                          long long* total_cells, long long* steps,
+                          long long* samples) {
   if (!h) return HLBM_E_ARG;
   Ctx& c = h->c;
   Counters k;
@@ -1093,6 +1129,7 @@ hlbm_status hlbm_counters(hlbm_ctx* h, long long* pairs, long long* cells,
   if (cells) *cells = (long long)k.det_cells;
   if (total_cells) *total_cells = (long long)k.total_cells;
   if (steps) *steps = c.step;
+  if (samples) *samples = (long long)k.samples;
   return HLBM_OK;
 }
 
@@ -1225,7 +1262,8 @@ hlbm_status hlbm_set_state(hlbm_ctx* h, const void* blob, size_t bytes) {
   HIPCHECK(hipStreamSynchronize(c.stream));
   free_adjoint(c);
   c.fluid_ready = true;
-  return check_flags(c);
+  st = check_flags(c);
+  return st != HLBM_OK ? st : prepare_graphs(c);
 }
 
 hlbm_status hlbm_adjoint_record(hlbm_ctx* h, int ksteps, int ckpt_every) {
@@ -1368,6 +1406,20 @@ hlbm_status hlbm_adjoint_gradient(hlbm_ctx* h, const double* dJ_dU, double* dJ_d
   }
   return check_flags(c);
 }
+
+hlbm_status hlbm_adjoint(hlbm_ctx* h, int ksteps, int ckpt_every, const double* dJ_dU,
+                         double* dJ_ds, double* dJ_dq0) {
+  hlbm_status st = hlbm_adjoint_record(h, ksteps, ckpt_every);
+  if (st != HLBM_OK) return st;
+  return hlbm_adjoint_gradient(h, dJ_dU, dJ_ds, nullptr, dJ_dq0, nullptr, nullptr, nullptr);
+}
+
+// the build passes the hash of the sources (paper_2401_10878_amd/build.py);
+// a compile without it reports a hash no source set has
+#ifndef HLBM_SOURCE_HASH
+#define HLBM_SOURCE_HASH "unhashed"
+#endif
+const char* hlbm_build_hash(void) { return HLBM_SOURCE_HASH; }
 
 const char* hlbm_last_error(const hlbm_ctx* h) {
   return h ? h->c.err.c_str() : "null context";

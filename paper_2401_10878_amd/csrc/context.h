@@ -37,6 +37,7 @@ struct Counters {
   unsigned long long det_cells;    // sum of counts (latest detection)
   unsigned long long total_cells;  // sum over all detections
   unsigned long long steps;
+  unsigned long long samples;      // midpoint samples of the latest treatment
   int tile_overflow;
   int pair_overflow;
   int unstable;

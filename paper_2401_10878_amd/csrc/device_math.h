@@ -27,6 +27,7 @@ constexpr int DX = 4, DY = 4, DZ = 4;
 constexpr int LX = 64, LY = 4, LZ = 1;
 constexpr int LCAP_MAX = 64;    // lattice-block candidate capacity
 constexpr int MAXC = 32;        // contacts per particle in one step
+constexpr int BAL_PARTS = 256;  // first-stage workgroups of the balance sums
 // owner-map entry: the owning particle's id, or -1 (no owner)
 __device__ inline int owner_id(int v) { return v < 0 ? -1 : v; }
 constexpr int WAVE = 64;
@@ -110,6 +111,26 @@ struct Particles {
   const double* Iinv;   // [n][9] inverse body inertia tensor (polyhedra)
   const PolyDev* poly;  // [MAXPOLY] polyhedron types
 };
+
+// Half extent along world axis k of a body with rotation R: exact for cubes
+// and polyhedra (largest |world coordinate| of a vertex), the circumradius
+// for spheres and octahedra.
+__device__ inline double half_extent(int shape, double size, const double* R, int k,
+                                     const PolyDev* poly) {
+  double e = size;
+  if (shape == 1) e = 0.5 * size * (fabs(R[3 * k]) + fabs(R[3 * k + 1]) + fabs(R[3 * k + 2]));
+  if (poly && shape >= POLY0) {
+    CPoly* pd = (CPoly*)poly + (shape - POLY0);
+    e = 0.0;
+    for (int i = 0; i < pd->nv; ++i) {
+      const double c = fabs((R[3 * k] * pd->v[i][0] + R[3 * k + 1] * pd->v[i][1]) +
+                            R[3 * k + 2] * pd->v[i][2]);
+      e = c > e ? c : e;
+    }
+    e = size * e;
+  }
+  return e;
+}
 
 // Rotation matrix of q = (w, x, y, z).
 __device__ inline void quat_to_rot(const double* q, double* R) {
@@ -317,6 +338,98 @@ __device__ inline T poly_sdf(const PolyDev* table, int t, const T* p, T* gb, T f
   return poly_sdf_unit<T>(base + t, p, gb, far);
 }
 
+// The same distance in the oracle's own arithmetic, for the FP64 decisions
+// that must come out bit for bit alike (node ownership and rough detection,
+// and the box correction and overlap integration of a contact): the plane
+// distances of every face; inside, the largest; outside, the smallest of
+// the distances to the face interiors the point projects into (faces it is
+// above, the projection tested against each boundary edge with a cross
+// product) and to every undirected edge (segment projection divided by
+// |e|^2), faces first and then edges in table order on ties.  With far <
+// inf, an outside point whose largest plane distance exceeds far returns
+// that lower bound (for the integration's inside test only).
+__device__ inline double poly_sdf_exact_unit(CPoly* P, const double* p, double* gb,
+                                             double far) {
+  const int nf = P->nf;
+  double best = -1e300;
+  int fm = 0;
+  for (int f = 0; f < nf; ++f) {
+    const HLBM_CONST double* n = P->pl[f];
+    const double d = (n[0] * p[0] + n[1] * p[1]) + n[2] * p[2] - n[3];
+    if (d > best) {
+      best = d;
+      fm = f;
+    }
+  }
+  if (best <= 0.0 || best > far) {
+    if (gb)
+      for (int k = 0; k < 3; ++k) gb[k] = P->pl[fm][k];
+    return best;
+  }
+  double dmin2 = 1e300, c0 = 0.0, c1 = 0.0, c2 = 0.0;
+  int face_hit = -1;
+  for (int f = 0; f < nf; ++f) {
+    const HLBM_CONST double* n = P->pl[f];
+    const double d = (n[0] * p[0] + n[1] * p[1]) + n[2] * p[2] - n[3];
+    if (d <= 0.0) continue;
+    const double q0 = p[0] - d * n[0], q1 = p[1] - d * n[1], q2 = p[2] - d * n[2];
+    const int b0 = P->fs[f], cnt = P->fs[f + 1] - b0;
+    bool inside = true;
+    for (int j = 0; j < cnt; ++j) {
+      const HLBM_CONST double* a = P->v[P->fv[b0 + j]];
+      const HLBM_CONST double* b = P->v[P->fv[b0 + (j + 1 == cnt ? 0 : j + 1)]];
+      const double e0 = b[0] - a[0], e1 = b[1] - a[1], e2 = b[2] - a[2];
+      const double w0 = q0 - a[0], w1 = q1 - a[1], w2 = q2 - a[2];
+      const double x0 = e1 * w2 - e2 * w1, x1 = e2 * w0 - e0 * w2, x2 = e0 * w1 - e1 * w0;
+      if ((x0 * n[0] + x1 * n[1]) + x2 * n[2] < 0.0) inside = false;
+    }
+    if (inside && d * d < dmin2) {
+      dmin2 = d * d;
+      face_hit = f;
+      c0 = q0;
+      c1 = q1;
+      c2 = q2;
+    }
+  }
+  for (int i = 0; i < P->ne; ++i) {
+    const HLBM_CONST double* a = P->v[P->e[i][0]];
+    const HLBM_CONST double* b = P->v[P->e[i][1]];
+    const double e0 = b[0] - a[0], e1 = b[1] - a[1], e2 = b[2] - a[2];
+    const double w0 = p[0] - a[0], w1 = p[1] - a[1], w2 = p[2] - a[2];
+    const double ee = (e0 * e0 + e1 * e1) + e2 * e2;
+    double t = ((w0 * e0 + w1 * e1) + w2 * e2) / ee;
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    const double y0 = a[0] + t * e0, y1 = a[1] + t * e1, y2 = a[2] + t * e2;
+    const double dx = p[0] - y0, dy = p[1] - y1, dz = p[2] - y2;
+    const double d2 = (dx * dx + dy * dy) + dz * dz;
+    if (d2 < dmin2) {
+      dmin2 = d2;
+      face_hit = -1;
+      c0 = y0;
+      c1 = y1;
+      c2 = y2;
+    }
+  }
+  const double d = sqrt(dmin2);
+  if (gb) {
+    if (face_hit >= 0) {
+      for (int k = 0; k < 3; ++k) gb[k] = P->pl[face_hit][k];
+    } else {
+      gb[0] = (p[0] - c0) / d;
+      gb[1] = (p[1] - c1) / d;
+      gb[2] = (p[2] - c2) / d;
+    }
+  }
+  return d;
+}
+__device__ inline double poly_sdf_exact(const PolyDev* table, int t, const double* p,
+                                        double* gb, double far) {
+  CPoly* base = (CPoly*)table;
+  const int t0 = __builtin_amdgcn_readfirstlane(t);
+  if (__ballot(t != t0) == 0) return poly_sdf_exact_unit(base + t0, p, gb, far);
+  return poly_sdf_exact_unit(base + t, p, gb, far);
+}
+
 // Exact signed distance (negative inside) at world offset r from the centre.
 // sphere: |r| - radius.  cube (edge a): body offset p = R^T r,
 // q_k = |p_k| - a/2, d = |max(q, 0)| + min(max_k q_k, 0).
@@ -351,6 +464,22 @@ __device__ inline double sdf(int shape, double size, const double* R,
   const double outside = s2 > 0.0 ? sqrt(s2) : 0.0;
   const double inside = fmin(fmax(fmax(q0, q1), q2), 0.0);
   return outside + inside;
+}
+
+// sdf and sdf_grad with a polyhedron evaluated in the oracle's arithmetic
+// (the body offset divided by the scale, poly_sdf_exact): the forms of the
+// FP64 decisions; the other shapes share sdf / sdf_grad, which already
+// follow it.
+__device__ inline double sdf_exact(int shape, double size, const double* R,
+                                   double r0, double r1, double r2, const PolyDev* poly) {
+  if (poly && shape >= POLY0) {
+    double p[3];
+    p[0] = (R[0] * r0 + R[3] * r1 + R[6] * r2) / size;
+    p[1] = (R[1] * r0 + R[4] * r1 + R[7] * r2) / size;
+    p[2] = (R[2] * r0 + R[5] * r1 + R[8] * r2) / size;
+    return size * poly_sdf_exact(poly, shape - POLY0, p, nullptr, 1e300);
+  }
+  return sdf(shape, size, R, r0, r1, r2, poly);
 }
 
 // The same signed distance in FP32 arithmetic (inputs rounded to FP32), for
@@ -470,6 +599,22 @@ __device__ inline double sdf_grad(int shape, double size, const double* R,
   for (int k = 0; k < 3; ++k)
     g[k] = R[3 * k + 0] * gb[0] + R[3 * k + 1] * gb[1] + R[3 * k + 2] * gb[2];
   return outside + inside;
+}
+
+__device__ inline double sdf_grad_exact(int shape, double size, const double* R,
+                                        const double* r, double* g, const PolyDev* poly,
+                                        double far = 1e300) {
+  if (poly && shape >= POLY0) {
+    double p[3], gb[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) p[k] = (R[0 + k] * r[0] + R[3 + k] * r[1] + R[6 + k] * r[2]) / size;
+    const double d = size * poly_sdf_exact(poly, shape - POLY0, p, gb, far / size);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      g[k] = R[3 * k + 0] * gb[0] + R[3 * k + 1] * gb[1] + R[3 * k + 2] * gb[2];
+    return d;
+  }
+  return sdf_grad(shape, size, R, r, g, poly, far);
 }
 
 // Coupling weight B(d): 1 for d <= -eps/2, 0 for d >= eps/2, cos^2 ramp.

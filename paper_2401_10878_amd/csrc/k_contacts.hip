@@ -50,6 +50,7 @@ __global__ void k_clear_step(PairTable next, double* Fc, double* Tc, int np,
   if (tid == 0) {
     ctr->det_pairs = 0;
     ctr->det_cells = 0;
+    ctr->samples = 0;
   }
 }
 
@@ -105,8 +106,8 @@ struct Body {
 __device__ inline double body_sdf(const Body& b, const double* y, double* g,
                                   double far = 1e300) {
   const double r[3] = {y[0] - b.X[0], y[1] - b.X[1], y[2] - b.X[2]};
-  if (g) return sdf_grad(b.shape, b.size, b.R, r, g, b.poly, far);
-  return sdf(b.shape, b.size, b.R, r[0], r[1], r[2], b.poly);
+  if (g) return sdf_grad_exact(b.shape, b.size, b.R, r, g, b.poly, far);
+  return sdf_exact(b.shape, b.size, b.R, r[0], r[1], r[2], b.poly);
 }
 
 // enlarged distance of member b (particle, or wall -1 bottom / -2 top)
@@ -181,9 +182,23 @@ __global__ __launch_bounds__(256) void k_treat(PairTable t, Particles P, Geom g,
 
   double lo[3], hi[3];
   const bool carried = rec->carried != 0;
+  // a new particle-wall pair: the flagged nodes lie on the fluid side of
+  // the wall plane and the overlap beyond it, so the wall-side face starts
+  // at the far side of the enlarged body (half extent along z plus the
+  // enlargement) and the correction moves it onto the body
+  double wall_lo = 1e300, wall_hi = -1e300;
+  if (!carried && b < 0) {
+    const double ez = half_extent(A.shape, A.size, A.R, 2, A.poly) + delta;
+    if (b == -1) wall_lo = A.X[2] - ez;
+    else wall_hi = A.X[2] + ez;
+  }
   for (int k = 0; k < 3; ++k) {
     lo[k] = carried ? rec->lo[k] : (double)rec->rlo[k] - 0.5;
     hi[k] = carried ? rec->hi[k] : (double)rec->rhi[k] + 0.5;
+    if (k == 2) {
+      lo[k] = fmin(lo[k], wall_lo);
+      hi[k] = fmax(hi[k], wall_hi);
+    }
     const double mid = 0.5 * (lo[k] + hi[k]);
     const int sh = image_shift(mid - A.X[k], L[k], per[k]);
     lo[k] += (double)(sh * (int)L[k]);
@@ -192,12 +207,14 @@ __global__ __launch_bounds__(256) void k_treat(PairTable t, Particles P, Geom g,
 
   // ---- box correction, one pass -----------------------------------------
   bool ok = true;
+  int nfaces = 0;   // faces sampled (the box can empty on the way)
   // fully unrolled, so that the face's axis k (and u, v) index registers
 #pragma unroll
   for (int face = 0; face < 6; ++face) {
     for (int k = 0; k < 3; ++k)
       if (!(hi[k] > lo[k])) ok = false;
     if (!ok) continue;
+    ++nfaces;
     const int k = face / 2, plus = face % 2;
     const int u = k == 0 ? 1 : 0, v = k == 2 ? 1 : 2;
     const double hu = (hi[u] - lo[u]) / (double)nc;
@@ -255,6 +272,10 @@ __global__ __launch_bounds__(256) void k_treat(PairTable t, Particles P, Geom g,
     }
     dmax = wave_max(dmax);
   }
+  // midpoint samples of this record (each evaluates both members)
+  if (lane == 0)
+    atomicAdd(&ctr->samples,
+              (unsigned long long)(nfaces * nc * nc + (ok ? nc * nc * nc : 0)));
   if (!ok || n_in == 0) {
     if (lane == 0) {
       rec->keep = 0;

@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
         const double r0 = minimg(fx - X0, Lx, true);
         const double r1 = minimg(fy - X1, Ly, true);
         const double r2 = minimg(fz - X2, Lz, perz);
-        const double d = sdf(P.shape[p], P.size[p], R, r0, r1, r2, POLY ? P.poly : nullptr);
+        const double d = sdf_exact(P.shape[p], P.size[p], R, r0, r1, r2, POLY ? P.poly : nullptr);
         if (own_open && ((pown >> c) & 1ull) && d < own_t &&
             (d < bd || (d == bd && p < ep))) {
           bd = d;

@@ -1,5 +1,6 @@
-// D3Q19 stream-collide with the HLBM velocity-shift coupling, and the
-// momentum exchange of the next step as a pass of its own.
+// D3Q19 stream-collide with the HLBM velocity-shift coupling and the
+// momentum exchange of the next step in one pass (and the momentum exchange
+// as a pass of its own, for the initial state).
 //
 // Lattice pass, per node y (one lane), with the particle state already
 // advanced:
@@ -11,12 +12,15 @@
 //            f_i* = f_i^eq(rho, u + du) + (1 - 1/tau)(f_i - f_i^eq(rho, u))
 //            (BGK eq. (12) plus the EDM source eq. (14), rearranged)
 //
-// Momentum-exchange pass over the populations f* just written, eq. (16)
-// read with post-streaming populations: for a node x owned by o,
+// Momentum exchange, eq. (16) read with post-streaming populations: for a
+// node x owned by o,
 //   S(x) = sum_i (c_i - u_p(x)) f_i*(x) + (c_i + u_p(x)) f_opp(i)(x)
 // where f_opp(i)(x) is the value the next streaming brings to x.  The force
 // and torque on particle o are F = -sum S, T = -sum r x S over the nodes it
-// owns (eqs. (17)-(18)), summed per lattice block without atomics.
+// owns (eqs. (17)-(18)), summed per lattice block without atomics.  The
+// lattice pass pushes each value it stores into the two sums it enters (of
+// its own node and of the node it streams to); the separate pass pulls
+// both for an owned node.
 //
 // Storage is a template parameter: FP64, FP32, or binary16 deviations
 // h_i = f_i - w_i (FP32 arithmetic).
@@ -48,6 +52,7 @@ struct Store<double> {
   }
   __device__ static void st(double* p, int k, C v) { __builtin_nontemporal_store(v, p + k); }
   __device__ static C ldn(const double* p, int k) { return __builtin_nontemporal_load(p + k); }
+  __device__ static C as_stored(C v) { return v; }
 };
 template <>
 struct Store<float> {
@@ -59,6 +64,7 @@ struct Store<float> {
   }
   __device__ static void st(float* p, int k, C v) { __builtin_nontemporal_store(v, p + k); }
   __device__ static C ldn(const float* p, int k) { return __builtin_nontemporal_load(p + k); }
+  __device__ static C as_stored(C v) { return v; }
 };
 template <>
 struct Store<__half> {
@@ -74,6 +80,8 @@ struct Store<__half> {
   __device__ static C ldn(const __half* p, int k) {
     return __half2float(__ushort_as_half(__builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(p) + k)));
   }
+  // the value st writes, read back (round to nearest even)
+  __device__ static C as_stored(C v) { return __half2float(__float2half_rn(v)); }
 };
 template <typename S>
 __device__ inline double full_f(typename Store<S>::C h, int i) {
@@ -218,18 +226,160 @@ __device__ inline Nbr neighbours(const Geom& g, int x, int y, int z) {
   return nb;
 }
 
-// At most 128 VGPRs (four wavefronts per SIMD) without spills.  POLY: built
+// Velocity c_i of direction i (1..18) for a run-time index, from the order
+// rest, +-x, +-y, +-z, then the edge pairs (1,1,0), (-1,-1,0), (1,-1,0),
+// (-1,1,0) of the planes xy, xz, yz.
+__device__ inline void dir_of(int i, int& d0, int& d1, int& d2) {
+  d0 = d1 = d2 = 0;
+  if (i <= 6) {
+    const int a = (i - 1) >> 1, sg = (i & 1) ? 1 : -1;
+    d0 = a == 0 ? sg : 0;
+    d1 = a == 1 ? sg : 0;
+    d2 = a == 2 ? sg : 0;
+  } else {
+    const int k = i - 7, grp = k >> 2, j = k & 3;
+    const int s1 = (j == 0 || j == 2) ? 1 : -1, s2 = (j == 0 || j == 3) ? 1 : -1;
+    d0 = grp == 2 ? 0 : s1;
+    d1 = grp == 0 ? s2 : (grp == 2 ? s1 : 0);
+    d2 = grp == 0 ? 0 : s2;
+  }
+}
+
+// Masked moments of the stored post-collision deviations v_i (i >= 1) of
+// one node over the links in `mask` (bit i): m0 = sum v_i, m1 = sum c_i v_i
+// and the second moment Pi = sum c_i c_i^T v_i (six components).
+template <typename C>
+struct LinkMoments {
+  C m0, m1[3], pxx, pyy, pzz, pxy, pxz, pyz;
+};
+template <typename C>
+__device__ inline void link_zero(LinkMoments<C>& m) {
+  m.m0 = m.m1[0] = m.m1[1] = m.m1[2] = (C)0;
+  m.pxx = m.pyy = m.pzz = m.pxy = m.pxz = m.pyz = (C)0;
+}
+template <typename C>
+__device__ inline void link_add(LinkMoments<C>& m, C a, int i);
+template <typename C>
+__device__ inline LinkMoments<C> link_moments(const C* v, unsigned mask) {
+  LinkMoments<C> m;
+  link_zero(m);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) link_add(m, ((mask >> i) & 1u) ? v[i] : (C)0, i);
+  return m;
+}
+// adds value a of direction i
+template <typename C>
+__device__ inline void link_add(LinkMoments<C>& m, C a, int i) {
+  m.m0 += a;
+  if (cx(i)) m.m1[0] += cx(i) > 0 ? a : -a;
+  if (cy(i)) m.m1[1] += cy(i) > 0 ? a : -a;
+  if (cz(i)) m.m1[2] += cz(i) > 0 ? a : -a;
+  if (cx(i)) m.pxx += a;
+  if (cy(i)) m.pyy += a;
+  if (cz(i)) m.pzz += a;
+  if (cx(i) && cy(i)) m.pxy += cx(i) * cy(i) > 0 ? a : -a;
+  if (cx(i) && cz(i)) m.pxz += cx(i) * cz(i) > 0 ? a : -a;
+  if (cy(i) && cz(i)) m.pyz += cy(i) * cz(i) > 0 ? a : -a;
+}
+
+// Force G and torque T that one node y hands to particle q through the
+// links in m (y + c_i owned by q), eqs. (16)-(18) summed link by link: the
+// post-collision value v_i leaving y enters S(y + c_i) as -(c_i - u_q(y +
+// c_i)) v_i, and with r = r_q(y), u = u_q(y), u_q(y + c_i) = u + w x c_i,
+// r_q(y + c_i) = r + c_i the sums over the links are
+//   G += m1 - u m0 - w x m1,
+//   T  = r x G - m1 x u + (Pi - tr(Pi) 1) w
+// (c x (w x c) = |c|^2 w - c (c . w)).  G may carry the node's own terms
+// already (they act at r).
+template <typename C>
+__device__ inline void link_force(const LinkMoments<C>& m, const C* r, const C* u,
+                                  const C* w, C* G, C* T) {
+  G[0] += (m.m1[0] - u[0] * m.m0) - (w[1] * m.m1[2] - w[2] * m.m1[1]);
+  G[1] += (m.m1[1] - u[1] * m.m0) - (w[2] * m.m1[0] - w[0] * m.m1[2]);
+  G[2] += (m.m1[2] - u[2] * m.m0) - (w[0] * m.m1[1] - w[1] * m.m1[0]);
+  T[0] = (r[1] * G[2] - r[2] * G[1]) - (m.m1[1] * u[2] - m.m1[2] * u[1]) +
+         ((m.pxy * w[1] + m.pxz * w[2]) - (m.pyy + m.pzz) * w[0]);
+  T[1] = (r[2] * G[0] - r[0] * G[2]) - (m.m1[2] * u[0] - m.m1[0] * u[2]) +
+         ((m.pxy * w[0] + m.pyz * w[2]) - (m.pxx + m.pzz) * w[1]);
+  T[2] = (r[0] * G[1] - r[1] * G[0]) - (m.m1[0] * u[1] - m.m1[1] * u[0]) +
+         ((m.pxz * w[0] + m.pyz * w[1]) - (m.pxx + m.pyy) * w[2]);
+}
+
+// Kinematics of particle q seen from node (x, y, z): r = minimg(node - X),
+// u = U + w x r, w (in the compute precision C; the minimum image in FP64).
+template <typename C>
+__device__ inline void kinematics(const Particles& P, int q, int x, int y, int z,
+                                  const Geom& g, C* r, C* u, C* w) {
+  const double X0 = P.X[3 * q], X1 = P.X[3 * q + 1], X2 = P.X[3 * q + 2];
+  const double U0 = P.U[3 * q], U1 = P.U[3 * q + 1], U2 = P.U[3 * q + 2];
+  const double W0 = P.W[3 * q], W1 = P.W[3 * q + 1], W2 = P.W[3 * q + 2];
+  r[0] = (C)minimg((double)x - X0, (double)g.nx, true);
+  r[1] = (C)minimg((double)y - X1, (double)g.ny, true);
+  r[2] = (C)minimg((double)z - X2, (double)g.nz, g.periodic_z != 0);
+  w[0] = (C)W0;
+  w[1] = (C)W1;
+  w[2] = (C)W2;
+  u[0] = (C)U0 + (w[1] * r[2] - w[2] * r[1]);
+  u[1] = (C)U1 + (w[2] * r[0] - w[0] * r[2]);
+  u[2] = (C)U2 + (w[0] * r[1] - w[1] * r[0]);
+}
+
+// Commit of one round of per-lane (force G, torque T) contributions to the
+// block's LDS rows (commit_group adds -sum, so the values go in negated and
+// widened to FP64).
+template <typename C>
+__device__ inline void commit_round(int q, const C* G, const C* T, int lid,
+                                    double (*row)[6], double* ovf) {
+  double s[3], t[3];
+  for (int k = 0; k < 3; ++k) {
+    s[k] = -(double)G[k];
+    t[k] = -(double)T[k];
+  }
+  commit_group(q, s, t, lid, row, ovf);
+}
+
+// Register budget without spills: FP64 at most 128 VGPRs (four wavefronts
+// per SIMD); FP32 and binary16 at most 80 (six) for periodic scenes of
+// spheres and cubes, else 96 (five).  POLY: built
 // with the polyhedron signed distance (scenes without polyhedra run the
 // form without it, which needs fewer registers).  BAL: with the block sums
-// and device acceleration of the zero-net-flux balance force.
-template <typename S, bool POLY, bool BAL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_lattice(const S* __restrict__ src,
+// and device acceleration of the zero-net-flux balance force.  WALL: z
+// bounded by walls (half-way bounce-back).
+//
+// The pass also evaluates the momentum exchange of the NEXT step, eqs.
+// (16)-(18), with the owner map and particle state its collision used: every
+// post-collision value v_i it stores at node y enters exactly two sums of
+// eq. (16) read with post-streaming populations, the own term
+// (c_i - u_p(y)) v_i of S(y) and the incoming term -(c_i - u_q(y + c_i)) v_i
+// of S(y + c_i) (or, beyond a wall, the bounced term of S(y)).  Each lane
+// pushes these terms to the owners of y and of its 18 neighbours (read from
+// the owner map), grouped by particle through link masks, and the
+// wavefronts reduce them per particle into the block's partial-sum slots
+// (F_p = -sum S, T_p = -sum r x S, fixed order, no atomics).  The
+// storage's rest weights cancel in every S(x), so the pushed values are the
+// stored deviations h_i (FP32) or f_i - w_i (FP64).  Blocks whose candidate
+// list is empty (no particle owns a node within one node of the block), and
+// wavefronts without an owned node or a neighbour of one, skip it.  With
+// binary16 storage the kernel stores only; the momentum exchange is the
+// separate pass over the stored (rounded) values.
+template <typename S, bool POLY, bool BAL, bool WALL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    sizeof(S) == 8 ? 4 : ((POLY || WALL) ? 5 : 6), 8))) void k_lattice(const S* __restrict__ src,
                                                  S* __restrict__ dst,
                                                  const int* __restrict__ owner,
                                                  Particles P, Geom g, Phys ph,
                                                  Counters* ctr,
-                                                 double* __restrict__ bal_part) {
+                                                 double* __restrict__ bal_part,
+                                                 Tiles tl) {
   using C = typename Store<S>::C;
+  // the momentum exchange is summed here for FP64 and FP32 storage; binary16
+  // storage leaves it to the separate pass over the stored values
+  constexpr bool FUSED = sizeof(S) != 2;
+  __shared__ double red[4][LCAP_MAX][6];
+  // queue of the rare further-particle contributions, per wavefront
+  constexpr int XQ = 32;
+  __shared__ int xqid[4][XQ];
+  __shared__ double xqv[4][XQ][6];
   const BlockNode nd = block_node(g);
   const int x = nd.x, y = nd.y, z = nd.z;
   const bool valid = nd.valid;
@@ -237,24 +387,63 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const bool perz = g.periodic_z != 0;
   const Nbr nb = neighbours(g, x, y, z);
   const int self = nb.off(0, 0, 0);
+  // walls exist only on a bounded z axis (WALL): elsewhere the wall terms
+  // drop out at compile time
+  const bool wallm = WALL && nb.wall_m, wallp = WALL && nb.wall_p;
+  auto beyond = [&](int dz) { return dz < 0 ? (wallm ? 1 : 0) : (dz > 0 ? (wallp ? 2 : 0) : 0); };
+  const int lane = threadIdx.x % WAVE;
+  int cnt = tl.lcount[nd.block];
+  cnt = __builtin_amdgcn_readfirstlane(cnt < g.tile_cap ? cnt : g.tile_cap);
+  const bool mea = FUSED && cnt > 0;              // uniform over the block
+
+  // owners of the node and of its 18 neighbours (-2: beyond a wall): the
+  // link masks of the momentum exchange (same owner as the node, and the
+  // first other particle), and whether a third particle is involved
+  int o = -1, id1 = -1, id2 = -1;
+  unsigned msame = 0u, m1 = 0u, m2 = 0u;
+  bool more = false;
+  if (valid) o = owner_id(owner[self]);
+  if (mea && valid) {
+    int nbo[Q];
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+      nbo[i] = beyond(cz(i)) ? -2 : owner_id(owner[nb.off(cx(i), cy(i), cz(i))]);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      if (o >= 0 && nbo[i] == o) msame |= 1u << i;
+      if (id1 < 0 && nbo[i] >= 0 && nbo[i] != o) id1 = nbo[i];
+    }
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      if (id1 >= 0 && nbo[i] == id1) m1 |= 1u << i;
+      if (id2 < 0 && nbo[i] >= 0 && nbo[i] != o && nbo[i] != id1) id2 = nbo[i];
+    }
+    bool more3 = false;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      if (id2 >= 0 && nbo[i] == id2) m2 |= 1u << i;
+      more3 = more3 || (nbo[i] >= 0 && nbo[i] != o && nbo[i] != id1 && nbo[i] != id2);
+    }
+    // particles beyond the two entries kept in registers (A, B below): for
+    // an owned node its own and id1, so id2 already counts
+    more = o >= 0 ? (id2 >= 0 || more3) : more3;
+  }
 
   C f[Q];
-  int o = -1;
   if (valid) {
     // one load per direction from a selected index (a branch per direction
     // would make the compiler wait for memory between the loads), then the
     // moving-wall term of the links that bounced back
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const int src_i = nb.beyond(-cz(i)) ? opp(i) * n + self
+      const int src_i = beyond(-cz(i)) ? opp(i) * n + self
                                           : i * n + nb.off(-cx(i), -cy(i), -cz(i));
       f[i] = Store<S>::ldn(src, src_i);
     }
-    o = owner_id(owner[self]);
-    if (nb.wall_m || nb.wall_p) {
+    if (wallm || wallp) {
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        const int bw = nb.beyond(-cz(i));
+        const int bw = beyond(-cz(i));
         if (bw) {
           const double* uw = ph.wall_u[bw - 1];
           const double cu = cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2];
@@ -286,33 +475,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 
   // coupling: B and u_p of the owner, in FP64 for FP64 storage and in FP32
   // otherwise (the owner itself was decided in FP64)
-  C upy[3] = {(C)0, (C)0, (C)0};
+  C rp[3] = {(C)0, (C)0, (C)0}, upy[3] = {(C)0, (C)0, (C)0}, wp[3] = {(C)0, (C)0, (C)0};
   C B = (C)0;
   if (o >= 0) {
-    // the owner's record, all loads issued before any use
-    const double X0 = P.X[3 * o], X1 = P.X[3 * o + 1], X2 = P.X[3 * o + 2];
-    const double U0 = P.U[3 * o], U1 = P.U[3 * o + 1], U2 = P.U[3 * o + 2];
-    const double W0 = P.W[3 * o], W1 = P.W[3 * o + 1], W2 = P.W[3 * o + 2];
+    kinematics<C>(P, o, x, y, z, g, rp, upy, wp);
     const int shape = P.shape[o];
     const double size = P.size[o];
     double Ro[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) Ro[k] = P.R[9 * o + k];
-    const C r0 = (C)minimg((double)x - X0, (double)g.nx, true);
-    const C r1 = (C)minimg((double)y - X1, (double)g.ny, true);
-    const C r2 = (C)minimg((double)z - X2, (double)g.nz, perz);
-    C d;
     if constexpr (Store<S>::shifted) {
-      d = sdf32(shape, (float)size, Ro, r0, r1, r2, POLY ? P.poly : nullptr);
+      const C d = sdf32(shape, (float)size, Ro, rp[0], rp[1], rp[2], POLY ? P.poly : nullptr);
       B = weight32(d, (float)ph.eps);
     } else {
-      d = sdf(shape, size, Ro, r0, r1, r2, POLY ? P.poly : nullptr);
+      const C d = sdf(shape, size, Ro, rp[0], rp[1], rp[2], POLY ? P.poly : nullptr);
       B = weight(d, ph.eps);
     }
-    const C w0 = (C)W0, w1 = (C)W1, w2 = (C)W2;
-    upy[0] = (C)U0 + (w1 * r2 - w2 * r1);
-    upy[1] = (C)U1 + (w2 * r0 - w0 * r2);
-    upy[2] = (C)U2 + (w0 * r1 - w1 * r0);
   }
   // uniform fluid acceleration: fixed, or the zero-net-flux controller's
   double ax = ph.a_ext[0], ay = ph.a_ext[1], az = ph.a_ext[2];
@@ -368,6 +546,197 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     }
     block_sums4(m, j0, j1, j2, nd, bal_part);
   }
+  if (!FUSED || !mea) return;                     // uniform over the block
+
+  // ---- momentum exchange of the next step, pushed link by link ----------
+  const int* list = tl.llist + nd.block * g.tile_cap;
+  const int* ent = tl.lent + nd.block * g.tile_cap;
+  const int lid = lane < cnt ? list[lane] : -1;   // candidate list, one per lane
+  for (int c = lane; c < cnt; c += WAVE)
+    for (int k = 0; k < 6; ++k) red[nd.wave][c][k] = 0.0;
+  // Entries of the lane: A the node's own particle (own terms and links to
+  // its own nodes), B the first other particle owning a neighbour (for a
+  // fluid node: the first and second particles owning a neighbour); further
+  // particles around one node (rare) after the commit of A and B.
+  const int qa = o >= 0 ? o : id1;
+  const int qb = o >= 0 ? id1 : id2;
+  const unsigned mA = o >= 0 ? msame : m1;
+  const unsigned mB = o >= 0 ? m1 : m2;
+  const bool multi = __ballot(qb >= 0) != 0;      // uniform over the wavefront
+  if (__ballot(qa >= 0) != 0) {                   // else no lane has an entry
+  // One pass over the stored values v_i (FP64: minus the rest weight): the
+  // link moments of A (and B), and the own terms of S(y), sum_i (c_i - u) v_i
+  // over every link plus, for a link beyond a wall, the bounced value
+  // b_i = v_i - 6 w_i c_i . u_w entering as -(c_opp(i) - u) b_i =
+  // (c_i + u) b_i: the force on the owner is -(J' + W1) + u (m0' - W0),
+  // m0' = sum_{i>=1} v_i, J' = sum c_i v_i, W1 = sum c_i b_i, W0 = sum b_i.
+  // The collision conserves mass and moves the momentum to rho v, so
+  // m0' = (rho - 1) - v_0 (D - v_0 when shifted) and J' = rho v (to the
+  // rounding of the collision).
+  LinkMoments<C> La, Lb;
+  link_zero(La);
+  link_zero(Lb);
+  const C v_0 = Store<S>::shifted ? f[0] : f[0] - (C)wgt(0);
+  C m0 = (Store<S>::shifted ? D : rho - (C)1) - v_0;
+  C j[3] = {rho * v0, rho * v1, rho * v2};
+  const bool walls = wallm || wallp;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const C vi = Store<S>::shifted ? f[i] : f[i] - (C)wgt(i);
+    if (walls) {
+      const int bw = beyond(cz(i));
+      if (bw) {
+        const double* uw = ph.wall_u[bw - 1];
+        const C bi = vi - (C)(6.0 * wgt(i) * (cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2]));
+        m0 -= bi;
+        if (cx(i)) j[0] += cx(i) > 0 ? bi : -bi;
+        if (cy(i)) j[1] += cy(i) > 0 ? bi : -bi;
+        if (cz(i)) j[2] += cz(i) > 0 ? bi : -bi;
+      }
+    }
+    link_add(La, ((mA >> i) & 1u) ? vi : (C)0, i);
+    if (multi) link_add(Lb, ((mB >> i) & 1u) ? vi : (C)0, i);
+  }
+  C Ga[3] = {(C)0, (C)0, (C)0}, Ta[3] = {(C)0, (C)0, (C)0};
+  C Gb[3] = {(C)0, (C)0, (C)0}, Tb[3] = {(C)0, (C)0, (C)0};
+  if (qa >= 0) {
+    const bool own = o >= 0;
+    C rr[3], uk[3], wk[3];
+    // (the coupling's r, u_p, w of the owner are evaluated again here
+    // rather than kept live across the collision)
+    kinematics<C>(P, qa, x, y, z, g, rr, uk, wk);
+    for (int k = 0; k < 3; ++k) Ga[k] = own ? uk[k] * m0 - j[k] : (C)0;
+    link_force<C>(La, rr, uk, wk, Ga, Ta);
+  }
+  if (multi && qb >= 0) {
+    C rb[3], ub[3], wb[3];
+    kinematics<C>(P, qb, x, y, z, g, rb, ub, wb);
+    link_force<C>(Lb, rb, ub, wb, Gb, Tb);
+  }
+  // one commit for A and B: each distinct particle of the wavefront in
+  // turn, the lanes adding the entries that name it (FP64 wave sums into
+  // the block's LDS rows, which hold -sum)
+  {
+    bool pa = qa >= 0, pb = qb >= 0;
+    for (;;) {
+      const uint64_t ba = __ballot(pa), bb = __ballot(pb);
+      if ((ba | bb) == 0) break;
+      const int pick = ba ? __builtin_amdgcn_readlane(qa, __ffsll((long long)ba) - 1)
+                          : __builtin_amdgcn_readlane(qb, __ffsll((long long)bb) - 1);
+      const bool ta = pa && qa == pick, tb = pb && qb == pick;
+      double vv[6];
+      for (int k = 0; k < 3; ++k) {
+        vv[k] = -((ta ? (double)Ga[k] : 0.0) + (tb ? (double)Gb[k] : 0.0));
+        vv[3 + k] = -((ta ? (double)Ta[k] : 0.0) + (tb ? (double)Tb[k] : 0.0));
+      }
+      const double sum = wave_sum6_scatter(vv);
+      const uint64_t hit = __ballot(lid == pick);
+      if (lane < 12 && (lane & 1) == 0) {
+        const int k = lane >> 1;
+        if (hit) {
+          red[nd.wave][__ffsll((long long)hit) - 1][k] -= sum;
+        } else {
+          atomic_add_f64(&tl.ovf[6 * pick + k], -sum);
+        }
+      }
+      if (ta) pa = false;
+      if (tb) pb = false;
+    }
+  }
+  }
+  // further particles around one node (rare): in increasing id order per
+  // node, from the node's values read back from what was just stored, one
+  // link at a time (a loop the compiler keeps rolled, so that this path
+  // adds no registers to the kernel); each lane's contribution goes into a
+  // per-wavefront LDS queue in lane order, which is added to the block
+  // rows in queue order (a full queue sends the rest to the overflow sums
+  // with atomics)
+  if (__ballot(more)) {
+    const int skip1 = o >= 0 ? id1 : id2;   // the entries already committed
+    int last = -1, nq = 0;
+    while (__ballot(more)) {
+      int q = -1;
+      unsigned mask = 0u;
+      if (more) {
+#pragma nounroll
+        for (int i = 1; i < Q; ++i) {
+          int d0, d1, d2;
+          dir_of(i, d0, d1, d2);
+          // the neighbour's index from its coordinates (periodic wrap; a
+          // z beyond a wall has no node)
+          int xn = x + d0, yn = y + d1, zn = z + d2;
+          xn = xn < 0 ? xn + g.nx : (xn >= g.nx ? xn - g.nx : xn);
+          yn = yn < 0 ? yn + g.ny : (yn >= g.ny ? yn - g.ny : yn);
+          const bool bw = WALL && (zn < 0 || zn >= g.nz);
+          zn = zn < 0 ? zn + g.nz : (zn >= g.nz ? zn - g.nz : zn);
+          const int b = bw ? -2 : owner_id(owner[xn + g.nx * (yn + g.ny * zn)]);
+          const bool cand = b >= 0 && b != o && b != id1 && b != skip1 && b > last;
+          const bool lower = cand && (q < 0 || b < q);
+          mask = lower ? (1u << i) : ((cand && b == q) ? (mask | (1u << i)) : mask);
+          q = lower ? b : q;
+        }
+        more = q >= 0;
+        last = q;
+      }
+      const uint64_t bq = __ballot(q >= 0);
+      if (q >= 0) {
+        LinkMoments<C> Lq;
+        link_zero(Lq);
+#pragma nounroll
+        for (int i = 1; i < Q; ++i) {
+          if ((mask >> i) & 1u) {
+            int d0, d1, d2;
+            dir_of(i, d0, d1, d2);
+            const C sv = Store<S>::ld(dst, i * n + self);
+            const C a = Store<S>::shifted ? sv : sv - (C)(i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+            const C e0 = (C)d0, e1 = (C)d1, e2 = (C)d2;
+            Lq.m0 += a;
+            Lq.m1[0] += e0 * a;
+            Lq.m1[1] += e1 * a;
+            Lq.m1[2] += e2 * a;
+            Lq.pxx += (e0 * e0) * a;
+            Lq.pyy += (e1 * e1) * a;
+            Lq.pzz += (e2 * e2) * a;
+            Lq.pxy += (e0 * e1) * a;
+            Lq.pxz += (e0 * e2) * a;
+            Lq.pyz += (e1 * e2) * a;
+          }
+        }
+        C G[3] = {(C)0, (C)0, (C)0}, T[3] = {(C)0, (C)0, (C)0}, rq[3], uq[3], wq[3];
+        kinematics<C>(P, q, x, y, z, g, rq, uq, wq);
+        link_force<C>(Lq, rq, uq, wq, G, T);
+        const int slot = nq + __builtin_popcountll(bq & ((1ull << lane) - 1ull));
+        if (slot < XQ) {
+          xqid[nd.wave][slot] = q;
+          for (int k = 0; k < 3; ++k) {
+            xqv[nd.wave][slot][k] = (double)G[k];
+            xqv[nd.wave][slot][3 + k] = (double)T[k];
+          }
+        } else {
+          for (int k = 0; k < 3; ++k) {
+            atomic_add_f64(&tl.ovf[6 * q + k], (double)G[k]);
+            atomic_add_f64(&tl.ovf[6 * q + 3 + k], (double)T[k]);
+          }
+        }
+      }
+      nq += __builtin_popcountll(bq);
+    }
+    nq = nq < XQ ? nq : XQ;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int e = 0; e < nq; ++e) {
+      const int q = xqid[nd.wave][e];
+      const uint64_t hit = __ballot(lid == q);
+      if (lane < 6) {
+        if (hit)
+          red[nd.wave][__ffsll((long long)hit) - 1][lane] -= -xqv[nd.wave][e][lane];
+        else
+          atomic_add_f64(&tl.ovf[6 * q + lane], xqv[nd.wave][e][lane]);
+      }
+    }
+  }
+  store_block(red, list, ent, cnt, g, tl.part);
 }
 
 // Momentum exchange, eqs. (16)-(18), over the populations f* of the last
@@ -480,19 +849,15 @@ __global__ __launch_bounds__(256) void k_pop_moments(const S* __restrict__ f, Ge
   block_sums4(m, j0, j1, j2, nd, out);
 }
 
-// Zero-net-flux balance controller (balance mode 2), one workgroup: the
-// block sums are added in fixed order (thread t takes blocks t, t + 256, ..,
-// then a fixed tree), giving the lattice mass M and momentum P.
-// init: M, P_{-1} = P, b_0 = -P / M.  Update after the collision of step t
-// (which used b_t): C_t = P_t - P_{t-1} - b_t M, b_{t+1} = -(P_t + C_t) / M.
-// The acceleration in use is a = fluid_accel + b.
-__global__ __launch_bounds__(256) void k_balance(const double* __restrict__ part,
-                                                 unsigned nblocks, Counters* ctr,
-                                                 Phys ph, int init) {
-  __shared__ double sh[256][4];
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (unsigned b = threadIdx.x; b < nblocks; b += 256)
-    for (int k = 0; k < 4; ++k) acc[k] += part[4 * (size_t)b + k];
+// Zero-net-flux balance controller (balance mode 2).  The lattice blocks'
+// (mass, momentum) sums are added in two fixed-order stages: BAL_PARTS
+// workgroups each sum one contiguous range of blocks (thread t takes
+// entries t, t + 256, .. of the range, then a fixed tree), then one
+// workgroup sums the BAL_PARTS results the same way, giving the lattice mass
+// M and momentum P.  init: M, P_{-1} = P, b_0 = -P / M.  Update after the
+// collision of step t (which used b_t): C_t = P_t - P_{t-1} - b_t M,
+// b_{t+1} = -(P_t + C_t) / M.  The acceleration in use is a = fluid_accel + b.
+__device__ void tree_sum4(double (*sh)[4], double* acc) {
   for (int k = 0; k < 4; ++k) sh[threadIdx.x][k] = acc[k];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -500,6 +865,29 @@ __global__ __launch_bounds__(256) void k_balance(const double* __restrict__ part
       for (int k = 0; k < 4; ++k) sh[threadIdx.x][k] += sh[threadIdx.x + w][k];
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(256) void k_balance_part(const double* __restrict__ part,
+                                                      unsigned nblocks,
+                                                      double* __restrict__ out) {
+  __shared__ double sh[256][4];
+  const unsigned chunk = (nblocks + BAL_PARTS - 1) / BAL_PARTS;
+  const unsigned b0 = blockIdx.x * chunk;
+  const unsigned b1 = b0 + chunk < nblocks ? b0 + chunk : nblocks;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (unsigned b = b0 + threadIdx.x; b < b1; b += 256)
+    for (int k = 0; k < 4; ++k) acc[k] += part[4 * (size_t)b + k];
+  tree_sum4(sh, acc);
+  if (threadIdx.x < 4) out[4 * blockIdx.x + threadIdx.x] = sh[0][threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_balance(const double* __restrict__ parts,
+                                                 Counters* ctr, Phys ph, int init) {
+  __shared__ double sh[256][4];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (unsigned b = threadIdx.x; b < BAL_PARTS; b += 256)
+    for (int k = 0; k < 4; ++k) acc[k] += parts[4 * (size_t)b + k];
+  tree_sum4(sh, acc);
   if (threadIdx.x == 0) {
     if (init) ctr->bal_M = sh[0][0];
     const double M = ctr->bal_M;
@@ -581,11 +969,14 @@ static unsigned tile_blocks(const Geom& g) {
 
 template <typename S>
 static void run_lattice(Ctx& c, const void* src, void* dst) {
-  const bool bal = c.ph.bal_mode == 2;
-  auto k = c.has_poly ? (bal ? k_lattice<S, true, true> : k_lattice<S, true, false>)
-                      : (bal ? k_lattice<S, false, true> : k_lattice<S, false, false>);
+  const bool bal = c.ph.bal_mode == 2, wall = c.g.periodic_z == 0;
+  auto k = c.has_poly
+               ? (bal ? k_lattice<S, true, true, false>
+                      : (wall ? k_lattice<S, true, false, true> : k_lattice<S, true, false, false>))
+               : (bal ? k_lattice<S, false, true, false>
+                      : (wall ? k_lattice<S, false, false, true> : k_lattice<S, false, false, false>));
   hipLaunchKernelGGL(k, dim3(tile_blocks(c.g)), dim3(256), 0, c.stream, (const S*)src,
-                     (S*)dst, c.owner, c.part, c.g, c.ph, c.counters, c.bal_part);
+                     (S*)dst, c.owner, c.part, c.g, c.ph, c.counters, c.bal_part, c.tl);
 }
 
 hipError_t launch_lattice(Ctx& c, const void* src, void* dst) {
@@ -612,8 +1003,12 @@ static void run_pop_moments(Ctx& c, const void* f) {
 
 hipError_t launch_balance(Ctx& c, const void* f, int init) {
   if (init) DISPATCH(c, run_pop_moments, (c, f));
-  hipLaunchKernelGGL(k_balance, dim3(1), dim3(256), 0, c.stream, c.bal_part,
-                     tile_blocks(c.g), c.counters, c.ph, init);
+  const unsigned nb = tile_blocks(c.g);
+  double* parts = c.bal_part + 4 * (size_t)nb;
+  hipLaunchKernelGGL(k_balance_part, dim3(BAL_PARTS), dim3(256), 0, c.stream, c.bal_part,
+                     nb, parts);
+  hipLaunchKernelGGL(k_balance, dim3(1), dim3(256), 0, c.stream, parts, c.counters, c.ph,
+                     init);
   return hipGetLastError();
 }
 

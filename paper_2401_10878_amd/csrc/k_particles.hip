@@ -211,22 +211,15 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
   const double size = P.size[ip];
   const int n3[3] = {g.nx, g.ny, g.nz};
   double ext[3];
+  // lattice blocks list the particles owning a node within one node of the
+  // block (the lattice pass pushes momentum-exchange terms to the owners of
+  // each node's neighbours): half extent + eps/2 + 1 node
+  const double margin_l = fmax(margin, 0.5 * ph.eps + 1.25);
+  double extl[3];
   for (int k = 0; k < 3; ++k) {
-    ext[k] = size;
-    if (shape == 1)
-      ext[k] = 0.5 * size * (fabs(R[3 * k]) + fabs(R[3 * k + 1]) + fabs(R[3 * k + 2])) ;
-    if (shape >= POLY0) {
-      // largest |world coordinate| of a vertex along axis k
-      CPoly* pd = (CPoly*)P.poly + (shape - POLY0);
-      double e = 0.0;
-      for (int i = 0; i < pd->nv; ++i) {
-        const double c = fabs((R[3 * k] * pd->v[i][0] + R[3 * k + 1] * pd->v[i][1]) +
-                              R[3 * k + 2] * pd->v[i][2]);
-        e = c > e ? c : e;
-      }
-      ext[k] = size * e;
-    }
-    ext[k] += margin;
+    const double e = half_extent(shape, size, R, k, P.poly);
+    ext[k] = e + margin;
+    extl[k] = e + margin_l;
   }
   // detection tiles
   {
@@ -275,7 +268,7 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
     const int nt3[3] = {g.ltx, g.lty, g.ltz};
     const int ts3[3] = {LX, LY, LZ};
     TileSpan sp[3];
-    for (int k = 0; k < 3; ++k) sp[k] = axis_tiles(X[k], ext[k], n3[k], nt3[k], ts3[k], per[k]);
+    for (int k = 0; k < 3; ++k) sp[k] = axis_tiles(X[k], extl[k], n3[k], nt3[k], ts3[k], per[k]);
     const int cxn = sp[0].count(), cyn = sp[1].count(), czn = sp[2].count();
     int total = cxn * cyn * czn;
     if (total > g.maxent) {

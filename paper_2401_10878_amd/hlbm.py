@@ -15,9 +15,7 @@ import re
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# HLBM_LIBRARY may point at another build of the same library (for A/B
-# timing of kernel variants); the default is the in-tree build.
-LIBPATH = os.environ.get("HLBM_LIBRARY") or os.path.join(HERE, "libhlbm.so")
+LIBPATH = os.path.join(HERE, "libhlbm.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "hlbm.h")
 
 Q = 19
@@ -78,6 +76,13 @@ def load():
         raise RuntimeError(
             f"{LIBPATH} is missing: build it with python -m paper_2401_10878_amd.build")
     L = C.CDLL(LIBPATH)
+    from . import build as _build
+    L.hlbm_build_hash.restype = C.c_char_p
+    built, here = L.hlbm_build_hash().decode(), _build.source_hash()
+    if built != here:
+        raise RuntimeError(
+            f"{LIBPATH} was built from other sources (hash {built}, sources {here}): "
+            "rebuild it with python -m paper_2401_10878_amd.build")
     P, d, i, v = C.POINTER, C.c_double, C.c_int, C.c_void_p
     L.hlbm_create.argtypes = [P(Params), v, P(v)]
     L.hlbm_bind_populations.argtypes = [v, v, v, C.c_size_t]
@@ -96,7 +101,7 @@ def load():
     L.hlbm_read_fields.argtypes = [v, P(d), P(d), P(i)]
     L.hlbm_read_populations.argtypes = [v, P(d)]
     L.hlbm_read_coupling.argtypes = [v, P(d), P(d)]
-    L.hlbm_counters.argtypes = [v] + [P(C.c_longlong)] * 4
+    L.hlbm_counters.argtypes = [v] + [P(C.c_longlong)] * 5
     L.hlbm_stream.argtypes = [v]
     L.hlbm_stream.restype = v
     L.hlbm_fluid_acceleration.argtypes = [v, P(d)]
@@ -104,12 +109,14 @@ def load():
     L.hlbm_set_state.argtypes = [v, v, C.c_size_t]
     L.hlbm_adjoint_record.argtypes = [v, i, i]
     L.hlbm_adjoint_gradient.argtypes = [v] + [P(d)] * 7
+    L.hlbm_adjoint.argtypes = [v, i, i, P(d), P(d), P(d)]
     L.hlbm_last_error.argtypes = [v]
     L.hlbm_last_error.restype = C.c_char_p
     L.hlbm_destroy.argtypes = [v]
     for name in header_functions():
         f = getattr(L, name)
-        if name not in ("hlbm_stream", "hlbm_last_error", "hlbm_destroy"):
+        if name not in ("hlbm_stream", "hlbm_last_error", "hlbm_destroy",
+                        "hlbm_build_hash"):
             f.restype = C.c_int
     L.hlbm_destroy.restype = None
     _lib = L
@@ -302,10 +309,10 @@ class Simulation:
         return f
 
     def counters(self):
-        v = [C.c_longlong() for _ in range(4)]
+        v = [C.c_longlong() for _ in range(5)]
         self._check(self.L.hlbm_counters(self.h, *[C.byref(x) for x in v]))
         return dict(pairs=v[0].value, cells=v[1].value, total_cells=v[2].value,
-                    steps=v[3].value)
+                    steps=v[3].value, samples=v[4].value)
 
     def fluid_acceleration(self):
         a = np.zeros(3)
@@ -341,38 +348,68 @@ class Simulation:
             _dp(out["X0"]), _dp(out["U0"]), _dp(out["omega0"])))
         return {k: v[:self.np] for k, v in out.items()}
 
+    def adjoint(self, ksteps, ckpt_every, dJ_dU):
+        """Record ksteps steps and return (dJ/ds, dJ/dq0) of
+        J = sum_p dJ_dU[p] . U_p at the end of the window, in one call."""
+        n = max(self.np, 1)
+        seed = np.zeros((n, 3))
+        seed[:self.np] = np.asarray(dJ_dU, np.float64).reshape(self.np, 3)
+        ds, dq = np.zeros(n), np.zeros((n, 4))
+        self._check(self.L.hlbm_adjoint(self.h, int(ksteps), int(ckpt_every),
+                                        _dp(seed), _dp(ds), _dp(dq)))
+        return ds[:self.np], dq[:self.np]
+
 
 def _settling_function():
     import torch
+    from torch.autograd.function import once_differentiable
 
     class MeanSettlingVelocity(torch.autograd.Function):
         """J = mean over particles of the vertical velocity U_z after ksteps
         coupled steps from fluid at rest, as a function of the particles'
         density ratios (n) and initial quaternions (n x 4).  The backward pass
         is the library's adjoint (owners and contact forces of the forward run
-        held fixed); the quaternion gradient is tangent to |q| = 1."""
+        held fixed).  The library runs on the unit quaternions q / |q|; the
+        gradient by q is that of J(q / |q|), i.e. the library's gradient
+        tangent to the unit sphere divided by |q|.  J and the gradients come
+        back on the device and in the dtype of the inputs; the backward pass
+        can run once (it releases the recorded window)."""
 
         @staticmethod
         def forward(ctx, density, q0, params, scene, ksteps, ckpt_every):
             sc = scene.copy()
             sc.density = density.detach().cpu().double().numpy().copy()
-            sc.q = q0.detach().cpu().double().numpy().copy()
+            qraw = q0.detach().cpu().double().numpy().copy()
+            sc.q = qraw
             sim = Simulation(params.replace(precision=0), sc)
             sim.init_equilibrium()
             sim.adjoint_record(int(ksteps), int(ckpt_every))
             U = sim.particles()["U"]
             ctx.sim = sim
             ctx.n = sc.n
-            return torch.tensor(U[:, 2].mean(), dtype=torch.float64)
+            ctx.qnorm = np.sqrt((qraw * qraw).sum(axis=1))
+            ctx.like = ((density.device, density.dtype), (q0.device, q0.dtype))
+            return torch.tensor(U[:, 2].mean(), dtype=density.dtype,
+                                device=density.device)
 
         @staticmethod
+        @once_differentiable
         def backward(ctx, grad):
+            if ctx.sim is None:
+                raise RuntimeError("MeanSettlingVelocity: the recorded window was "
+                                   "released by an earlier backward pass")
             g = float(grad)
             seed = np.zeros((ctx.n, 3))
             seed[:, 2] = g / ctx.n
-            r = ctx.sim.adjoint_gradient(seed)
-            ctx.sim.close()
-            return (torch.from_numpy(r["s"]), torch.from_numpy(r["q0"]),
+            try:
+                r = ctx.sim.adjoint_gradient(seed)
+            finally:
+                ctx.sim.close()
+                ctx.sim = None
+            (dd, dt), (qd, qt) = ctx.like
+            gq = r["q0"] / ctx.qnorm[:, None]
+            return (torch.from_numpy(r["s"]).to(device=dd, dtype=dt),
+                    torch.from_numpy(gq).to(device=qd, dtype=qt),
                     None, None, None, None)
 
     return MeanSettlingVelocity

@@ -516,7 +516,8 @@ def _dense_centres(seed: int, L: int, n: int, d: float,
 
 def c3_dense_cubes(seed: int = 3, L: int = 256, phi: float = 0.30,
                    edge: float = 14.0) -> Workload:
-    """256^3 periodic, 1834 cubes a=14 (phi 0.30), s 1.5, Ar 1000.
+    """256^3 periodic, 1834 cubes a=14 (phi 0.30), s 1.5, Ar 1000; zero net
+    volume flow held by the balance controller (balance mode 2, Sec. 5.1).
 
     Centres are the sphere centres of the matching sphere workload (the paper
     keeps the initial positions for spheres and cubes); orientations are
@@ -531,7 +532,7 @@ def c3_dense_cubes(seed: int = 3, L: int = 256, phi: float = 0.30,
     q = cube_orientations(rng, X, edge, (L, L, L), (True, True, True))
     sc = Scene(np.full(n, CUBE, np.int32), np.full(n, edge), np.full(n, s), X,
                q, np.zeros((n, 3)), np.zeros((n, 3)))
-    p = _base_params((L, L, L), 1, tau, lu, 1).replace(
+    p = _base_params((L, L, L), 1, tau, lu, 2).replace(
         max_pairs=max(1024, 8 * n), tile_capacity=48, precision=1)
     return Workload("C3", p, sc, 1000,
                     f"{L}^3 periodic, {n} cubes a={edge:g}, phi~{phi}, s=1.5, Ar=1000")
@@ -553,7 +554,7 @@ def c3_dense_boxes(seed: int = 3, L: int = 256, phi: float = 0.30,
     q = box_orientations(rng, X, 0.5 * dims3, (L, L, L), (True, True, True))
     sc = Scene(np.full(n, POLY0, np.int32), np.ones(n), np.full(n, s), X,
                q, np.zeros((n, 3)), np.zeros((n, 3)))
-    p = _base_params((L, L, L), 1, tau, lu, 1).replace(
+    p = _base_params((L, L, L), 1, tau, lu, 2).replace(
         max_pairs=max(1024, 8 * n), tile_capacity=48, precision=1)
     return Workload("C3B", p, sc, 1000,
                     f"{L}^3 periodic, {n} boxes {dims3[0]:.2f} x {dims3[1]:.2f} x "
@@ -563,7 +564,8 @@ def c3_dense_boxes(seed: int = 3, L: int = 256, phi: float = 0.30,
 
 def c4_dense_spheres(seed: int = 3, L: int = 256, phi: float = 0.30,
                      edge: float = 14.0) -> Workload:
-    """256^3 periodic, 1834 spheres of the cubes' volume-equivalent diameter."""
+    """256^3 periodic, 1834 spheres of the cubes' volume-equivalent diameter;
+    zero net volume flow (balance mode 2, Sec. 5.1)."""
     s, ar, tau = 1.5, 2000.0, 0.55
     dsph = cube_equiv_diameter(edge)
     lu = lattice_units(dsph, s, ar, tau)
@@ -572,7 +574,7 @@ def c4_dense_spheres(seed: int = 3, L: int = 256, phi: float = 0.30,
     q = np.tile(np.array([1.0, 0.0, 0.0, 0.0]), (n, 1))
     sc = Scene(np.full(n, SPHERE, np.int32), np.full(n, 0.5 * dsph),
                np.full(n, s), X, q, np.zeros((n, 3)), np.zeros((n, 3)))
-    p = _base_params((L, L, L), 1, tau, lu, 1).replace(
+    p = _base_params((L, L, L), 1, tau, lu, 2).replace(
         max_pairs=max(1024, 8 * n), tile_capacity=48, precision=2)
     return Workload("C4", p, sc, 1000,
                     f"{L}^3 periodic, {n} spheres D={dsph:.2f}, phi~{phi}, s=1.5, Ar=2000")

@@ -5,6 +5,18 @@ boxes, inside-sample counts) must match bit for bit when both start from the
 same state; floating-point outputs within 1e-12 (FP64 path), 1e-5 (FP32)
 and 1e-3 (FP16 storage), relative to the largest magnitude of the oracle's
 field or, for forces, to max(|F_oracle|, a reference force).
+
+Forces (and the particle state they drive) after several steps of the
+reduced-precision paths are held to FTOL and STOL, ten times TOL.  The
+hydrodynamic force is a sum of about 10^3 link terms (c_i - u)(f*_i - f_i)
+per particle of these scenes, each carrying the rounding of the stored
+values; the FP32 path stores deviations h = f - w of about 1e-2, whose
+rounding (about 1e-9 after a few steps, the population error measured here
+being 5e-9 of max |f| = 1/3) adds up as a random walk to about
+30 x 2 x 1.7e-9 = 1e-7, or 6e-5 of the reference force 1.7e-3.  Binary16
+storage rounds the same deviations with 2^-11 instead of 2^-24 of relative
+precision.  Measured worst cases after 18 steps: FP32 1.9e-5, binary16
+2.9e-3.  FP64 keeps 1e-11 for forces and 1e-12 for the state.
 """
 import math
 import sys
@@ -15,6 +27,8 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 TOL = {0: 1e-12, 1: 1e-5, 2: 1e-3}
+FTOL = {0: 1e-11, 1: 1e-4, 2: 1e-2}       # forces after several steps
+STOL = {0: 1e-12, 1: 1e-4, 2: 1e-2}       # particle state after several steps
 
 
 def _say(*a):
@@ -127,12 +141,12 @@ def test_steps_parity(O, W, H, case, prec):
         pe = rel_field(g.populations(), o.populations())
         _say(f"  step {o.step_count}: pop {pe:.2e} force {ferr:.2e}")
         assert pe <= tol
-        assert ferr <= max(tol, 1e-11) * (10 if prec else 1)
+        assert ferr <= FTOL[prec]
         po, pg = o.particles(), g.particles()
         for key in ("X", "U", "q", "omega"):
             a, b = pg[key], po[key]
             s = max(np.abs(b).max(), 1e-3 if key == "U" else 1e-6)
-            assert np.abs(a - b).max() <= max(tol, 1e-12) * s * (10 if prec else 1), key
+            assert np.abs(a - b).max() <= STOL[prec] * s, key
 
 
 def test_two_sphere_workload_parity(O, W, H):
@@ -426,7 +440,7 @@ def test_octahedra_parity(O, W, H, prec):
         eo, eg = o.forces(), g.forces()
         err = max(force_err(eg["Fh"], eo["Fh"], Fref), force_err(eg["Fc"], eo["Fc"], Fref))
         _say(f"  octahedra precision {prec} step {o.step_count}: force {err:.2e}")
-        assert err <= max(tol, 1e-11) * (10 if prec else 1)
+        assert err <= FTOL[prec]
         if prec == 0:
             assert np.array_equal(g.fields()["owner"], o.fields()["owner"])
             assert [(c["a"], c["b"], c["count"]) for c in o.contacts()] == \

@@ -75,9 +75,9 @@ def test_polyhedra_parity(O, W, H, prec, eps):
         ew = _rel(pg["omega"], po["omega"], 1e-6)
         eX = np.abs(pg["X"] - po["X"]).max()
         _say(f"  step {k + 1}: force {eF:.2e} torque {eT:.2e} omega {ew:.2e} X {eX:.2e}")
-        assert eF <= max(tol, 1e-11) * (10 if prec else 1)
-        assert eT <= max(tol, 1e-11) * (10 if prec else 1)
-        assert ew <= max(tol, 1e-11) * (10 if prec else 1)
+        assert eF <= max(tol, 1e-11)
+        assert eT <= max(tol, 1e-11)
+        assert ew <= max(tol, 1e-11)
         if prec == 0:
             assert np.array_equal(g.fields()["owner"], o.fields()["owner"])
             assert [(c["a"], c["b"], c["count"]) for c in o.contacts()] == \
