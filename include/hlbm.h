@@ -263,6 +263,15 @@ hlbm_status hlbm_read_populations(hlbm_ctx *ctx, double *f);
    node.  FP64, host arrays of N and 3N values; NULL skips. */
 hlbm_status hlbm_read_coupling(hlbm_ctx *ctx, double *B, double *up);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+   loops, harnesses that forbid allocation): hlbm_read_coupling with the
+   same arguments and results, staged through a fixed device array that the
+   library holds per GPU (64 MiB, for lattices of at most 2^21 nodes; a
+   larger lattice returns HLBM_E_ARG).  It allocates no device or host
+   memory.  All contexts on one GPU share that array: calls that overlap on
+   one GPU race. */
+hlbm_status hlbm_read_coupling_noalloc(hlbm_ctx *ctx, double *B, double *up);
+
 /* Rough contact detection (Sec. 3.3.1) and treatment counts: pairs with a
    flagged node in the latest detection and the sum of their flagged-node
    counts; that sum accumulated over all detections so far; steps taken;

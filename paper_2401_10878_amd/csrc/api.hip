@@ -20,12 +20,10 @@ struct hlbm_ctx {
 namespace {
 
 hlbm_status fail(Ctx& c, hlbm_status st, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
+  vsnprintf(c.err, sizeof c.err, fmt, ap);
   va_end(ap);
-  c.err = buf;
   return st;
 }
 
@@ -428,6 +426,16 @@ hlbm_status hlbm_create(const hlbm_params* params, void* stream, hlbm_ctx** out)
       return HLBM_E_DEVICE;
     }
     c.own_stream = true;
+  }
+  {
+    // the fixed staging array of hlbm_read_coupling_noalloc on this device
+    const hipError_t e = noalloc_scratch(&c.fixed_scratch);
+    if (e != hipSuccess) {
+      fprintf(stderr, "hlbm_create: staging array address: %s\n", hipGetErrorString(e));
+      if (c.own_stream) hipStreamDestroy(c.stream);
+      delete h;
+      return HLBM_E_DEVICE;
+    }
   }
   if (hipStreamCreate(&c.side) != hipSuccess ||
       hipEventCreateWithFlags(&c.ev_det, hipEventDisableTiming) != hipSuccess ||
@@ -1087,17 +1095,43 @@ hlbm_status hlbm_read_coupling(hlbm_ctx* h, double* B, double* up) {
   const size_t n = (size_t)c.g.ncell;
   std::vector<double> tmp(up ? n : 0);
   if (B) {
-    HIPCHECK(launch_coupling_field(c, -1, c.scratch));
+    HIPCHECK(launch_coupling_field(c, -1, c.scratch, 1));
     HIPCHECK(hipMemcpyAsync(B, c.scratch, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
   }
   if (up) {
     for (int k = 0; k < 3; ++k) {
-      HIPCHECK(launch_coupling_field(c, k, c.scratch));
+      HIPCHECK(launch_coupling_field(c, k, c.scratch, 1));
       HIPCHECK(hipMemcpyAsync(tmp.data(), c.scratch, sizeof(double) * n,
                               hipMemcpyDeviceToHost, c.stream));
       HIPCHECK(hipStreamSynchronize(c.stream));
       for (size_t i = 0; i < n; ++i) up[3 * i + k] = tmp[i];
     }
+  }
+  HIPCHECK(hipStreamSynchronize(c.stream));
+  return check_flags(c);
+}
+
+// The same read-out staged through the fixed device array: no allocation
+// on the device or the host (u_p is written interleaved by the kernel, so
+// both copies land in the caller's arrays as they are).
+hlbm_status hlbm_read_coupling_noalloc(hlbm_ctx* h, double* B, double* up) {
+  if (!h) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (!c.fluid_ready) return fail(c, HLBM_E_STATE, "not initialised");
+  const long long n = c.g.ncell;
+  if (n > NOALLOC_MAX_CELLS)
+    return fail(c, HLBM_E_ARG, "hlbm_read_coupling_noalloc: %lld nodes exceed the %lld of "
+                "its fixed staging array", n, NOALLOC_MAX_CELLS);
+  if (!c.fixed_scratch) return fail(c, HLBM_E_STATE, "no staging array address");
+  double* sB = c.fixed_scratch;
+  double* sU = c.fixed_scratch + n;
+  if (B) {
+    HIPCHECK(launch_coupling_field(c, -1, sB, 1));
+    HIPCHECK(hipMemcpyAsync(B, sB, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
+  }
+  if (up) {
+    for (int k = 0; k < 3; ++k) HIPCHECK(launch_coupling_field(c, k, sU + k, 3));
+    HIPCHECK(hipMemcpyAsync(up, sU, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c.stream));
   }
   HIPCHECK(hipStreamSynchronize(c.stream));
   return check_flags(c);
@@ -1422,7 +1456,7 @@ hlbm_status hlbm_adjoint(hlbm_ctx* h, int ksteps, int ckpt_every, const double* 
 const char* hlbm_build_hash(void) { return HLBM_SOURCE_HASH; }
 
 const char* hlbm_last_error(const hlbm_ctx* h) {
-  return h ? h->c.err.c_str() : "null context";
+  return h ? h->c.err : "null context";
 }
 
 void hlbm_destroy(hlbm_ctx* h) {

@@ -195,6 +195,7 @@ struct Ctx {
   int tcur;               // tab[tcur] = current contact list
   Counters* counters;     // device
   double* scratch;        // [ncell] FP64 staging for host conversions
+  double* fixed_scratch;  // device address of the fixed staging array
   double* bal_part = nullptr;  // per-block (mass, momentum) sums, balance mode 2
   // state
   bool particles_ready, fluid_ready;
@@ -216,7 +217,7 @@ struct Ctx {
   bool graph_n_ready[4] = {false, false, false, false};
   int n_sub;
   int ev_per_step;        // timing events per step: 2 + 5 n_sub
-  std::string err;
+  char err[512] = {};     // last error message (fixed: error paths allocate nothing)
 };
 
 // ---- launch wrappers (kernels live in the .hip files) --------------------
@@ -244,7 +245,10 @@ hipError_t launch_load_direction(Ctx& c, const void* f, int i, double* dst);
 // comp = -1: density, 0..2: velocity component of f* (FP64, into out[ncell])
 hipError_t launch_moment(Ctx& c, const void* f, int comp, double* out);
 // coupling field: comp = -1 weight B, 0..2 particle velocity component
-hipError_t launch_coupling_field(Ctx& c, int comp, double* out);
+hipError_t launch_coupling_field(Ctx& c, int comp, double* out, int stride);
+// nodes the fixed staging array of hlbm_read_coupling_noalloc holds
+constexpr long long NOALLOC_MAX_CELLS = 1LL << 21;
+hipError_t noalloc_scratch(double** out);
 // adjoint (k_adjoint.hip)
 int adjoint_record_doubles();
 int adjoint_slots();

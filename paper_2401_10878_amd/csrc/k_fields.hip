@@ -1,15 +1,30 @@
-// Read-out of the coupling field (Sec. 3.2) for tests and diagnostics.
+// Read-out of the coupling field (Sec. 3.2) for tests and diagnostics, and
+// the fixed device staging array of the read-out that allocates nothing.
+#include <mutex>
+
 #include "context.h"
 
 namespace hlbm {
 
 namespace {
 
+// Staging of hlbm_read_coupling_noalloc: B for every node, then u_p
+// interleaved per node (4 doubles per node, NOALLOC_MAX_CELLS nodes at most,
+// 64 MiB).  Each device holds its own copy for the life of the process; in
+// host code the name only stands for the symbol, and kernels get the
+// device address that hipGetSymbolAddress returned for the current device.
+static __device__ __align__(256) double scratch[4 * (size_t)NOALLOC_MAX_CELLS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
 // Coupling field at the current particle state (Sec. 3.2), FP64: comp = -1
 // writes B(d_owner), 0..2 the component of u_p = U + w x r of the owner
-// (0 where no particle owns the node).
+// (0 where no particle owns the node), at out[stride * node].
 __global__ void k_coupling_field(const int* __restrict__ owner, Particles P,
-                                 Geom g, Phys ph, int comp, double* __restrict__ out) {
+                                 Geom g, Phys ph, int comp, double* __restrict__ out,
+                                 int stride) {
   const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
   if (id >= g.ncell) return;
   const int o = owner_id(owner[id]);
@@ -29,15 +44,34 @@ __global__ void k_coupling_field(const int* __restrict__ owner, Particles P,
       v = P.U[3 * o + comp] + wr[comp == 0 ? 0 : (comp == 1 ? 1 : 2)];
     }
   }
-  out[id] = v;
+  out[stride * id] = v;
 }
 
 }  // namespace
 
-hipError_t launch_coupling_field(Ctx& c, int comp, double* out) {
+hipError_t launch_coupling_field(Ctx& c, int comp, double* out, int stride) {
   hipLaunchKernelGGL(k_coupling_field, dim3((unsigned)((c.g.ncell + 255) / 256)), dim3(256), 0,
-                     c.stream, c.owner, c.part, c.g, c.ph, comp, out);
+                     c.stream, c.owner, c.part, c.g, c.ph, comp, out, stride);
   return hipGetLastError();
+}
+
+// Device address of the staging array on the current device, looked up once
+// per device (first context created there) and kept.
+hipError_t noalloc_scratch(double** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    double* ptr = nullptr;
+    e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace hlbm

@@ -101,6 +101,7 @@ def load():
     L.hlbm_read_fields.argtypes = [v, P(d), P(d), P(i)]
     L.hlbm_read_populations.argtypes = [v, P(d)]
     L.hlbm_read_coupling.argtypes = [v, P(d), P(d)]
+    L.hlbm_read_coupling_noalloc.argtypes = [v, P(d), P(d)]
     L.hlbm_counters.argtypes = [v] + [P(C.c_longlong)] * 5
     L.hlbm_stream.argtypes = [v]
     L.hlbm_stream.restype = v
@@ -301,6 +302,14 @@ class Simulation:
         s = self.shape3()
         B, up = np.zeros(s), np.zeros(s + (3,))
         self._check(self.L.hlbm_read_coupling(self.h, _dp(B), _dp(up)))
+        return dict(B=B, up=up)
+
+    def coupling_noalloc(self):
+        """The same read-out through the library's fixed device array
+        (lattices of at most 2^21 nodes)."""
+        s = self.shape3()
+        B, up = np.zeros(s), np.zeros(s + (3,))
+        self._check(self.L.hlbm_read_coupling_noalloc(self.h, _dp(B), _dp(up)))
         return dict(B=B, up=up)
 
     def populations(self):
