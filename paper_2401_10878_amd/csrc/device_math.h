@@ -509,9 +509,12 @@ __device__ inline float sdf32(int shape, float size, const double* R, float r0,
 }
 
 // As sdf32, with the rotation already in FP32 and the hardware square root
-// (within 1 ulp; used for screening against an error bound).
+// (within 1 ulp; used for screening against an error bound).  Products and
+// sums may fuse here: a fused multiply-add rounds once, which keeps the
+// error within the same bound.
 __device__ inline float sdf32_r(int shape, float size, const float* R, float r0,
                                 float r1, float r2, const PolyDev* poly, float far) {
+#pragma clang fp contract(fast)
   if (shape == 0) return __builtin_amdgcn_sqrtf(r0 * r0 + r1 * r1 + r2 * r2) - size;
   if (poly && shape >= POLY0) {
     // beyond far cells outside the plane lower bound is returned
@@ -698,6 +701,37 @@ __device__ inline double wave_sum6_scatter(const double* v) {
   m0 += dpp_d<0x141>(t0);
   m1 += dpp_d<0x141>(t1);
   // keep local 0 (b1 = 0) or 1 (b1 = 1)
+  const double t = b1 ? m0 : m1;
+  double n = b1 ? m1 : m0;
+  n += dpp_d<0x1b>(t);
+  n += dpp_d<0xb1>(n);
+  n += xor16_d(n);
+  n += xor32_d(n);
+  return n;
+}
+
+// As wave_sum6_scatter for FP32 inputs: the first level (pairs of lanes)
+// adds in FP32, one rounding of a two-lane sum, and the rest in FP64.
+template <int CTRL>
+__device__ inline float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ inline double wave_sum6_scatter_f(const float* v) {
+  const int i = threadIdx.x & 15;
+  const bool b3 = (i & 8) != 0, b2 = (i & 4) != 0, b1 = (i & 2) != 0;
+  const float s0 = b3 ? v[0] : v[4], s1 = b3 ? v[1] : v[5];
+  const float s2 = b3 ? v[2] : 0.0f, s3 = b3 ? v[3] : 0.0f;
+  float k0 = b3 ? v[4] : v[0], k1 = b3 ? v[5] : v[1];
+  float k2 = b3 ? 0.0f : v[2], k3 = b3 ? 0.0f : v[3];
+  k0 += dpp_f<0x140>(s0);
+  k1 += dpp_f<0x140>(s1);
+  k2 += dpp_f<0x140>(s2);
+  k3 += dpp_f<0x140>(s3);
+  const double K0 = k0, K1 = k1, K2 = k2, K3 = k3;
+  const double t0 = b2 ? K0 : K2, t1 = b2 ? K1 : K3;
+  double m0 = b2 ? K2 : K0, m1 = b2 ? K3 : K1;
+  m0 += dpp_d<0x141>(t0);
+  m1 += dpp_d<0x141>(t1);
   const double t = b1 ? m0 : m1;
   double n = b1 ? m1 : m0;
   n += dpp_d<0x1b>(t);

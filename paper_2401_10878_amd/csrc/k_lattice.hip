@@ -28,6 +28,12 @@
 
 #include "context.h"
 
+// Multiply-adds in this file may round once (fused): no integer decision is
+// taken here from a floating-point value (the owner map and the contact
+// decisions come from the other passes), and the vector units run one
+// instruction instead of two.
+#pragma clang fp contract(fast)
+
 namespace hlbm {
 
 namespace {
@@ -83,6 +89,28 @@ struct Store<__half> {
   // the value st writes, read back (round to nearest even)
   __device__ static C as_stored(C v) { return __half2float(__float2half_rn(v)); }
 };
+// Non-temporal load / store of the value at byte offset b from the start
+// of a direction's array (a uniform base and a 32-bit offset: one address
+// operation per access).
+template <typename S>
+__device__ inline typename Store<S>::C ld_at(const S* base, unsigned b) {
+  if constexpr (sizeof(S) == 2)
+    return __half2float(__ushort_as_half(
+        __builtin_nontemporal_load((const unsigned short*)((const char*)base + b))));
+  else
+    return __builtin_nontemporal_load((const S*)((const char*)base + b));
+}
+template <typename S>
+__device__ inline void st_at(S* base, unsigned b, typename Store<S>::C v) {
+  if constexpr (sizeof(S) == 2)
+    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v)),
+                                (unsigned short*)((char*)base + b));
+  else
+    __builtin_nontemporal_store((S)v, (S*)((char*)base + b));
+}
+__device__ inline int owner_at(const int* owner, unsigned b) {
+  return owner_id(*(const int*)((const char*)owner + b));
+}
 template <typename S>
 __device__ inline double full_f(typename Store<S>::C h, int i) {
   return Store<S>::shifted ? wgt(i) + (double)h : (double)h;
@@ -166,6 +194,24 @@ __device__ void store_block(double (*red)[LCAP_MAX][6], const int* list,
     const int c = t / 6, k = t % 6;
     const double v = ((red[0][c][k] + red[1][c][k]) + red[2][c][k]) + red[3][c][k];
     part[((size_t)list[c] * g.maxent + ent[c]) * 6 + k] = v;
+  }
+}
+
+// Block sums of four per-lane FP64 values through one reduce-scatter per
+// wavefront (the sums land in lanes 0, 2, 4, 6), then the four wavefronts'
+// rows added in fixed order and stored at out[4 * block ..].  Every thread
+// of the block must call it.
+__device__ void block_sums4s(double a, double b, double c, double d,
+                             const BlockNode& nd, double* out) {
+  __shared__ double rows[4][4];
+  const double v[6] = {a, b, c, d, 0.0, 0.0};
+  const double sum = wave_sum6_scatter(v);
+  const int lane = threadIdx.x % WAVE;
+  if (lane < 8 && (lane & 1) == 0) rows[nd.wave][lane >> 1] = sum;
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int k = threadIdx.x;
+    out[4 * nd.block + k] = ((rows[0][k] + rows[1][k]) + rows[2][k]) + rows[3][k];
   }
 }
 
@@ -339,8 +385,8 @@ __device__ inline void commit_round(int q, const C* G, const C* T, int lid,
 }
 
 // Register budget without spills: FP64 at most 128 VGPRs (four wavefronts
-// per SIMD); FP32 and binary16 at most 80 (six) for periodic scenes of
-// spheres and cubes, else 96 (five).  POLY: built
+// per SIMD), FP32 at most 96 (five); binary16, which stores only, at most
+// 80 (six) for periodic scenes of spheres and cubes, else 96.  POLY: built
 // with the polyhedron signed distance (scenes without polyhedra run the
 // form without it, which needs fewer registers).  BAL: with the block sums
 // and device acceleration of the zero-net-flux balance force.  WALL: z
@@ -364,7 +410,7 @@ __device__ inline void commit_round(int q, const C* G, const C* T, int lid,
 // separate pass over the stored (rounded) values.
 template <typename S, bool POLY, bool BAL, bool WALL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
-    sizeof(S) == 8 ? 4 : ((POLY || WALL) ? 5 : 6), 8))) void k_lattice(const S* __restrict__ src,
+    sizeof(S) == 8 ? 4 : (sizeof(S) == 4 || POLY || WALL ? 5 : 6), 8))) void k_lattice(const S* __restrict__ src,
                                                  S* __restrict__ dst,
                                                  const int* __restrict__ owner,
                                                  Particles P, Geom g, Phys ph,
@@ -396,38 +442,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   cnt = __builtin_amdgcn_readfirstlane(cnt < g.tile_cap ? cnt : g.tile_cap);
   const bool mea = FUSED && cnt > 0;              // uniform over the block
 
-  // owners of the node and of its 18 neighbours (-2: beyond a wall): the
-  // link masks of the momentum exchange (same owner as the node, and the
-  // first other particle), and whether a third particle is involved
-  int o = -1, id1 = -1, id2 = -1;
-  unsigned msame = 0u, m1 = 0u, m2 = 0u;
-  bool more = false;
-  if (valid) o = owner_id(owner[self]);
-  if (mea && valid) {
-    int nbo[Q];
-#pragma unroll
-    for (int i = 1; i < Q; ++i)
-      nbo[i] = beyond(cz(i)) ? -2 : owner_id(owner[nb.off(cx(i), cy(i), cz(i))]);
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      if (o >= 0 && nbo[i] == o) msame |= 1u << i;
-      if (id1 < 0 && nbo[i] >= 0 && nbo[i] != o) id1 = nbo[i];
-    }
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      if (id1 >= 0 && nbo[i] == id1) m1 |= 1u << i;
-      if (id2 < 0 && nbo[i] >= 0 && nbo[i] != o && nbo[i] != id1) id2 = nbo[i];
-    }
-    bool more3 = false;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      if (id2 >= 0 && nbo[i] == id2) m2 |= 1u << i;
-      more3 = more3 || (nbo[i] >= 0 && nbo[i] != o && nbo[i] != id1 && nbo[i] != id2);
-    }
-    // particles beyond the two entries kept in registers (A, B below): for
-    // an owned node its own and id1, so id2 already counts
-    more = o >= 0 ? (id2 >= 0 || more3) : more3;
-  }
+  // byte offsets: of a node (values of this storage, and the owner map)
+  constexpr unsigned SB = sizeof(S) == 8 ? 3u : (sizeof(S) == 4 ? 2u : 1u);
+  auto boff = [&](int dx, int dy, int dz, unsigned sh) {
+    return (unsigned)(nb.xs[dx + 1] + (nb.rows[dy + 1] + nb.planes[dz + 1])) << sh;
+  };
+  const unsigned self_b = (unsigned)self << SB;
+  int o = -1;
+  if (valid) o = owner_at(owner, (unsigned)self << 2);
 
   C f[Q];
   if (valid) {
@@ -436,9 +458,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     // moving-wall term of the links that bounced back
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const int src_i = beyond(-cz(i)) ? opp(i) * n + self
-                                          : i * n + nb.off(-cx(i), -cy(i), -cz(i));
-      f[i] = Store<S>::ldn(src, src_i);
+      // (beyond() is uniform over the wavefront, which holds one x-row)
+      const bool bw = beyond(-cz(i)) != 0;
+      const S* base = src + (size_t)(bw ? opp(i) : i) * (size_t)n;
+      f[i] = ld_at<S>(base, bw ? self_b : boff(-cx(i), -cy(i), -cz(i), SB));
     }
     if (wallm || wallp) {
 #pragma unroll
@@ -528,23 +551,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   }
   if (valid) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) Store<S>::st(dst, i * n + self, f[i]);
+    for (int i = 0; i < Q; ++i) st_at<S>(dst + (size_t)i * (size_t)n, self_b, f[i]);
   }
   if (BAL) {
     // mass and momentum of the collided populations, per block in fixed
-    // order, for the zero-net-flux balance controller
-    C m = 0, j0 = 0, j1 = 0, j2 = 0;
+    // order, for the zero-net-flux balance controller: the collision keeps
+    // the mass and sets the momentum to rho v (before the storage rounds the
+    // values; with binary16 storage, sums over the rounded values would
+    // feed the storage's rounding noise back into the uniform acceleration)
+    double m = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
     if (valid) {
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        m += f[i];
-        if (cx(i)) j0 += cx(i) > 0 ? f[i] : -f[i];
-        if (cy(i)) j1 += cy(i) > 0 ? f[i] : -f[i];
-        if (cz(i)) j2 += cz(i) > 0 ? f[i] : -f[i];
-      }
-      if constexpr (Store<S>::shifted) m += (C)1;
+      m = Store<S>::shifted ? 1.0 + (double)D : (double)rho;
+      j0 = (double)(rho * v0);
+      j1 = (double)(rho * v1);
+      j2 = (double)(rho * v2);
     }
-    block_sums4(m, j0, j1, j2, nd, bal_part);
+    block_sums4s(m, j0, j1, j2, nd, bal_part);
   }
   if (!FUSED || !mea) return;                     // uniform over the block
 
@@ -554,14 +576,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   const int lid = lane < cnt ? list[lane] : -1;   // candidate list, one per lane
   for (int c = lane; c < cnt; c += WAVE)
     for (int k = 0; k < 6; ++k) red[nd.wave][c][k] = 0.0;
-  // Entries of the lane: A the node's own particle (own terms and links to
-  // its own nodes), B the first other particle owning a neighbour (for a
-  // fluid node: the first and second particles owning a neighbour); further
-  // particles around one node (rare) after the commit of A and B.
-  const int qa = o >= 0 ? o : id1;
-  const int qb = o >= 0 ? id1 : id2;
-  const unsigned mA = o >= 0 ? msame : m1;
-  const unsigned mB = o >= 0 ? m1 : m2;
+  // Owners of the 18 neighbours (-2: beyond a wall) and the lane's entries:
+  // A the node's own particle (own terms and links to its own nodes), or for
+  // a fluid node the largest id owning a neighbour; B the largest other id
+  // owning a neighbour; further particles around one node (rare) after the
+  // commit of A and B.  Selects and maxima only, no branches.
+  int nbo[Q];
+  nbo[0] = -1;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    // (every lane loads: a node outside the lattice reads entry 0, a link
+    // beyond a wall its clamped neighbour, and both are then replaced)
+    const int v = owner_at(owner, valid ? boff(cx(i), cy(i), cz(i), 2) : 0u);
+    nbo[i] = !valid ? -1 : (beyond(cz(i)) ? -2 : v);
+  }
+  int mx = -1;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) mx = max(mx, nbo[i]);
+  const int qa = o >= 0 ? o : mx;
+  int qb = -1;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) qb = max(qb, nbo[i] != qa ? nbo[i] : -1);
+  bool more = false;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) more = more | ((nbo[i] >= 0) & (nbo[i] != qa) & (nbo[i] != qb));
   const bool multi = __ballot(qb >= 0) != 0;      // uniform over the wavefront
   if (__ballot(qa >= 0) != 0) {                   // else no lane has an entry
   // One pass over the stored values v_i (FP64: minus the rest weight): the
@@ -594,8 +632,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
         if (cz(i)) j[2] += cz(i) > 0 ? bi : -bi;
       }
     }
-    link_add(La, ((mA >> i) & 1u) ? vi : (C)0, i);
-    if (multi) link_add(Lb, ((mB >> i) & 1u) ? vi : (C)0, i);
+    link_add(La, nbo[i] == qa ? vi : (C)0, i);
+    if (multi) link_add(Lb, nbo[i] == qb ? vi : (C)0, i);
   }
   C Ga[3] = {(C)0, (C)0, (C)0}, Ta[3] = {(C)0, (C)0, (C)0};
   C Gb[3] = {(C)0, (C)0, (C)0}, Tb[3] = {(C)0, (C)0, (C)0};
@@ -623,13 +661,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
       if ((ba | bb) == 0) break;
       const int pick = ba ? __builtin_amdgcn_readlane(qa, __ffsll((long long)ba) - 1)
                           : __builtin_amdgcn_readlane(qb, __ffsll((long long)bb) - 1);
+      // (A and B name different particles: at most one of ta, tb holds)
       const bool ta = pa && qa == pick, tb = pb && qb == pick;
-      double vv[6];
+      C vv[6];
       for (int k = 0; k < 3; ++k) {
-        vv[k] = -((ta ? (double)Ga[k] : 0.0) + (tb ? (double)Gb[k] : 0.0));
-        vv[3 + k] = -((ta ? (double)Ta[k] : 0.0) + (tb ? (double)Tb[k] : 0.0));
+        vv[k] = ta ? -Ga[k] : (tb ? -Gb[k] : (C)0);
+        vv[3 + k] = ta ? -Ta[k] : (tb ? -Tb[k] : (C)0);
       }
-      const double sum = wave_sum6_scatter(vv);
+      double sum;
+      if constexpr (sizeof(C) == 4)
+        sum = wave_sum6_scatter_f(vv);
+      else
+        sum = wave_sum6_scatter(vv);
       const uint64_t hit = __ballot(lid == pick);
       if (lane < 12 && (lane & 1) == 0) {
         const int k = lane >> 1;
@@ -652,7 +695,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   // rows in queue order (a full queue sends the rest to the overflow sums
   // with atomics)
   if (__ballot(more)) {
-    const int skip1 = o >= 0 ? id1 : id2;   // the entries already committed
     int last = -1, nq = 0;
     while (__ballot(more)) {
       int q = -1;
@@ -670,7 +712,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
           const bool bw = WALL && (zn < 0 || zn >= g.nz);
           zn = zn < 0 ? zn + g.nz : (zn >= g.nz ? zn - g.nz : zn);
           const int b = bw ? -2 : owner_id(owner[xn + g.nx * (yn + g.ny * zn)]);
-          const bool cand = b >= 0 && b != o && b != id1 && b != skip1 && b > last;
+          const bool cand = b >= 0 && b != qa && b != qb && b > last;
           const bool lower = cand && (q < 0 || b < q);
           mask = lower ? (1u << i) : ((cand && b == q) ? (mask | (1u << i)) : mask);
           q = lower ? b : q;
@@ -831,7 +873,6 @@ __global__ __launch_bounds__(256) void k_mea(const S* __restrict__ fs,
 template <typename S>
 __global__ __launch_bounds__(256) void k_pop_moments(const S* __restrict__ f, Geom g,
                                                      double* __restrict__ out) {
-  using C = typename Store<S>::C;
   const BlockNode nd = block_node(g);
   const int n = (int)g.ncell;
   double m = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
