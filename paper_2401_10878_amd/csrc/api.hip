@@ -749,9 +749,9 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
   const size_t nn = n > 0 ? n : 1;
   // layout of the one particle allocation (doubles, then ints)
   // 5 scalars, X 3, q 4, U 3, W 3, R 9, Fh 3, Th 3, Fc 3, Tc 3
-  // (plus 6 doubles' room for the 12 FP32 screening values), inverse
+  // (plus SREC / 2 doubles' room for the FP32 screening record), inverse
   // inertia 9
-  const size_t nd = nn * (5 + 3 + 4 + 3 + 3 + 9 + 3 + 3 + 3 + 3 + 6 + 9);
+  const size_t nd = nn * (5 + 3 + 4 + 3 + 3 + 9 + 3 + 3 + 3 + 3 + SREC / 2 + 9);
   const size_t bytes = nd * sizeof(double) + nn * sizeof(int);
   c.part_bytes = bytes;
   HIPCHECK(hipMalloc(&c.part_block, bytes));
@@ -762,7 +762,7 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
   double* dmass = take(1); double* dinert = take(1);
   c.part.X = take(3); c.part.q = take(4); c.part.U = take(3); c.part.W = take(3);
   c.part.R = take(9);
-  c.part.XR32 = (float*)take(6);
+  c.part.XR32 = (float*)take(SREC / 2);
   c.Fh = take(3); c.Th = take(3);
   c.Fc = take(3); c.Tc = take(3);
   double* diinv = take(9);

@@ -28,6 +28,11 @@ constexpr int LX = 64, LY = 4, LZ = 1;
 constexpr int LCAP_MAX = 64;    // lattice-block candidate capacity
 constexpr int MAXC = 32;        // contacts per particle in one step
 constexpr int BAL_PARTS = 256;  // first-stage workgroups of the balance sums
+// FP32 screening record of a particle, per particle: centre (3), rotation
+// (9), then the detection thresholds with the particle's FP32 error bound
+// tol: eps/2 + tol, eps/2 - tol, sqrt(0.75) + delta_c + tol,
+// sqrt(0.75) + delta_c - tol, the larger upper threshold, and the size
+constexpr int SREC = 20;
 // owner-map entry: the owning particle's id, or -1 (no owner)
 __device__ inline int owner_id(int v) { return v < 0 ? -1 : v; }
 constexpr int WAVE = 64;
@@ -628,10 +633,14 @@ __device__ inline double weight(double d, double eps) {
   return c * c;
 }
 
+// FP32 form for the FP32 and binary16 storage: the hardware cosine of the
+// angle in revolutions, cos(pi (d + eps/2) / (2 eps)) = cos(2 pi t) with
+// t = (d + eps/2) / (4 eps) in [0, 1/4] (absolute error about 1e-6, below
+// what the FP32 populations resolve of the velocity shift).
 __device__ inline float weight32(float d, float eps) {
   if (d <= -0.5f * eps) return 1.0f;
   if (d >= 0.5f * eps) return 0.0f;
-  const float c = cosf((float)PI * (d + 0.5f * eps) / (2.0f * eps));
+  const float c = __builtin_amdgcn_cosf((d + 0.5f * eps) * (0.25f / eps));
   return c * c;
 }
 

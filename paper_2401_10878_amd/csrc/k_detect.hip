@@ -80,8 +80,7 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
   const int z = tz * DZ + lane / (DX * DY);
   const bool valid = x < g.nx && y < g.ny && z < g.nz;
   const bool perz = g.periodic_z != 0;
-  const double fx = (double)x, fy = (double)y, fz = (double)z;
-  const double Lx = (double)g.nx, Ly = (double)g.ny, Lz = (double)g.nz;
+  const long long node = (long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z);
 
   // The tile's count and candidate ids in one round trip (lane c reads slot
   // c of the list whatever the count); the loops take candidate c's id with
@@ -92,95 +91,108 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
   const int my_id = lane < g.tile_cap ? list[lane] : 0;
   int cnt = __builtin_amdgcn_readfirstlane(cnt_raw);
   cnt = cnt < g.tile_cap ? cnt : g.tile_cap;
+  if (cnt == 0) {
+    // no particle within reach of the tile: fluid, nothing flagged
+    if (valid) owner[node] = -1;
+    return;
+  }
   const bool have = lane < cnt;
   const int pid = have ? my_id : 0;
   const float fxf = (float)x, fyf = (float)y, fzf = (float)z;
   const float Lxf = (float)g.nx, Lyf = (float)g.ny, Lzf = (float)g.nz;
   const double own_t = 0.5 * ph.eps;              // owner:     d < eps/2
-  const double det_t = DETECT + ph.delta_c;       // detection: d < sqrt(0.75) + delta_c
 
   // Pass 1, FP32: classify each candidate against both thresholds with a
-  // bound on the FP32 error.  Per lane: pown = candidates that may own the
-  // node (d < eps/2 + tol), near_own = one of them lies within tol of eps/2,
-  // dun = candidates within tol of the detection threshold, mask = the FP32
-  // detection decision (final for candidates outside dun).
+  // bound tol on the FP32 error (the thresholds +- tol come with the
+  // candidate's screening record).  Per lane: mask = candidates that may
+  // be flagged (d < sqrt(0.75) + delta_c + tol; when eps/2 is the smaller
+  // threshold, a superset of those that may own the node), nown = how many
+  // may own it (d < eps/2 + tol) and bp
+  // the last of them; near_own / any_dun = one of them lies within tol of
+  // its threshold, so FP32 cannot decide.  Over the wavefront (ballots):
+  // det_w = candidates some lane may flag.
   //
-  // The error bound tol = 1e-3 + 1e-5 (|r|_1 + size) is taken with |r|_1 at
-  // its largest for a node within reach of either threshold, sqrt 3 (R + 2)
-  // with R the circumradius, so it is uniform per candidate: a node farther
-  // out has d far above both thresholds, where the bound is not needed.
-  int bp = -1;
-  bool near_own = false;
-  uint64_t pown = 0, dun = 0, mask = 0;
-  const float ot = (float)own_t, dt = (float)det_t;
+  // tol = 1e-3 + 1e-5 (|r|_1 + size) is taken with |r|_1 at its largest for
+  // a node within reach of either threshold, sqrt 3 (R + 2) with R the
+  // circumradius, so it is uniform per candidate: a node farther out has d
+  // far above both thresholds, where the bound is not needed.
+  int bp = -1, nown = 0;
+  bool near_own = false, any_dun = false;
+  uint64_t mask = 0, det_w = 0;
+  // with a coupling band wider than the detection reach (eps/2 > sqrt(0.75)
+  // + delta_c) a candidate may own a node it cannot flag: those are kept
+  // apart for pass 2 (uniform branch)
+  const bool own_wider = 0.5 * ph.eps > DETECT + ph.delta_c;
+  uint64_t mown = 0;
   for (int c = 0; c < cnt; ++c) {
     const int p = __builtin_amdgcn_readlane(pid, c);
-    const float* xr = P.XR32 + 12 * p;      // uniform: scalar loads
+    const float* xr = P.XR32 + SREC * p;    // uniform: scalar loads
     const int shape = P.shape[p];
-    const float size = (float)P.size[p];
     const float f0 = minimg_f(fxf - xr[0], Lxf, true);
     const float f1 = minimg_f(fyf - xr[1], Lyf, true);
     const float f2 = minimg_f(fzf - xr[2], Lzf, perz);
-    const float rc = POLY && shape >= POLY0 ? (float)P.poly[shape - POLY0].rc * size
-                                    : (shape == 1 ? 0.8660254f * size : size);
-    const float tol = 1e-3f + 1e-5f * (1.7320508f * (rc + 2.0f) + size);
     // a polyhedron's plane lower bound beyond both thresholds ends its search
-    const float d = sdf32_r(shape, size, xr + 3, f0, f1, f2, POLY ? P.poly : nullptr,
-                            fmaxf(ot, dt) + tol);
+    const float d = sdf32_r(shape, xr[17], xr + 3, f0, f1, f2, POLY ? P.poly : nullptr,
+                            xr[16]);
     // (selects, not branches: the bookkeeping runs for every candidate)
-    const uint64_t bit = 1ull << c;
-    const bool may_own = d < ot + tol, may_det = d < dt + tol;
-    pown |= may_own ? bit : 0ull;
+    const bool may_own = valid && d < xr[12], may_det = valid && d < xr[14];
+    nown += may_own ? 1 : 0;
     bp = may_own ? p : bp;
-    near_own = near_own || (may_own && d > ot - tol);
-    mask |= may_det ? bit : 0ull;
-    dun |= (may_det && d > dt - tol) ? bit : 0ull;
+    near_own = near_own || (may_own && d > xr[13]);
+    any_dun = any_dun || (may_det && d > xr[15]);
+    mask |= may_det ? 1ull << c : 0ull;
+    if (own_wider) mown |= may_own ? 1ull << c : 0ull;
+    if (__ballot(may_det)) det_w |= 1ull << c;
   }
-  // Pass 2, FP64, only where pass 1 did not settle: the owner when two or
-  // more candidates may own the node or one lies within tol of eps/2
-  // (smallest (d, id) over the possible owners), and the detection bit of
-  // each candidate within tol of its threshold.  The wavefront loops over
-  // the union of those candidates; each lane evaluates only its own.
-  const bool own_open = valid && (near_own || (pown & (pown - 1)) != 0);
-  const uint64_t need = valid ? ((own_open ? pown : 0) | dun) : 0;
-  uint64_t todo = wave_or_u64(need);
-  if (todo) {
+  // Pass 2, FP64, only for lanes pass 1 did not settle: the owner when two
+  // or more candidates may own the node or one lies within tol of eps/2
+  // (smallest (d, id) among the candidates with d < eps/2), and the
+  // detection bits where one lies within tol of its threshold.  Such a lane
+  // re-evaluates every candidate it may flag or that may own it, in the
+  // oracle's exact expressions (for a candidate clearly inside or outside a
+  // threshold the exact decision is the FP32 one).  The wavefront loops over
+  // the union of those candidates.
+  const bool own_open = near_own || nown > 1;
+  const bool open = own_open || any_dun;
+  uint64_t orm = det_w;
+  if (__ballot(open)) {
+    const double fx = (double)x, fy = (double)y, fz = (double)z;
+    const double Lx = (double)g.nx, Ly = (double)g.ny, Lz = (double)g.nz;
+    const uint64_t m1 = open ? (mask | mown) : 0ull;
+    uint64_t todo = wave_or_u64(m1);
     double bd = 1.0e300;
     int ep = -1;
     while (todo) {
       const int c = __builtin_ctzll(todo);
       todo &= todo - 1;
       const int p = __builtin_amdgcn_readlane(pid, c);
-      if ((need >> c) & 1ull) {
+      if ((m1 >> c) & 1ull) {
         const double X0 = P.X[3 * p], X1 = P.X[3 * p + 1], X2 = P.X[3 * p + 2];
         const double* R = P.R + 9 * p;
         const double r0 = minimg(fx - X0, Lx, true);
         const double r1 = minimg(fy - X1, Ly, true);
         const double r2 = minimg(fz - X2, Lz, perz);
         const double d = sdf_exact(P.shape[p], P.size[p], R, r0, r1, r2, POLY ? P.poly : nullptr);
-        if (own_open && ((pown >> c) & 1ull) && d < own_t &&
-            (d < bd || (d == bd && p < ep))) {
+        if (own_open && d < own_t && (d < bd || (d == bd && p < ep))) {
           bd = d;
           ep = p;
         }
-        if ((dun >> c) & 1ull) {
+        if (any_dun) {
           if (d - ph.delta_c < DETECT) mask |= 1ull << c;
           else mask &= ~(1ull << c);
         }
       }
     }
     if (own_open) bp = ep;
-  }
-  if (!valid) {
-    bp = -1;
-    mask = 0;
+    orm = wave_or_u64(mask);
   }
   // owner map: the owner's id, or -1
-  if (valid)
-    owner[(long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z)] = bp;
+  if (valid) owner[node] = bp;
 
-  const uint64_t orm = wave_or_u64(mask);
+  // orm: candidates flagged at some node of the tile
   if (orm == 0) return;
+  const double fx = (double)x, fy = (double)y, fz = (double)z;
+  const double Lx = (double)g.nx, Ly = (double)g.ny, Lz = (double)g.nz;
   const bool wbot = valid && !perz && (fz + 0.5 < DETECT);
   const bool wtop = valid && !perz && ((Lz - 0.5) - fz < DETECT);
   const bool anywall = __ballot(wbot || wtop) != 0;

@@ -493,7 +493,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   }
   const C rho = Store<S>::shifted ? (C)1 + D : D;
   if (valid && !(rho > (C)0 && rho < (C)1e30)) atomicOr(&ctr->unstable, 1);
-  const C inv = (C)1 / rho;
+  // (FP32: the hardware reciprocal, within 1 ulp)
+  C inv;
+  if constexpr (sizeof(C) == 4)
+    inv = __builtin_amdgcn_rcpf(rho);
+  else
+    inv = (C)1 / rho;
   const C u0 = J0 * inv, u1 = J1 * inv, u2 = J2 * inv;
 
   // coupling: B and u_p of the owner, in FP64 for FP64 storage and in FP32

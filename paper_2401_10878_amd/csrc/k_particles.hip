@@ -199,8 +199,26 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
     }
     for (int k = 0; k < 4; ++k) P.q[4 * ip + k] = q[k];
     for (int k = 0; k < 9; ++k) P.R[9 * ip + k] = R[k];
-    for (int k = 0; k < 3; ++k) P.XR32[12 * ip + k] = (float)X[k];
-    for (int k = 0; k < 9; ++k) P.XR32[12 * ip + 3 + k] = (float)R[k];
+    float* rec = P.XR32 + SREC * ip;
+    for (int k = 0; k < 3; ++k) rec[k] = (float)X[k];
+    for (int k = 0; k < 9; ++k) rec[3 + k] = (float)R[k];
+    // the detection screen's thresholds with this particle's FP32 error
+    // bound: 1e-3 + 1e-5 (|r|_1 + size) at |r|_1 = sqrt 3 (R_c + 2), the
+    // largest for a node within reach of either threshold (R_c the
+    // circumradius)
+    const int sh = P.shape[ip];
+    const float fs = (float)P.size[ip];
+    const float rc = sh >= POLY0 ? (float)P.poly[sh - POLY0].rc * fs
+                                 : (sh == 1 ? 0.8660254f * fs : fs);
+    const float tol = 1e-3f + 1e-5f * (1.7320508f * (rc + 2.0f) + fs);
+    const float ot = (float)(0.5 * ph.eps), dt = (float)(DETECT + ph.delta_c);
+    rec[12] = ot + tol;
+    rec[13] = ot - tol;
+    rec[14] = dt + tol;
+    rec[15] = dt - tol;
+    rec[16] = fmaxf(ot, dt) + tol;
+    rec[17] = fs;
+    rec[18] = rec[19] = 0.0f;
   }
 
   // 3. Reach box: axis-aligned half extent of the body plus the largest
