@@ -386,7 +386,7 @@ __device__ inline void commit_round(int q, const C* G, const C* T, int lid,
 
 // Register budget without spills: FP64 at most 128 VGPRs (four wavefronts
 // per SIMD), FP32 at most 96 (five); binary16, which stores only, at most
-// 80 (six) for periodic scenes of spheres and cubes, else 96.  POLY: built
+// 64 (eight) for periodic scenes of spheres and cubes, else 96.  POLY: built
 // with the polyhedron signed distance (scenes without polyhedra run the
 // form without it, which needs fewer registers).  BAL: with the block sums
 // and device acceleration of the zero-net-flux balance force.  WALL: z
@@ -410,7 +410,7 @@ __device__ inline void commit_round(int q, const C* G, const C* T, int lid,
 // separate pass over the stored (rounded) values.
 template <typename S, bool POLY, bool BAL, bool WALL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
-    sizeof(S) == 8 ? 4 : (sizeof(S) == 4 || POLY || WALL ? 5 : 6), 8))) void k_lattice(const S* __restrict__ src,
+    sizeof(S) == 8 ? 4 : (sizeof(S) == 4 || POLY || WALL ? 5 : 8), 8))) void k_lattice(const S* __restrict__ src,
                                                  S* __restrict__ dst,
                                                  const int* __restrict__ owner,
                                                  Particles P, Geom g, Phys ph,
