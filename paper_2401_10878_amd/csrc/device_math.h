@@ -31,7 +31,8 @@ constexpr int BAL_PARTS = 256;  // first-stage workgroups of the balance sums
 // FP32 screening record of a particle, per particle: centre (3), rotation
 // (9), then the detection thresholds with the particle's FP32 error bound
 // tol: eps/2 + tol, eps/2 - tol, sqrt(0.75) + delta_c + tol,
-// sqrt(0.75) + delta_c - tol, the larger upper threshold, and the size
+// sqrt(0.75) + delta_c - tol, the larger upper threshold, the size and
+// the shape code (its bits)
 constexpr int SREC = 20;
 // owner-map entry: the owning particle's id, or -1 (no owner)
 __device__ inline int owner_id(int v) { return v < 0 ? -1 : v; }

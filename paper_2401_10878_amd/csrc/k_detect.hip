@@ -126,20 +126,26 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
   uint64_t mown = 0;
   for (int c = 0; c < cnt; ++c) {
     const int p = __builtin_amdgcn_readlane(pid, c);
-    const float* xr = P.XR32 + SREC * p;    // uniform: scalar loads
-    const int shape = P.shape[p];
+    // the whole record at once (uniform: scalar loads issued together),
+    // and bookkeeping without short-circuit branches, so that one wait
+    // serves the candidate
+    const float* src = P.XR32 + SREC * p;
+    float xr[19];
+#pragma unroll
+    for (int k = 0; k < 19; ++k) xr[k] = src[k];
+    __builtin_amdgcn_sched_barrier(0);
+    const int shape = __float_as_int(xr[18]);
     const float f0 = minimg_f(fxf - xr[0], Lxf, true);
     const float f1 = minimg_f(fyf - xr[1], Lyf, true);
     const float f2 = minimg_f(fzf - xr[2], Lzf, perz);
     // a polyhedron's plane lower bound beyond both thresholds ends its search
     const float d = sdf32_r(shape, xr[17], xr + 3, f0, f1, f2, POLY ? P.poly : nullptr,
                             xr[16]);
-    // (selects, not branches: the bookkeeping runs for every candidate)
-    const bool may_own = valid && d < xr[12], may_det = valid && d < xr[14];
+    const bool may_own = valid & (d < xr[12]), may_det = valid & (d < xr[14]);
     nown += may_own ? 1 : 0;
     bp = may_own ? p : bp;
-    near_own = near_own || (may_own && d > xr[13]);
-    any_dun = any_dun || (may_det && d > xr[15]);
+    near_own = near_own | (may_own & (d > xr[13]));
+    any_dun = any_dun | (may_det & (d > xr[15]));
     mask |= may_det ? 1ull << c : 0ull;
     if (own_wider) mown |= may_own ? 1ull << c : 0ull;
     if (__ballot(may_det)) det_w |= 1ull << c;

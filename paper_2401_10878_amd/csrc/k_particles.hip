@@ -218,7 +218,8 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
     rec[15] = dt - tol;
     rec[16] = fmaxf(ot, dt) + tol;
     rec[17] = fs;
-    rec[18] = rec[19] = 0.0f;
+    rec[18] = __int_as_float(sh);
+    rec[19] = 0.0f;
   }
 
   // 3. Reach box: axis-aligned half extent of the body plus the largest

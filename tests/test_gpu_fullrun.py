@@ -12,7 +12,10 @@ written by tests/golden/make_fullrun_refs.py, and is compared with it:
   episode leave the pointwise trajectory comparison from that step on;
 * at the stored snapshots: positions, orientations, velocities, angular
   velocities and the hydrodynamic force of the remaining particles, and the
-  mean settling velocity (mean U_z) of all particles.
+  mean settling velocity (mean U_z) of all particles;
+* at the end, for the fully periodic boxes: the lattice momentum per unit
+  lattice mass against the mean settling velocity (zero net volume flow:
+  below 1e-3 of it, the bound the stored oracle runs meet).
 
 The bounds asserted are the ones measured, with a margin (the rounding of
 the FP64 path differs from the oracle's in the order of its sums, and a node
@@ -104,9 +107,14 @@ def run_gpu(W, H, name, prec, snap_steps, nsteps):
     for t in range(1, nsteps + 1):
         sim.step(1)
         record(t)
+    flow = None
+    if wl.params.periodic_z:
+        f = sim.fields(owner=False)
+        rho, u = f["rho"], f["u"]
+        flow = (float(rho.sum()), (rho[..., None] * u).reshape(-1, 3).sum(axis=0))
     sim.close()
     return wl, {k: np.stack(v) for k, v in snaps.items()}, det_hash, act_hash, \
-        ep.close(nsteps)
+        ep.close(nsteps), flow
 
 
 def episode_shifts(ref_ep, gpu_ep):
@@ -129,7 +137,7 @@ def test_full_run_against_oracle(W, H, name, prec):
     nsteps = int(ref["steps"])
     snap_steps = [int(s) for s in ref["snap_steps"]]
     _say(f"{name} precision {prec}: {nsteps} steps")
-    wl, g, det_hash, act_hash, gep = run_gpu(W, H, name, prec, set(snap_steps), nsteps)
+    wl, g, det_hash, act_hash, gep, flow = run_gpu(W, H, name, prec, set(snap_steps), nsteps)
     sc = wl.scene
     # scales: velocities and forces relative to max(|oracle|, reference)
     gmag = abs(wl.params.gravity[2])
@@ -168,6 +176,13 @@ def test_full_run_against_oracle(W, H, name, prec):
     uzr = ref["snap_U"][-1][:, 2].mean()
     msv = abs(uz - uzr) / abs(uzr)
     _say(f"  mean settling velocity: gpu {uz:.9e} oracle {uzr:.9e} rel {msv:.2e}")
+    if flow is not None:
+        M, P = flow
+        drift = np.abs(P).max() / M / abs(uz)
+        _say(f"  lattice momentum / mass: {np.abs(P).max() / M:.3e} "
+             f"({drift:.2e} of the mean settling velocity; oracle "
+             f"{np.abs(ref['momentum']).max() / float(ref['mass']):.3e})")
+        assert drift < 1e-3
     b = BOUNDS[(name, prec)]
     if b["shifts"] is not None:
         assert only_ref + only_gpu <= b["shifts"], (only_ref, only_gpu)
