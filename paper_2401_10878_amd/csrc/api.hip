@@ -135,7 +135,7 @@ hlbm_status prologue(Ctx& c) {
   HIPCHECK(launch_particles(c, 0));
   HIPCHECK(launch_detect(c, c.tab[p]));
   HIPCHECK(launch_mea(c, c.fbuf[c.cur]));
-  if (c.ph.bal_mode == 2) HIPCHECK(launch_balance(c, c.fbuf[c.cur], 1));
+  if (c.ph.bal_mode == 2) HIPCHECK(launch_balance(c, c.fbuf[c.cur], 1, c.stream));
   c.step = 0;
   c.fluid_ready = true;
   const hlbm_status st = check_flags(c);
@@ -191,9 +191,22 @@ hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev, int pre) {
   }
   // the lattice pass also sums the momentum exchange of the next step for
   // FP64 and FP32 storage (the last timing slot stays empty); for binary16
-  // storage the separate pass does, over the populations just stored
+  // storage the separate pass does, over the populations just stored.
+  // The balance controller's sums feed only the next collision: with
+  // PRE_NEXT they run on the side stream, beside the next step's
+  // bookkeeping, particle motion and detection, and the next lattice pass
+  // waits for them.
+  const bool bal = c.ph.bal_mode == 2;
+  if (bal && (pre & PRE_DONE) && (e = hipStreamWaitEvent(c.stream, c.ev_bal, 0))) return e;
   if ((e = launch_lattice(c, c.fbuf[p], c.fbuf[1 - p]))) return e;
-  if (c.ph.bal_mode == 2 && (e = launch_balance(c, nullptr, 0))) return e;
+  if (bal && (pre & PRE_NEXT)) {
+    if ((e = hipEventRecord(c.ev_lat, c.stream))) return e;
+    if ((e = hipStreamWaitEvent(c.side, c.ev_lat, 0))) return e;
+    if ((e = launch_balance(c, nullptr, 0, c.side))) return e;
+    if ((e = hipEventRecord(c.ev_bal, c.side))) return e;
+  } else if (bal && (e = launch_balance(c, nullptr, 0, c.stream))) {
+    return e;
+  }
   if ((e = mark())) return e;
   if (c.precision == HLBM_FP16S && (e = launch_mea(c, c.fbuf[1 - p]))) return e;
   return mark();
@@ -439,9 +452,14 @@ hlbm_status hlbm_create(const hlbm_params* params, void* stream, hlbm_ctx** out)
   }
   if (hipStreamCreate(&c.side) != hipSuccess ||
       hipEventCreateWithFlags(&c.ev_det, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c.ev_treat, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c.ev_treat, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c.ev_lat, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c.ev_bal, hipEventDisableTiming) != hipSuccess) {
     if (c.side) hipStreamDestroy(c.side);
     if (c.ev_det) hipEventDestroy(c.ev_det);
+    if (c.ev_treat) hipEventDestroy(c.ev_treat);
+    if (c.ev_lat) hipEventDestroy(c.ev_lat);
+    if (c.ev_bal) hipEventDestroy(c.ev_bal);
     if (c.own_stream) hipStreamDestroy(c.stream);
     delete h;
     return HLBM_E_DEVICE;
@@ -1487,6 +1505,8 @@ void hlbm_destroy(hlbm_ctx* h) {
   }
   if (c.ev_det) hipEventDestroy(c.ev_det);
   if (c.ev_treat) hipEventDestroy(c.ev_treat);
+  if (c.ev_lat) hipEventDestroy(c.ev_lat);
+  if (c.ev_bal) hipEventDestroy(c.ev_bal);
   if (c.own_stream && c.stream) hipStreamDestroy(c.stream);
   delete h;
 }

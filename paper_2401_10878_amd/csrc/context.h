@@ -162,6 +162,9 @@ struct Ctx {
   // `stream`; ev_treat: treatment done on `side`)
   hipStream_t side = nullptr;
   hipEvent_t ev_det = nullptr, ev_treat = nullptr;
+  // balance sums of a step on the side stream: after its lattice pass
+  // (ev_lat), before the next step's lattice pass (ev_bal)
+  hipEvent_t ev_lat = nullptr, ev_bal = nullptr;
   int precision;
   size_t bytes_per_value;
   // populations (two buffers, ping-pong); fbuf[cur] holds f* of the last step
@@ -236,7 +239,7 @@ hipError_t launch_lattice(Ctx& c, const void* src, void* dst);
 hipError_t launch_mea(Ctx& c, const void* fstar);
 // balance mode 2: lattice mass and momentum of f at the start (init = 1), or
 // the controller update after a collision from the lattice pass's block sums
-hipError_t launch_balance(Ctx& c, const void* f, int init);
+hipError_t launch_balance(Ctx& c, const void* f, int init, hipStream_t st);
 hipError_t launch_treat(Ctx& c, PairTable t, hipStream_t s);
 hipError_t launch_fill_equilibrium(Ctx& c, void* f, double rho,
                                    const double u[3]);

@@ -1047,13 +1047,13 @@ static void run_pop_moments(Ctx& c, const void* f) {
                      c.stream, (const S*)f, c.g, c.bal_part);
 }
 
-hipError_t launch_balance(Ctx& c, const void* f, int init) {
+hipError_t launch_balance(Ctx& c, const void* f, int init, hipStream_t st) {
   if (init) DISPATCH(c, run_pop_moments, (c, f));
   const unsigned nb = tile_blocks(c.g);
   double* parts = c.bal_part + 4 * (size_t)nb;
-  hipLaunchKernelGGL(k_balance_part, dim3(BAL_PARTS), dim3(256), 0, c.stream, c.bal_part,
+  hipLaunchKernelGGL(k_balance_part, dim3(BAL_PARTS), dim3(256), 0, st, c.bal_part,
                      nb, parts);
-  hipLaunchKernelGGL(k_balance, dim3(1), dim3(256), 0, c.stream, parts, c.counters, c.ph,
+  hipLaunchKernelGGL(k_balance, dim3(1), dim3(256), 0, st, parts, c.counters, c.ph,
                      init);
   return hipGetLastError();
 }
