@@ -197,15 +197,20 @@ __device__ void store_block(double (*red)[LCAP_MAX][6], const int* list,
   }
 }
 
-// Block sums of four per-lane FP64 values through one reduce-scatter per
-// wavefront (the sums land in lanes 0, 2, 4, 6), then the four wavefronts'
-// rows added in fixed order and stored at out[4 * block ..].  Every thread
-// of the block must call it.
-__device__ void block_sums4s(double a, double b, double c, double d,
-                             const BlockNode& nd, double* out) {
+// Block sums of four per-lane values through one reduce-scatter per
+// wavefront (the sums land in lanes 0, 2, 4, 6; FP32 values add their first
+// level, two lanes, in FP32 and the rest in FP64), then the four
+// wavefronts' rows added in fixed order and stored at out[4 * block ..].
+// Every thread of the block must call it.
+template <typename C>
+__device__ void block_sums4s(C a, C b, C c, C d, const BlockNode& nd, double* out) {
   __shared__ double rows[4][4];
-  const double v[6] = {a, b, c, d, 0.0, 0.0};
-  const double sum = wave_sum6_scatter(v);
+  const C v[6] = {a, b, c, d, (C)0, (C)0};
+  double sum;
+  if constexpr (sizeof(C) == 4)
+    sum = wave_sum6_scatter_f(v);
+  else
+    sum = wave_sum6_scatter(v);
   const int lane = threadIdx.x % WAVE;
   if (lane < 8 && (lane & 1) == 0) rows[nd.wave][lane >> 1] = sum;
   __syncthreads();
@@ -564,14 +569,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     // the mass and sets the momentum to rho v (before the storage rounds the
     // values; with binary16 storage, sums over the rounded values would
     // feed the storage's rounding noise back into the uniform acceleration)
-    double m = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
+    C m = (C)0, j0 = (C)0, j1 = (C)0, j2 = (C)0;
     if (valid) {
-      m = Store<S>::shifted ? 1.0 + (double)D : (double)rho;
-      j0 = (double)(rho * v0);
-      j1 = (double)(rho * v1);
-      j2 = (double)(rho * v2);
+      m = rho;
+      j0 = rho * v0;
+      j1 = rho * v1;
+      j2 = rho * v2;
     }
-    block_sums4s(m, j0, j1, j2, nd, bal_part);
+    block_sums4s<C>(m, j0, j1, j2, nd, bal_part);
   }
   if (!FUSED || !mea) return;                     // uniform over the block
 
