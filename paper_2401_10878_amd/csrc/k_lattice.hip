@@ -156,7 +156,8 @@ __device__ inline BlockNode block_node(const Geom& g) {
 // is added (by lane 0, in a fixed order) to that candidate's LDS row as
 // -sum, the force and torque on the particle (eqs. (17)-(18)).  An id missing
 // from the candidate list (not expected) goes to the overflow sums.
-__device__ void commit_group(int q, const double* s, const double* t, int lid,
+template <typename V>
+__device__ void commit_group(int q, const V* s, const V* t, int lid,
                              double (*row)[6], double* ovf) {
   const int lane = threadIdx.x % WAVE;
   bool pend = q >= 0;
@@ -165,12 +166,17 @@ __device__ void commit_group(int q, const double* s, const double* t, int lid,
     if (m == 0) break;
     const int pick = __builtin_amdgcn_readlane(q, __ffsll((long long)m) - 1);
     const bool take = pend && q == pick;
-    double v[6];
+    V v[6];
     for (int k = 0; k < 3; ++k) {
-      v[k] = take ? s[k] : 0.0;
-      v[3 + k] = take ? t[k] : 0.0;
+      v[k] = take ? s[k] : (V)0;
+      v[3 + k] = take ? t[k] : (V)0;
     }
-    const double sum = wave_sum6_scatter(v);   // component lane/2 in even lanes < 12
+    // component lane/2 in even lanes < 12 (FP32 values: first level in FP32)
+    double sum;
+    if constexpr (sizeof(V) == 4)
+      sum = wave_sum6_scatter_f(v);
+    else
+      sum = wave_sum6_scatter(v);
     const uint64_t hit = __ballot(lid == pick);
     if (lane < 12 && (lane & 1) == 0) {
       const int k = lane >> 1;
@@ -829,7 +835,10 @@ __global__ __launch_bounds__(256) void k_mea(const S* __restrict__ fs,
   const Nbr nb = neighbours(g, x, y, z);
   const int self = nb.off(0, 0, 0);
   const int o = nd.valid ? owner_id(owner[self]) : -1;
-  double s[3] = {0.0, 0.0, 0.0}, t[3] = {0.0, 0.0, 0.0};
+  // S and r x S in the compute precision C (FP64 for FP64 storage); the
+  // minimum image in FP64, the reductions across nodes in FP64 (after a
+  // first FP32 level for FP32 values)
+  C s[3] = {(C)0, (C)0, (C)0}, t[3] = {(C)0, (C)0, (C)0};
   if (o >= 0) {
     // all population and record loads issued before any use
     // (beyond a wall the neighbour index is clamped into the lattice; that
@@ -861,15 +870,16 @@ __global__ __launch_bounds__(256) void k_mea(const S* __restrict__ fs,
       if (cy(i)) dJ1 += cy(i) > 0 ? d : -d;
       if (cz(i)) dJ2 += cz(i) > 0 ? d : -d;
     }
-    const double r0 = minimg((double)x - X0, (double)g.nx, true);
-    const double r1 = minimg((double)y - X1, (double)g.ny, true);
-    const double r2 = minimg((double)z - X2, (double)g.nz, g.periodic_z != 0);
-    const double up0 = U0 + (W1 * r2 - W2 * r1);
-    const double up1 = U1 + (W2 * r0 - W0 * r2);
-    const double up2 = U2 + (W0 * r1 - W1 * r0);
-    s[0] = (double)dJ0 - up0 * (double)dD;
-    s[1] = (double)dJ1 - up1 * (double)dD;
-    s[2] = (double)dJ2 - up2 * (double)dD;
+    const C r0 = (C)minimg((double)x - X0, (double)g.nx, true);
+    const C r1 = (C)minimg((double)y - X1, (double)g.ny, true);
+    const C r2 = (C)minimg((double)z - X2, (double)g.nz, g.periodic_z != 0);
+    const C w0 = (C)W0, w1 = (C)W1, w2 = (C)W2;
+    const C up0 = (C)U0 + (w1 * r2 - w2 * r1);
+    const C up1 = (C)U1 + (w2 * r0 - w0 * r2);
+    const C up2 = (C)U2 + (w0 * r1 - w1 * r0);
+    s[0] = dJ0 - up0 * dD;
+    s[1] = dJ1 - up1 * dD;
+    s[2] = dJ2 - up2 * dD;
     t[0] = r1 * s[2] - r2 * s[1];
     t[1] = r2 * s[0] - r0 * s[2];
     t[2] = r0 * s[1] - r1 * s[0];
