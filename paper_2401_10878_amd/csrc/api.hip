@@ -768,14 +768,16 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
   // layout of the one particle allocation (doubles, then ints)
   // 5 scalars, X 3, q 4, U 3, W 3, R 9, Fh 3, Th 3, Fc 3, Tc 3
   // (plus SREC / 2 doubles' room for the FP32 screening record), inverse
-  // inertia 9
-  const size_t nd = nn * (5 + 3 + 4 + 3 + 3 + 9 + 3 + 3 + 3 + 3 + SREC / 2 + 9);
+  // inertia 9; the FP32 kinematic record (LREC / 2 doubles) first, so that
+  // its 16-byte rows are aligned
+  const size_t nd = nn * (LREC / 2 + 5 + 3 + 4 + 3 + 3 + 9 + 3 + 3 + 3 + 3 + SREC / 2 + 9);
   const size_t bytes = nd * sizeof(double) + nn * sizeof(int);
   c.part_bytes = bytes;
   HIPCHECK(hipMalloc(&c.part_block, bytes));
   HIPCHECK(hipMemsetAsync(c.part_block, 0, bytes, c.stream));
   double* d = (double*)c.part_block;
   auto take = [&](size_t k) { double* p = d; d += k * nn; return p; };
+  c.part.LR32 = (float*)take(LREC / 2);
   double* dsz = take(1); double* dds = take(1); double* dvol = take(1);
   double* dmass = take(1); double* dinert = take(1);
   c.part.X = take(3); c.part.q = take(4); c.part.U = take(3); c.part.W = take(3);

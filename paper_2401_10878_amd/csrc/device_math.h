@@ -34,6 +34,13 @@ constexpr int BAL_PARTS = 256;  // first-stage workgroups of the balance sums
 // sqrt(0.75) + delta_c - tol, the larger upper threshold, the size and
 // the shape code (its bits)
 constexpr int SREC = 20;
+// FP32 kinematic record of a particle for the lattice pass (FP32 and
+// binary16 storage), 16-byte aligned: the integer part of the centre (3,
+// int bits) and its fraction (3), U (3), omega (3), the rotation (9), the
+// size and the shape code (its bits), one unused word.  A node's offset
+// from the centre is the integer difference wrapped to the minimum image
+// minus the fraction: one rounding, as for the FP64 offset rounded to FP32.
+constexpr int LREC = 24;
 // owner-map entry: the owning particle's id, or -1 (no owner)
 __device__ inline int owner_id(int v) { return v < 0 ? -1 : v; }
 constexpr int WAVE = 64;
@@ -113,7 +120,8 @@ struct Particles {
   double* U;            // [n][3]
   double* W;            // [n][3] angular velocity
   double* R;            // [n][9] rotation (body -> world), row-major
-  float* XR32;          // [n][12] X (3) and R (9) rounded to FP32, for screening
+  float* XR32;          // [n][SREC] FP32 screening record of detection
+  float* LR32;          // [n][LREC] FP32 kinematic record of the lattice pass
   const double* Iinv;   // [n][9] inverse body inertia tensor (polyhedra)
   const PolyDev* poly;  // [MAXPOLY] polyhedron types
 };
@@ -488,10 +496,12 @@ __device__ inline double sdf_exact(int shape, double size, const double* R,
   return sdf(shape, size, R, r0, r1, r2, poly);
 }
 
-// The same signed distance in FP32 arithmetic (inputs rounded to FP32), for
-// conservative screening against thresholds: its error is below
-// 1e-6 (|r|_1 + size) plus a few units in the last place.
-__device__ inline float sdf32(int shape, float size, const double* R, float r0,
+// The same signed distance in FP32 arithmetic (inputs rounded to FP32, the
+// rotation given in FP64 or already rounded), for conservative screening
+// against thresholds: its error is below 1e-6 (|r|_1 + size) plus a few
+// units in the last place.
+template <typename RT>
+__device__ inline float sdf32(int shape, float size, const RT* R, float r0,
                               float r1, float r2, const PolyDev* poly) {
   if (shape == 0) return sqrtf(r0 * r0 + r1 * r1 + r2 * r2) - size;
   if (poly && shape >= POLY0) {

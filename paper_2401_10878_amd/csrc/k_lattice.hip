@@ -303,8 +303,9 @@ __device__ inline void dir_of(int i, int& d0, int& d1, int& d2) {
 }
 
 // Masked moments of the stored post-collision deviations v_i (i >= 1) of
-// one node over the links in `mask` (bit i): m0 = sum v_i, m1 = sum c_i v_i
-// and the second moment Pi = sum c_i c_i^T v_i (six components).
+// one node over a set of links: m0 = sum v_i, m1 = sum c_i v_i and the
+// second moment Pi = sum c_i c_i^T v_i (six components), added link by link
+// (the rare path of a third particle).
 template <typename C>
 struct LinkMoments {
   C m0, m1[3], pxx, pyy, pzz, pxy, pxz, pyz;
@@ -314,29 +315,62 @@ __device__ inline void link_zero(LinkMoments<C>& m) {
   m.m0 = m.m1[0] = m.m1[1] = m.m1[2] = (C)0;
   m.pxx = m.pyy = m.pzz = m.pxy = m.pxz = m.pyz = (C)0;
 }
+
+// What the force and torque of a set of links need of its moments: m0, m1,
+// the off-diagonal Pi and the sums qx = Pi_yy + Pi_zz, qy = Pi_xx + Pi_zz,
+// qz = Pi_xx + Pi_yy (the torque takes (Pi - tr(Pi) 1) w).
 template <typename C>
-__device__ inline void link_add(LinkMoments<C>& m, C a, int i);
+struct Closure {
+  C m0, m1[3], pxy, pxz, pyz, qx, qy, qz;
+};
 template <typename C>
-__device__ inline LinkMoments<C> link_moments(const C* v, unsigned mask) {
-  LinkMoments<C> m;
-  link_zero(m);
-#pragma unroll
-  for (int i = 1; i < Q; ++i) link_add(m, ((mask >> i) & 1u) ? v[i] : (C)0, i);
-  return m;
+__device__ inline Closure<C> closure_of(const LinkMoments<C>& m) {
+  return {m.m0, {m.m1[0], m.m1[1], m.m1[2]}, m.pxy, m.pxz, m.pyz,
+          m.pyy + m.pzz, m.pxx + m.pzz, m.pxx + m.pyy};
 }
-// adds value a of direction i
+
+// The closure over the links whose neighbour is owned by particle q
+// (nbo[i] == q), from the opposite pairs: with a_i the masked value and,
+// per pair (i, opp(i)) of first link c, s = a_i + a_opp(i) and
+// d = a_i - a_opp(i), the pair adds s to m0, c d to m1 and c c^T s to Pi.
+// The three axis pairs carry s1, s2, s3; the two pairs of each coordinate
+// plane (first links (1, 1, 0) and (1, -1, 0) for xy, and likewise for xz
+// and yz) add their sum S to both diagonal entries of the plane and their
+// difference to its off-diagonal entry, so that
+//   m0 = s1 + s2 + s3 + Sxy + Sxz + Syz,
+//   Pi_yy + Pi_zz = m0 - s1 + Syz (and cyclically).
 template <typename C>
-__device__ inline void link_add(LinkMoments<C>& m, C a, int i) {
-  m.m0 += a;
-  if (cx(i)) m.m1[0] += cx(i) > 0 ? a : -a;
-  if (cy(i)) m.m1[1] += cy(i) > 0 ? a : -a;
-  if (cz(i)) m.m1[2] += cz(i) > 0 ? a : -a;
-  if (cx(i)) m.pxx += a;
-  if (cy(i)) m.pyy += a;
-  if (cz(i)) m.pzz += a;
-  if (cx(i) && cy(i)) m.pxy += cx(i) * cy(i) > 0 ? a : -a;
-  if (cx(i) && cz(i)) m.pxz += cx(i) * cz(i) > 0 ? a : -a;
-  if (cy(i) && cz(i)) m.pyz += cy(i) * cz(i) > 0 ? a : -a;
+__device__ inline Closure<C> pair_closure(const C* v, const int* nbo, int q) {
+  static_assert(cx(1) == 1 && cy(3) == 1 && cz(5) == 1, "axis pairs");
+  static_assert(cx(7) == 1 && cy(7) == 1 && cz(7) == 0 && cx(9) == 1 && cy(9) == -1 &&
+                    cz(9) == 0, "xy pairs");
+  static_assert(cx(11) == 1 && cy(11) == 0 && cz(11) == 1 && cx(13) == 1 && cy(13) == 0 &&
+                    cz(13) == -1, "xz pairs");
+  static_assert(cx(15) == 0 && cy(15) == 1 && cz(15) == 1 && cx(17) == 0 && cy(17) == 1 &&
+                    cz(17) == -1, "yz pairs");
+  static_assert(opp(1) == 2 && opp(7) == 8 && opp(17) == 18, "pair order");
+  C sp[10], dp[10];
+#pragma unroll
+  for (int k = 1; k <= 9; ++k) {
+    const int i = 2 * k - 1;
+    const C a = nbo[i] == q ? v[i] : (C)0;
+    const C b = nbo[i + 1] == q ? v[i + 1] : (C)0;
+    sp[k] = a + b;
+    dp[k] = a - b;
+  }
+  const C Sxy = sp[4] + sp[5], Sxz = sp[6] + sp[7], Syz = sp[8] + sp[9];
+  Closure<C> m;
+  m.pxy = sp[4] - sp[5];
+  m.pxz = sp[6] - sp[7];
+  m.pyz = sp[8] - sp[9];
+  m.m0 = ((sp[1] + sp[2]) + sp[3]) + ((Sxy + Sxz) + Syz);
+  m.m1[0] = (dp[1] + (dp[4] + dp[5])) + (dp[6] + dp[7]);
+  m.m1[1] = (dp[2] + (dp[4] - dp[5])) + (dp[8] + dp[9]);
+  m.m1[2] = (dp[3] + (dp[6] - dp[7])) + (dp[8] - dp[9]);
+  m.qx = (m.m0 - sp[1]) + Syz;
+  m.qy = (m.m0 - sp[2]) + Sxz;
+  m.qz = (m.m0 - sp[3]) + Sxy;
+  return m;
 }
 
 // Force G and torque T that one node y hands to particle q through the
@@ -349,36 +383,60 @@ __device__ inline void link_add(LinkMoments<C>& m, C a, int i) {
 // (c x (w x c) = |c|^2 w - c (c . w)).  G may carry the node's own terms
 // already (they act at r).
 template <typename C>
-__device__ inline void link_force(const LinkMoments<C>& m, const C* r, const C* u,
+__device__ inline void link_force(const Closure<C>& m, const C* r, const C* u,
                                   const C* w, C* G, C* T) {
   G[0] += (m.m1[0] - u[0] * m.m0) - (w[1] * m.m1[2] - w[2] * m.m1[1]);
   G[1] += (m.m1[1] - u[1] * m.m0) - (w[2] * m.m1[0] - w[0] * m.m1[2]);
   G[2] += (m.m1[2] - u[2] * m.m0) - (w[0] * m.m1[1] - w[1] * m.m1[0]);
   T[0] = (r[1] * G[2] - r[2] * G[1]) - (m.m1[1] * u[2] - m.m1[2] * u[1]) +
-         ((m.pxy * w[1] + m.pxz * w[2]) - (m.pyy + m.pzz) * w[0]);
+         ((m.pxy * w[1] + m.pxz * w[2]) - m.qx * w[0]);
   T[1] = (r[2] * G[0] - r[0] * G[2]) - (m.m1[2] * u[0] - m.m1[0] * u[2]) +
-         ((m.pxy * w[0] + m.pyz * w[2]) - (m.pxx + m.pzz) * w[1]);
+         ((m.pxy * w[0] + m.pyz * w[2]) - m.qy * w[1]);
   T[2] = (r[0] * G[1] - r[1] * G[0]) - (m.m1[0] * u[1] - m.m1[1] * u[0]) +
-         ((m.pxz * w[0] + m.pyz * w[1]) - (m.pxx + m.pyy) * w[2]);
+         ((m.pxz * w[0] + m.pyz * w[1]) - m.qz * w[2]);
 }
 
 // Kinematics of particle q seen from node (x, y, z): r = minimg(node - X),
-// u = U + w x r, w (in the compute precision C; the minimum image in FP64).
+// u = U + w x r, w.  FP64 compute precision: from the FP64 state.  FP32:
+// from the particle's FP32 kinematic record, the offset as the integer
+// difference to the centre's integer part wrapped to the minimum image
+// (unambiguous for the nodes within a particle's reach, far below half a
+// periodic length) minus the fraction.
+__device__ inline int wrap_image(int k, int L, bool periodic) {
+  const int h = L >> 1;
+  k = (periodic && k > h) ? k - L : k;
+  return (periodic && k < -h) ? k + L : k;
+}
 template <typename C>
 __device__ inline void kinematics(const Particles& P, int q, int x, int y, int z,
                                   const Geom& g, C* r, C* u, C* w) {
-  const double X0 = P.X[3 * q], X1 = P.X[3 * q + 1], X2 = P.X[3 * q + 2];
-  const double U0 = P.U[3 * q], U1 = P.U[3 * q + 1], U2 = P.U[3 * q + 2];
-  const double W0 = P.W[3 * q], W1 = P.W[3 * q + 1], W2 = P.W[3 * q + 2];
-  r[0] = (C)minimg((double)x - X0, (double)g.nx, true);
-  r[1] = (C)minimg((double)y - X1, (double)g.ny, true);
-  r[2] = (C)minimg((double)z - X2, (double)g.nz, g.periodic_z != 0);
-  w[0] = (C)W0;
-  w[1] = (C)W1;
-  w[2] = (C)W2;
-  u[0] = (C)U0 + (w[1] * r[2] - w[2] * r[1]);
-  u[1] = (C)U1 + (w[2] * r[0] - w[0] * r[2]);
-  u[2] = (C)U2 + (w[0] * r[1] - w[1] * r[0]);
+  if constexpr (sizeof(C) == 4) {
+    const float4* rec = (const float4*)(P.LR32 + LREC * q);
+    const float4 a = rec[0], b = rec[1], c = rec[2];
+    // a: Xi0 Xi1 Xi2 Xf0, b: Xf1 Xf2 U0 U1, c: U2 W0 W1 W2
+    r[0] = (float)wrap_image(x - __float_as_int(a.x), g.nx, true) - a.w;
+    r[1] = (float)wrap_image(y - __float_as_int(a.y), g.ny, true) - b.x;
+    r[2] = (float)wrap_image(z - __float_as_int(a.z), g.nz, g.periodic_z != 0) - b.y;
+    w[0] = c.y;
+    w[1] = c.z;
+    w[2] = c.w;
+    u[0] = b.z + (w[1] * r[2] - w[2] * r[1]);
+    u[1] = b.w + (w[2] * r[0] - w[0] * r[2]);
+    u[2] = c.x + (w[0] * r[1] - w[1] * r[0]);
+  } else {
+    const double X0 = P.X[3 * q], X1 = P.X[3 * q + 1], X2 = P.X[3 * q + 2];
+    const double U0 = P.U[3 * q], U1 = P.U[3 * q + 1], U2 = P.U[3 * q + 2];
+    const double W0 = P.W[3 * q], W1 = P.W[3 * q + 1], W2 = P.W[3 * q + 2];
+    r[0] = (C)minimg((double)x - X0, (double)g.nx, true);
+    r[1] = (C)minimg((double)y - X1, (double)g.ny, true);
+    r[2] = (C)minimg((double)z - X2, (double)g.nz, g.periodic_z != 0);
+    w[0] = (C)W0;
+    w[1] = (C)W1;
+    w[2] = (C)W2;
+    u[0] = (C)U0 + (w[1] * r[2] - w[2] * r[1]);
+    u[1] = (C)U1 + (w[2] * r[0] - w[0] * r[2]);
+    u[2] = (C)U2 + (w[0] * r[1] - w[1] * r[0]);
+  }
 }
 
 // Commit of one round of per-lane (force G, torque T) contributions to the
@@ -441,9 +499,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   const int x = nd.x, y = nd.y, z = nd.z;
   const bool valid = nd.valid;
   const int n = (int)g.ncell;
-  const bool perz = g.periodic_z != 0;
-  const Nbr nb = neighbours(g, x, y, z);
-  const int self = nb.off(0, 0, 0);
+  // Every lane loads: a lane outside the lattice reads the nearest node
+  // (clamped coordinates) and then stores nothing and adds to no sum.
+  const Nbr nb = neighbours(g, x < g.nx ? x : g.nx - 1, y < g.ny ? y : g.ny - 1,
+                            z < g.nz ? z : g.nz - 1);
   // walls exist only on a bounded z axis (WALL): elsewhere the wall terms
   // drop out at compile time
   const bool wallm = WALL && nb.wall_m, wallp = WALL && nb.wall_p;
@@ -453,26 +512,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   cnt = __builtin_amdgcn_readfirstlane(cnt < g.tile_cap ? cnt : g.tile_cap);
   const bool mea = FUSED && cnt > 0;              // uniform over the block
 
-  // byte offsets: of a node (values of this storage, and the owner map)
+  // Addresses: the y and z parts of a node's index are uniform over the
+  // wavefront (one x-row), so they go into each access's base pointer with
+  // the direction; the lanes add only the byte offset of x - 1, x or x + 1.
   constexpr unsigned SB = sizeof(S) == 8 ? 3u : (sizeof(S) == 4 ? 2u : 1u);
-  auto boff = [&](int dx, int dy, int dz, unsigned sh) {
-    return (unsigned)(nb.xs[dx + 1] + (nb.rows[dy + 1] + nb.planes[dz + 1])) << sh;
-  };
-  const unsigned self_b = (unsigned)self << SB;
-  int o = -1;
-  if (valid) o = owner_at(owner, (unsigned)self << 2);
+  auto rowpl = [&](int dy, int dz) { return nb.rows[dy + 1] + nb.planes[dz + 1]; };
+  const unsigned xo[3] = {(unsigned)nb.xs[0] << SB, (unsigned)nb.xs[1] << SB,
+                          (unsigned)nb.xs[2] << SB};
+  const unsigned xw[3] = {(unsigned)nb.xs[0] << 2, (unsigned)nb.xs[1] << 2,
+                          (unsigned)nb.xs[2] << 2};
+  const int o = valid ? owner_at(owner + rowpl(0, 0), xw[1]) : -1;
 
   C f[Q];
-  if (valid) {
-    // one load per direction from a selected index (a branch per direction
-    // would make the compiler wait for memory between the loads), then the
-    // moving-wall term of the links that bounced back
+  {
+    // one load per direction from a selected base and offset (a branch per
+    // direction would make the compiler wait for memory between the
+    // loads), then the moving-wall term of the links that bounced back
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       // (beyond() is uniform over the wavefront, which holds one x-row)
       const bool bw = beyond(-cz(i)) != 0;
-      const S* base = src + (size_t)(bw ? opp(i) : i) * (size_t)n;
-      f[i] = ld_at<S>(base, bw ? self_b : boff(-cx(i), -cy(i), -cz(i), SB));
+      const S* base = src + (size_t)(bw ? opp(i) : i) * (size_t)n +
+                      (bw ? rowpl(0, 0) : rowpl(-cy(i), -cz(i)));
+      f[i] = ld_at<S>(base, bw ? xo[1] : xo[1 - cx(i)]);
     }
     if (wallm || wallp) {
 #pragma unroll
@@ -485,9 +547,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
         }
       }
     }
-  } else {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = Store<S>::shifted ? (C)0 : (C)wgt(i);
   }
 
   // f holds the stored values: f_i itself (FP64) or h_i = f_i - w_i.  The
@@ -518,15 +577,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   C B = (C)0;
   if (o >= 0) {
     kinematics<C>(P, o, x, y, z, g, rp, upy, wp);
-    const int shape = P.shape[o];
-    const double size = P.size[o];
-    double Ro[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) Ro[k] = P.R[9 * o + k];
     if constexpr (Store<S>::shifted) {
-      const C d = sdf32(shape, (float)size, Ro, rp[0], rp[1], rp[2], POLY ? P.poly : nullptr);
+      // rotation, size and shape from the FP32 kinematic record
+      const float4* rec = (const float4*)(P.LR32 + LREC * o);
+      const float4 ra = rec[3], rb = rec[4], rc = rec[5];
+      const float Rf[9] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w, rc.x};
+      const C d = sdf32(__float_as_int(rc.z), rc.y, Rf, rp[0], rp[1], rp[2],
+                        POLY ? P.poly : nullptr);
       B = weight32(d, (float)ph.eps);
     } else {
+      const int shape = P.shape[o];
+      const double size = P.size[o];
+      double Ro[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Ro[k] = P.R[9 * o + k];
       const C d = sdf(shape, size, Ro, rp[0], rp[1], rp[2], POLY ? P.poly : nullptr);
       B = weight(d, ph.eps);
     }
@@ -567,7 +631,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   }
   if (valid) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) st_at<S>(dst + (size_t)i * (size_t)n, self_b, f[i]);
+    for (int i = 0; i < Q; ++i) st_at<S>(dst + (size_t)i * (size_t)n + rowpl(0, 0), xo[1], f[i]);
   }
   if (BAL) {
     // mass and momentum of the collided populations, per block in fixed
@@ -596,27 +660,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   // A the node's own particle (own terms and links to its own nodes), or for
   // a fluid node the largest id owning a neighbour; B the largest other id
   // owning a neighbour; further particles around one node (rare) after the
-  // commit of A and B.  Selects and maxima only, no branches.
+  // commit of A and B.  Selects and extrema only, no branches.
+  // (any negative entry means no owner: the extrema and the comparisons
+  // below take none of them for a particle)
   int nbo[Q];
   nbo[0] = -1;
+  int mx = -1;
+  unsigned mn = ~0u;        // smallest id owning a neighbour (negative: none)
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
-    // (every lane loads: a node outside the lattice reads entry 0, a link
-    // beyond a wall its clamped neighbour, and both are then replaced)
-    const int v = owner_at(owner, valid ? boff(cx(i), cy(i), cz(i), 2) : 0u);
-    nbo[i] = !valid ? -1 : (beyond(cz(i)) ? -2 : v);
+    // (a link beyond a wall reads its clamped neighbour, then replaced)
+    const int v = *(const int*)((const char*)(owner + rowpl(cy(i), cz(i))) + xw[1 + cx(i)]);
+    nbo[i] = beyond(cz(i)) ? -2 : v;
+    mx = max(mx, nbo[i]);
+    mn = min(mn, (unsigned)nbo[i]);
   }
-  int mx = -1;
-#pragma unroll
-  for (int i = 1; i < Q; ++i) mx = max(mx, nbo[i]);
-  const int qa = o >= 0 ? o : mx;
+  const int qa = !valid ? -1 : (o >= 0 ? o : mx);
+  // a particle other than A owns a neighbour: the ids owning neighbours are
+  // not all A (A = mx for a fluid node)
+  const bool two = qa >= 0 && mx >= 0 && (mx != qa || (int)mn != qa);
+  const bool multi = __ballot(two) != 0;          // uniform over the wavefront
   int qb = -1;
-#pragma unroll
-  for (int i = 1; i < Q; ++i) qb = max(qb, nbo[i] != qa ? nbo[i] : -1);
   bool more = false;
+  if (multi) {
 #pragma unroll
-  for (int i = 1; i < Q; ++i) more = more | ((nbo[i] >= 0) & (nbo[i] != qa) & (nbo[i] != qb));
-  const bool multi = __ballot(qb >= 0) != 0;      // uniform over the wavefront
+    for (int i = 1; i < Q; ++i) qb = max(qb, nbo[i] != qa ? nbo[i] : -1);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) more = more | ((nbo[i] >= 0) & (nbo[i] != qa) & (nbo[i] != qb));
+    qb = two ? qb : -1;
+    more = more && two;
+  }
   if (__ballot(qa >= 0) != 0) {                   // else no lane has an entry
   // One pass over the stored values v_i (FP64: minus the rest weight): the
   // link moments of A (and B), and the own terms of S(y), sum_i (c_i - u) v_i
@@ -627,30 +700,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   // The collision conserves mass and moves the momentum to rho v, so
   // m0' = (rho - 1) - v_0 (D - v_0 when shifted) and J' = rho v (to the
   // rounding of the collision).
-  LinkMoments<C> La, Lb;
-  link_zero(La);
-  link_zero(Lb);
+  C vs[Q];
+#pragma unroll
+  for (int i = 1; i < Q; ++i) vs[i] = Store<S>::shifted ? f[i] : f[i] - (C)wgt(i);
   const C v_0 = Store<S>::shifted ? f[0] : f[0] - (C)wgt(0);
   C m0 = (Store<S>::shifted ? D : rho - (C)1) - v_0;
   C j[3] = {rho * v0, rho * v1, rho * v2};
-  const bool walls = wallm || wallp;
+  if (wallm || wallp) {
 #pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    const C vi = Store<S>::shifted ? f[i] : f[i] - (C)wgt(i);
-    if (walls) {
+    for (int i = 1; i < Q; ++i) {
       const int bw = beyond(cz(i));
       if (bw) {
         const double* uw = ph.wall_u[bw - 1];
-        const C bi = vi - (C)(6.0 * wgt(i) * (cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2]));
+        const C bi = vs[i] - (C)(6.0 * wgt(i) * (cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2]));
         m0 -= bi;
         if (cx(i)) j[0] += cx(i) > 0 ? bi : -bi;
         if (cy(i)) j[1] += cy(i) > 0 ? bi : -bi;
         if (cz(i)) j[2] += cz(i) > 0 ? bi : -bi;
       }
     }
-    link_add(La, nbo[i] == qa ? vi : (C)0, i);
-    if (multi) link_add(Lb, nbo[i] == qb ? vi : (C)0, i);
   }
+  const Closure<C> La = pair_closure<C>(vs, nbo, qa);
+  Closure<C> Lb;
+  if (multi) Lb = pair_closure<C>(vs, nbo, qb);
   C Ga[3] = {(C)0, (C)0, (C)0}, Ta[3] = {(C)0, (C)0, (C)0};
   C Gb[3] = {(C)0, (C)0, (C)0}, Tb[3] = {(C)0, (C)0, (C)0};
   if (qa >= 0) {
@@ -745,7 +817,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
           if ((mask >> i) & 1u) {
             int d0, d1, d2;
             dir_of(i, d0, d1, d2);
-            const C sv = Store<S>::ld(dst, i * n + self);
+            const C sv = Store<S>::ld(dst, i * n + nb.off(0, 0, 0));
             const C a = Store<S>::shifted ? sv : sv - (C)(i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
             const C e0 = (C)d0, e1 = (C)d1, e2 = (C)d2;
             Lq.m0 += a;
@@ -762,7 +834,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
         }
         C G[3] = {(C)0, (C)0, (C)0}, T[3] = {(C)0, (C)0, (C)0}, rq[3], uq[3], wq[3];
         kinematics<C>(P, q, x, y, z, g, rq, uq, wq);
-        link_force<C>(Lq, rq, uq, wq, G, T);
+        link_force<C>(closure_of(Lq), rq, uq, wq, G, T);
         const int slot = nq + __builtin_popcountll(bq & ((1ull << lane) - 1ull));
         if (slot < XQ) {
           xqid[nd.wave][slot] = q;

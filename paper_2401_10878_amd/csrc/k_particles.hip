@@ -220,6 +220,20 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
     rec[17] = fs;
     rec[18] = __int_as_float(sh);
     rec[19] = 0.0f;
+    // the lattice pass's kinematic record: centre split into an integer part
+    // and its fraction (exact in FP64, the fraction then rounded to FP32)
+    float* lr = P.LR32 + LREC * ip;
+    for (int k = 0; k < 3; ++k) {
+      const double fl = floor(X[k]);
+      lr[k] = __int_as_float((int)fl);
+      lr[3 + k] = (float)(X[k] - fl);
+      lr[6 + k] = (float)U[k];
+      lr[9 + k] = (float)W[k];
+    }
+    for (int k = 0; k < 9; ++k) lr[12 + k] = (float)R[k];
+    lr[21] = fs;
+    lr[22] = __int_as_float(sh);
+    lr[23] = 0.0f;
   }
 
   // 3. Reach box: axis-aligned half extent of the body plus the largest
