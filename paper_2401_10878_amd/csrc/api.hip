@@ -417,6 +417,8 @@ hlbm_status hlbm_create(const hlbm_params* params, void* stream, hlbm_ctx** out)
     c.ph.a_ext[k] = P.fluid_accel[k];
   }
   c.ph.eps = P.eps_b;
+  c.ph.eps_h32 = (float)(0.5 * P.eps_b);
+  c.ph.eps_q32 = (float)(0.25 / P.eps_b);
   c.ph.delta_c = P.enlarge;
   c.ph.n_c = P.n_c;
   // eq. (5) with both bodies (and walls) of the same material

@@ -110,6 +110,7 @@ struct Phys {
   double a_ext[3];        // uniform fluid acceleration (incl. balance 1)
   int bal_mode;           // 2: the acceleration is Counters::bal_a (device)
   double eps, delta_c;
+  float eps_h32, eps_q32;  // eps / 2 and 1 / (4 eps) in FP32 (coupling weight)
   int n_c;
   double estar;           // effective modulus, eq. (5)
   double restitution, mu_s, mu_k, u_k;

@@ -35,12 +35,13 @@ constexpr int BAL_PARTS = 256;  // first-stage workgroups of the balance sums
 // the shape code (its bits)
 constexpr int SREC = 20;
 // FP32 kinematic record of a particle for the lattice pass (FP32 and
-// binary16 storage), 16-byte aligned: the integer part of the centre (3,
-// int bits) and its fraction (3), U (3), omega (3), the rotation (9), the
-// size and the shape code (its bits), one unused word.  A node's offset
-// from the centre is the integer difference wrapped to the minimum image
-// minus the fraction: one rounding, as for the FP64 offset rounded to FP32.
-constexpr int LREC = 24;
+// binary16 storage), 128 bytes (a record address is a shift of the id): the
+// integer part of the centre (3, int bits) and its fraction (3), U (3),
+// omega (3), the rotation (9), the size and the shape code (its bits), then
+// unused words.  A node's offset from the centre is the integer difference
+// wrapped to the minimum image minus the fraction: one rounding, as for the
+// FP64 offset rounded to FP32.
+constexpr int LREC = 32;
 // owner-map entry: the owning particle's id, or -1 (no owner)
 __device__ inline int owner_id(int v) { return v < 0 ? -1 : v; }
 constexpr int WAVE = 64;
@@ -497,13 +498,13 @@ __device__ inline double sdf_exact(int shape, double size, const double* R,
 }
 
 // The same signed distance in FP32 arithmetic (inputs rounded to FP32, the
-// rotation given in FP64 or already rounded), for conservative screening
-// against thresholds: its error is below 1e-6 (|r|_1 + size) plus a few
-// units in the last place.
+// rotation given in FP64 or already rounded; the hardware square root,
+// within 1 ulp): its error is below 1e-6 (|r|_1 + size) plus a few units in
+// the last place.
 template <typename RT>
 __device__ inline float sdf32(int shape, float size, const RT* R, float r0,
                               float r1, float r2, const PolyDev* poly) {
-  if (shape == 0) return sqrtf(r0 * r0 + r1 * r1 + r2 * r2) - size;
+  if (shape == 0) return __builtin_amdgcn_sqrtf(r0 * r0 + r1 * r1 + r2 * r2) - size;
   if (poly && shape >= POLY0) {
     // exact at every distance (its callers evaluate nodes already known to
     // lie within eps/2 of the body)
@@ -521,7 +522,7 @@ __device__ inline float sdf32(int shape, float size, const RT* R, float r0,
   if (shape == 2) return octa_q<float>(size, fabsf(p0), fabsf(p1), fabsf(p2));
   const float q0 = fabsf(p0) - h, q1 = fabsf(p1) - h, q2 = fabsf(p2) - h;
   const float m0 = fmaxf(q0, 0.0f), m1 = fmaxf(q1, 0.0f), m2 = fmaxf(q2, 0.0f);
-  return sqrtf(m0 * m0 + m1 * m1 + m2 * m2) + fminf(fmaxf(fmaxf(q0, q1), q2), 0.0f);
+  return __builtin_amdgcn_sqrtf(m0 * m0 + m1 * m1 + m2 * m2) + fminf(fmaxf(fmaxf(q0, q1), q2), 0.0f);
 }
 
 // As sdf32, with the rotation already in FP32 and the hardware square root
@@ -648,10 +649,11 @@ __device__ inline double weight(double d, double eps) {
 // angle in revolutions, cos(pi (d + eps/2) / (2 eps)) = cos(2 pi t) with
 // t = (d + eps/2) / (4 eps) in [0, 1/4] (absolute error about 1e-6, below
 // what the FP32 populations resolve of the velocity shift).
-__device__ inline float weight32(float d, float eps) {
-  if (d <= -0.5f * eps) return 1.0f;
-  if (d >= 0.5f * eps) return 0.0f;
-  const float c = __builtin_amdgcn_cosf((d + 0.5f * eps) * (0.25f / eps));
+__device__ inline float weight32(float d, float eps_h, float eps_q) {
+  // eps_h = eps / 2, eps_q = 1 / (4 eps), both rounded to FP32
+  if (d <= -eps_h) return 1.0f;
+  if (d >= eps_h) return 0.0f;
+  const float c = __builtin_amdgcn_cosf((d + eps_h) * eps_q);
   return c * c;
 }
 

@@ -111,6 +111,50 @@ __device__ inline void st_at(S* base, unsigned b, typename Store<S>::C v) {
 __device__ inline int owner_at(const int* owner, unsigned b) {
   return owner_id(*(const int*)((const char*)owner + b));
 }
+// The same accesses as raw buffer operations: a scalar resource over the
+// array from p (no range check is relied on; every offset lies inside the
+// array) and a 32-bit per-lane byte offset, which the hardware adds without
+// vector address arithmetic.  Populations non-temporal, owner entries
+// cached.
+__device__ inline __amdgpu_buffer_rsrc_t rsrc_of(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, -1, 0x00020000);
+}
+constexpr int BUF_NT = 2;
+template <typename S>
+__device__ inline typename Store<S>::C ld_buf(const S* base, unsigned b) {
+  const __amdgpu_buffer_rsrc_t r = rsrc_of(base);
+  if constexpr (sizeof(S) == 2)
+    return __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, b, 0, BUF_NT)));
+  else if constexpr (sizeof(S) == 4)
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, b, 0, BUF_NT));
+  else
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, b, 0, BUF_NT));
+}
+template <typename S>
+__device__ inline void st_buf(S* base, unsigned b, typename Store<S>::C v) {
+  const __amdgpu_buffer_rsrc_t r = rsrc_of(base);
+  if constexpr (sizeof(S) == 2)
+    __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, b, 0, BUF_NT);
+  else if constexpr (sizeof(S) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, b, 0, BUF_NT);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v), r, b, 0, BUF_NT);
+}
+__device__ inline int ld_owner_buf(const int* base, unsigned b) {
+  return (int)__builtin_amdgcn_raw_buffer_load_b32(rsrc_of(base), b, 0, 0);
+}
+// c_i . (a, b, c) from the non-zero components of c_i only (a product with
+// a zero component is not dropped by the compiler: 0 * inf is not 0).  The
+// sum starts from -0, which adds exactly; the direction's components are
+// compile-time constants in the unrolled loops.
+template <typename C>
+__device__ inline C cdot(int i, C a, C b, C c) {
+  C r = (C)-0.0;
+  if (cx(i)) r += cx(i) > 0 ? a : -a;
+  if (cy(i)) r += cy(i) > 0 ? b : -b;
+  if (cz(i)) r += cz(i) > 0 ? c : -c;
+  return r;
+}
 template <typename S>
 __device__ inline double full_f(typename Store<S>::C h, int i) {
   return Store<S>::shifted ? wgt(i) + (double)h : (double)h;
@@ -534,7 +578,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
       const bool bw = beyond(-cz(i)) != 0;
       const S* base = src + (size_t)(bw ? opp(i) : i) * (size_t)n +
                       (bw ? rowpl(0, 0) : rowpl(-cy(i), -cz(i)));
-      f[i] = ld_at<S>(base, bw ? xo[1] : xo[1 - cx(i)]);
+      f[i] = ld_buf<S>(base, bw ? xo[1] : xo[1 - cx(i)]);
     }
     if (wallm || wallp) {
 #pragma unroll
@@ -553,7 +597,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   // collision below is written for both: with D = sum of stored values,
   // rho = D (+1 when shifted), J = sum c_i h_i = sum c_i f_i, and the
   // equilibrium is shifted by the same w_i.
-  C D = 0, J0 = 0, J1 = 0, J2 = 0;
+  // (sums start from -0, which adds exactly)
+  C D = (C)-0.0, J0 = (C)-0.0, J1 = (C)-0.0, J2 = (C)-0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     D += f[i];
@@ -584,7 +629,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
       const float Rf[9] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w, rc.x};
       const C d = sdf32(__float_as_int(rc.z), rc.y, Rf, rp[0], rp[1], rp[2],
                         POLY ? P.poly : nullptr);
-      B = weight32(d, (float)ph.eps);
+      B = weight32(d, ph.eps_h32, ph.eps_q32);
     } else {
       const int shape = P.shape[o];
       const double size = P.size[o];
@@ -621,8 +666,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   f[0] = keep * f[0] + (C)wgt(0) * A;
 #pragma unroll
   for (int i = 1; i < Q; i += 2) {
-    const C cu = (C)cx(i) * u0 + (C)cy(i) * u1 + (C)cz(i) * u2;
-    const C cv = (C)cx(i) * v0 + (C)cy(i) * v1 + (C)cz(i) * v2;
+    const C cu = cdot<C>(i, u0, u1, u2);
+    const C cv = cdot<C>(i, v0, v1, v2);
     const C wi = (C)wgt(i);
     const C even = wi * (A + (C)4.5 * rho * (cv * cv - keep * (cu * cu)));
     const C odd = (C)3 * wi * rho * (cv - keep * cu);
@@ -631,7 +676,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   }
   if (valid) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) st_at<S>(dst + (size_t)i * (size_t)n + rowpl(0, 0), xo[1], f[i]);
+    for (int i = 0; i < Q; ++i) st_buf<S>(dst + (size_t)i * (size_t)n + rowpl(0, 0), xo[1], f[i]);
   }
   if (BAL) {
     // mass and momentum of the collided populations, per block in fixed
@@ -670,7 +715,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     // (a link beyond a wall reads its clamped neighbour, then replaced)
-    const int v = *(const int*)((const char*)(owner + rowpl(cy(i), cz(i))) + xw[1 + cx(i)]);
+    const int v = ld_owner_buf(owner + rowpl(cy(i), cz(i)), xw[1 + cx(i)]);
     nbo[i] = beyond(cz(i)) ? -2 : v;
     mx = max(mx, nbo[i]);
     mn = min(mn, (unsigned)nbo[i]);
@@ -928,7 +973,7 @@ __global__ __launch_bounds__(256) void k_mea(const S* __restrict__ fs,
     const double X0 = P.X[3 * o], X1 = P.X[3 * o + 1], X2 = P.X[3 * o + 2];
     const double U0 = P.U[3 * o], U1 = P.U[3 * o + 1], U2 = P.U[3 * o + 2];
     const double W0 = P.W[3 * o], W1 = P.W[3 * o + 1], W2 = P.W[3 * o + 2];
-    C dD = 0, dJ0 = 0, dJ1 = 0, dJ2 = 0;
+    C dD = (C)-0.0, dJ0 = (C)-0.0, dJ1 = (C)-0.0, dJ2 = (C)-0.0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       const int bw = nb.beyond(-cz(i));

@@ -233,7 +233,7 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
     for (int k = 0; k < 9; ++k) lr[12 + k] = (float)R[k];
     lr[21] = fs;
     lr[22] = __int_as_float(sh);
-    lr[23] = 0.0f;
+    for (int k = 23; k < LREC; ++k) lr[k] = 0.0f;
   }
 
   // 3. Reach box: axis-aligned half extent of the body plus the largest
