@@ -280,8 +280,8 @@ def traffic_summary(outdir, workload_name):
                          bytes_per_launch=int(rd + wr), launches=ln[name],
                          algorithmic_bytes=alg,
                          traffic_over_algorithmic=round((rd + wr) / alg, 4))
-    # the separate momentum-exchange pass (binary16 storage; the initial
-    # state of every precision): measured bytes per launch
+    # the separate momentum-exchange pass (the initial state only):
+    # measured bytes per launch
     for name, fkib in mf.items():
         prec = next((v for k, v in mkind.items() if k in name), None)
         wkib = mw.get(name)
@@ -292,8 +292,7 @@ def traffic_summary(outdir, workload_name):
                                          launches=mn[name])
     d = dict(kernel="k_lattice", workload=workload_name,
              note="HBM bytes per launch of the stream-collide pass (which also sums "
-                  "the momentum exchange for FP64 and FP32 storage; binary16 storage "
-                  "runs the separate pass, listed beside it), from FETCH_SIZE and "
+                  "the momentum exchange of the next step), from FETCH_SIZE and "
                   "WRITE_SIZE scaled by a plain 1 GiB copy",
              kernel_source_sha256_16=lattice_source_hash(),
              commands=["cd /tmp && export TMPDIR=/tmp",
@@ -410,10 +409,8 @@ def main():
             main_res["pairs"] * (6 * p.n_c ** 2 + p.n_c ** 3)
             / (main_res["kernel_ms_per_step"]["treat"] * 1e-3), 1),
         # the lattice pass includes the momentum exchange of the next step
-        # (FP64, FP32); binary16 storage runs it as the separate "mea" pass
         kernel_ms_per_step={k: round(v, 5) for k, v in
-                            main_res["kernel_ms_per_step"].items()
-                            if k != "mea" or args.precision == "fp16s"},
+                            main_res["kernel_ms_per_step"].items() if k != "mea"},
         # the other launch mode of the same workload and precision
         **{("stream_ms_per_step" if graph else "graph_ms_per_step"): round(other_ms, 4)},
         precisions=others,

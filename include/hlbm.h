@@ -212,9 +212,9 @@ hlbm_status hlbm_use_graph(hlbm_ctx *ctx, int on);
    hlbm_step records HIP events on the context stream around each of its
    kernel launches (bookkeeping clear, contact treatment, particle motion +
    tile binning, contact carry-over, coupling map + rough detection,
-   stream-collide lattice pass (with the momentum exchange for FP64 and
-   FP32 storage), and the separate momentum-exchange pass, which runs for
-   binary16 storage only and is zero otherwise) for up to max_steps steps (graphs and the
+   stream-collide lattice pass with the momentum exchange of the next step,
+   and a seventh slot that stays zero: the separate momentum-exchange pass
+   runs only at initialisation) for up to max_steps steps (graphs and the
    overlapped contact treatment are bypassed meanwhile).  hlbm_timing_end
    synchronises and returns the summed milliseconds per kernel in that
    order, kernel_ms[7], and the number of timed steps. */

@@ -189,9 +189,8 @@ hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev, int pre) {
     if ((e = launch_treat(c, c.tab[t], c.side))) return e;
     if ((e = hipEventRecord(c.ev_treat, c.side))) return e;
   }
-  // the lattice pass also sums the momentum exchange of the next step for
-  // FP64 and FP32 storage (the last timing slot stays empty); for binary16
-  // storage the separate pass does, over the populations just stored.
+  // the lattice pass also sums the momentum exchange of the next step (the
+  // last timing slot stays empty).
   // The balance controller's sums feed only the next collision: with
   // PRE_NEXT they run on the side stream, beside the next step's
   // bookkeeping, particle motion and detection, and the next lattice pass
@@ -208,7 +207,6 @@ hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev, int pre) {
     return e;
   }
   if ((e = mark())) return e;
-  if (c.precision == HLBM_FP16S && (e = launch_mea(c, c.fbuf[1 - p]))) return e;
   return mark();
 }
 

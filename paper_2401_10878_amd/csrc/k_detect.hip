@@ -82,13 +82,14 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
   const bool perz = g.periodic_z != 0;
   const long long node = (long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z);
 
-  // The tile's count and candidate ids in one round trip (lane c reads slot
-  // c of the list whatever the count); the loops take candidate c's id with
-  // readlane and its FP32 screening record (centre, rotation) through
-  // scalar loads.
+  // The tile's count and its first SPEC candidate ids in one round trip
+  // (lane c < SPEC reads slot c of the list whatever the count; the rest of
+  // a longer list follows); the loops take candidate c's id with readlane
+  // and its FP32 screening record (centre, rotation) through scalar loads.
+  constexpr int SPEC = 8;
   const int* list = tl.dlist + (size_t)tile * g.tile_cap;
   const int cnt_raw = tl.dcount[tile];
-  const int my_id = lane < g.tile_cap ? list[lane] : 0;
+  int my_id = lane < (g.tile_cap < SPEC ? g.tile_cap : SPEC) ? list[lane] : 0;
   int cnt = __builtin_amdgcn_readfirstlane(cnt_raw);
   cnt = cnt < g.tile_cap ? cnt : g.tile_cap;
   if (cnt == 0) {
@@ -96,6 +97,7 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
     if (valid) owner[node] = -1;
     return;
   }
+  if (cnt > SPEC) my_id = lane < cnt ? list[lane] : 0;   // (uniform)
   const bool have = lane < cnt;
   const int pid = have ? my_id : 0;
   const float fxf = (float)x, fyf = (float)y, fzf = (float)z;

@@ -374,7 +374,8 @@ __device__ inline Closure<C> closure_of(const LinkMoments<C>& m) {
 }
 
 // The closure over the links whose neighbour is owned by particle q
-// (nbo[i] == q), from the opposite pairs: with a_i the masked value and,
+// (nbo[i] == q; ALL: over every link), from the opposite pairs: with a_i
+// the masked value and,
 // per pair (i, opp(i)) of first link c, s = a_i + a_opp(i) and
 // d = a_i - a_opp(i), the pair adds s to m0, c d to m1 and c c^T s to Pi.
 // The three axis pairs carry s1, s2, s3; the two pairs of each coordinate
@@ -383,7 +384,7 @@ __device__ inline Closure<C> closure_of(const LinkMoments<C>& m) {
 // difference to its off-diagonal entry, so that
 //   m0 = s1 + s2 + s3 + Sxy + Sxz + Syz,
 //   Pi_yy + Pi_zz = m0 - s1 + Syz (and cyclically).
-template <typename C>
+template <typename C, bool ALL = false>
 __device__ inline Closure<C> pair_closure(const C* v, const int* nbo, int q) {
   static_assert(cx(1) == 1 && cy(3) == 1 && cz(5) == 1, "axis pairs");
   static_assert(cx(7) == 1 && cy(7) == 1 && cz(7) == 0 && cx(9) == 1 && cy(9) == -1 &&
@@ -397,8 +398,8 @@ __device__ inline Closure<C> pair_closure(const C* v, const int* nbo, int q) {
 #pragma unroll
   for (int k = 1; k <= 9; ++k) {
     const int i = 2 * k - 1;
-    const C a = nbo[i] == q ? v[i] : (C)0;
-    const C b = nbo[i + 1] == q ? v[i + 1] : (C)0;
+    const C a = (ALL || nbo[i] == q) ? v[i] : (C)0;
+    const C b = (ALL || nbo[i + 1] == q) ? v[i + 1] : (C)0;
     sp[k] = a + b;
     dp[k] = a - b;
   }
@@ -498,8 +499,7 @@ __device__ inline void commit_round(int q, const C* G, const C* T, int lid,
 }
 
 // Register budget without spills: FP64 at most 128 VGPRs (four wavefronts
-// per SIMD), FP32 at most 96 (five); binary16, which stores only, at most
-// 64 (eight) for periodic scenes of spheres and cubes, else 96.  POLY: built
+// per SIMD), FP32 and binary16 at most 96 (five).  POLY: built
 // with the polyhedron signed distance (scenes without polyhedra run the
 // form without it, which needs fewer registers).  BAL: with the block sums
 // and device acceleration of the zero-net-flux balance force.  WALL: z
@@ -516,14 +516,13 @@ __device__ inline void commit_round(int q, const C* G, const C* T, int lid,
 // wavefronts reduce them per particle into the block's partial-sum slots
 // (F_p = -sum S, T_p = -sum r x S, fixed order, no atomics).  The
 // storage's rest weights cancel in every S(x), so the pushed values are the
-// stored deviations h_i (FP32) or f_i - w_i (FP64).  Blocks whose candidate
-// list is empty (no particle owns a node within one node of the block), and
-// wavefronts without an owned node or a neighbour of one, skip it.  With
-// binary16 storage the kernel stores only; the momentum exchange is the
-// separate pass over the stored (rounded) values.
+// stored deviations h_i (FP32, binary16: the values as rounded for storage)
+// or f_i - w_i (FP64).  Blocks whose candidate list is empty (no particle
+// owns a node within one node of the block), and wavefronts without an owned
+// node or a neighbour of one, skip it.
 template <typename S, bool POLY, bool BAL, bool WALL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
-    sizeof(S) == 8 ? 4 : (sizeof(S) == 4 || POLY || WALL ? 5 : 8), 8))) void k_lattice(const S* __restrict__ src,
+    sizeof(S) == 8 ? 4 : 5, 8))) void k_lattice(const S* __restrict__ src,
                                                  S* __restrict__ dst,
                                                  const int* __restrict__ owner,
                                                  Particles P, Geom g, Phys ph,
@@ -531,9 +530,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
                                                  double* __restrict__ bal_part,
                                                  Tiles tl) {
   using C = typename Store<S>::C;
-  // the momentum exchange is summed here for FP64 and FP32 storage; binary16
-  // storage leaves it to the separate pass over the stored values
-  constexpr bool FUSED = sizeof(S) != 2;
   __shared__ double red[4][LCAP_MAX][6];
   // queue of the rare further-particle contributions, per wavefront
   constexpr int XQ = 32;
@@ -554,7 +550,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   const int lane = threadIdx.x % WAVE;
   int cnt = tl.lcount[nd.block];
   cnt = __builtin_amdgcn_readfirstlane(cnt < g.tile_cap ? cnt : g.tile_cap);
-  const bool mea = FUSED && cnt > 0;              // uniform over the block
+  const bool mea = cnt > 0;                       // uniform over the block
 
   // Addresses: the y and z parts of a node's index are uniform over the
   // wavefront (one x-row), so they go into each access's base pointer with
@@ -693,7 +689,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     }
     block_sums4s<C>(m, j0, j1, j2, nd, bal_part);
   }
-  if (!FUSED || !mea) return;                     // uniform over the block
+  if (!mea) return;                               // uniform over the block
 
   // ---- momentum exchange of the next step, pushed link by link ----------
   const int* list = tl.llist + nd.block * g.tile_cap;
@@ -744,13 +740,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   // m0' = sum_{i>=1} v_i, J' = sum c_i v_i, W1 = sum c_i b_i, W0 = sum b_i.
   // The collision conserves mass and moves the momentum to rho v, so
   // m0' = (rho - 1) - v_0 (D - v_0 when shifted) and J' = rho v (to the
-  // rounding of the collision).
+  // rounding of the collision); binary16 storage rounds far more, and there
+  // m0' and J' are summed over the rounded values.
+  constexpr bool ROUNDED = sizeof(S) == 2;
   C vs[Q];
 #pragma unroll
-  for (int i = 1; i < Q; ++i) vs[i] = Store<S>::shifted ? f[i] : f[i] - (C)wgt(i);
-  const C v_0 = Store<S>::shifted ? f[0] : f[0] - (C)wgt(0);
-  C m0 = (Store<S>::shifted ? D : rho - (C)1) - v_0;
-  C j[3] = {rho * v0, rho * v1, rho * v2};
+  for (int i = 1; i < Q; ++i)
+    vs[i] = ROUNDED ? Store<S>::as_stored(f[i]) : (Store<S>::shifted ? f[i] : f[i] - (C)wgt(i));
+  C m0, j[3];
+  if constexpr (ROUNDED) {
+    const Closure<C> own = pair_closure<C, true>(vs, nullptr, 0);
+    m0 = own.m0;
+    j[0] = own.m1[0];
+    j[1] = own.m1[1];
+    j[2] = own.m1[2];
+  } else {
+    const C v_0 = Store<S>::shifted ? f[0] : f[0] - (C)wgt(0);
+    m0 = (Store<S>::shifted ? D : rho - (C)1) - v_0;
+    j[0] = rho * v0;
+    j[1] = rho * v1;
+    j[2] = rho * v2;
+  }
   if (wallm || wallp) {
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
@@ -915,7 +925,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
 }
 
 // Momentum exchange, eqs. (16)-(18), over the populations f* of the last
-// collision with the owner map and particle state that collision used.  With
+// collision with the owner map and particle state that collision used, as a
+// pass of its own: the force of the initial state (every later step's comes
+// from the stream-collide pass).  With
 // f_i(x) the value the next streaming brings to x (pull from x - c_i, or the
 // bounce-back value at a wall) and re-indexing the second sum by opp(i),
 //   S(x) = sum_i (c_i - u_p(x)) f_i*(x) + (c_i + u_p(x)) f_opp(i)(x)

@@ -72,6 +72,8 @@ __device__ TileSpan axis_tiles(double c, double e, int n, int nt, int ts,
   return s;
 }
 
+constexpr int UB = 4;   // binning: tiles per lane and round
+
 __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
                                                   double* __restrict__ Fh,
                                                   double* __restrict__ Th,
@@ -269,31 +271,45 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
     const double reach = fmax(0.5 * ph.eps, DETECT + ph.delta_c) +
                          0.5 * sqrt((double)(DX - 1) * (DX - 1) + (DY - 1) * (DY - 1) +
                                     (DZ - 1) * (DZ - 1)) + 0.01;
-    for (int t = lane; t < total; t += WAVE) {
-      const int ix = t % cxn, iy = (t / cxn) % cyn, iz = t / (cxn * cyn);
-      const int tx = sp[0].at(ix), ty = sp[1].at(iy), tz = sp[2].at(iz);
-      const double rc[3] = {minimg(tx * DX + 0.5 * (DX - 1) - X[0], L[0], true),
-                            minimg(ty * DY + 0.5 * (DY - 1) - X[1], L[1], true),
-                            minimg(tz * DZ + 0.5 * (DZ - 1) - X[2], L[2], per[2])};
-      if (shape >= POLY0) {
-        // FP32 with its error bound (as in the detection's screening), the
-        // plane lower bound ending the search beyond reach
-        const float is = 1.0f / (float)size;
-        float pb[3];
-        for (int k = 0; k < 3; ++k)
-          pb[k] = ((float)R[k] * (float)rc[0] + (float)R[3 + k] * (float)rc[1] +
-                   (float)R[6 + k] * (float)rc[2]) * is;
-        const float d = (float)size * poly_sdf<float>(P.poly, shape - POLY0, pb, nullptr,
-                                                      (float)reach * is);
-        const double tol = 1e-3 + 1e-5 * (fabs(rc[0]) + fabs(rc[1]) + fabs(rc[2]) + size);
-        if ((double)d > reach + tol) continue;
-      } else if (sdf(shape, size, R, rc[0], rc[1], rc[2], P.poly) > reach) {
-        continue;
+    // UB tiles per lane and round, their slot atomics in flight together
+    for (int t0 = lane; t0 < total; t0 += UB * WAVE) {
+      long long tile[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int t = t0 + u * WAVE;
+        tile[u] = -1;
+        if (t >= total) continue;
+        const int ix = t % cxn, iy = (t / cxn) % cyn, iz = t / (cxn * cyn);
+        const int tx = sp[0].at(ix), ty = sp[1].at(iy), tz = sp[2].at(iz);
+        const double rc[3] = {minimg(tx * DX + 0.5 * (DX - 1) - X[0], L[0], true),
+                              minimg(ty * DY + 0.5 * (DY - 1) - X[1], L[1], true),
+                              minimg(tz * DZ + 0.5 * (DZ - 1) - X[2], L[2], per[2])};
+        if (shape >= POLY0) {
+          // FP32 with its error bound (as in the detection's screening), the
+          // plane lower bound ending the search beyond reach
+          const float is = 1.0f / (float)size;
+          float pb[3];
+          for (int k = 0; k < 3; ++k)
+            pb[k] = ((float)R[k] * (float)rc[0] + (float)R[3 + k] * (float)rc[1] +
+                     (float)R[6 + k] * (float)rc[2]) * is;
+          const float d = (float)size * poly_sdf<float>(P.poly, shape - POLY0, pb, nullptr,
+                                                        (float)reach * is);
+          const double tol = 1e-3 + 1e-5 * (fabs(rc[0]) + fabs(rc[1]) + fabs(rc[2]) + size);
+          if ((double)d > reach + tol) continue;
+        } else if (sdf(shape, size, R, rc[0], rc[1], rc[2], P.poly) > reach) {
+          continue;
+        }
+        tile[u] = tx + (long long)g.dtx * (ty + (long long)g.dty * tz);
       }
-      const long long tile = tx + (long long)g.dtx * (ty + (long long)g.dty * tz);
-      const int slot = atomicAdd(&tl.dcount[tile], 1);
-      if (slot < g.tile_cap) tl.dlist[tile * g.tile_cap + slot] = ip;
-      else atomicOr(&ctr->tile_overflow, 1);
+      int slot[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) slot[u] = tile[u] >= 0 ? atomicAdd(&tl.dcount[tile[u]], 1) : 0;
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        if (tile[u] < 0) continue;
+        if (slot[u] < g.tile_cap) tl.dlist[tile[u] * g.tile_cap + slot[u]] = ip;
+        else atomicOr(&ctr->tile_overflow, 1);
+      }
     }
   }
   // lattice blocks, with the particle's own enumeration index
@@ -309,17 +325,31 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
       total = g.maxent;
     }
     if (lane == 0) tl.nent[ip] = total;
-    for (int t = lane; t < total; t += WAVE) {
-      const int ix = t % cxn, iy = (t / cxn) % cyn, iz = t / (cxn * cyn);
-      const long long tile = sp[0].at(ix) + (long long)g.ltx * (sp[1].at(iy) + (long long)g.lty * sp[2].at(iz));
-      const int slot = atomicAdd(&tl.lcount[tile], 1);
-      if (slot < g.tile_cap) {
-        tl.llist[tile * g.tile_cap + slot] = ip;
-        tl.lent[tile * g.tile_cap + slot] = t;
-      } else {
-        atomicOr(&ctr->tile_overflow, 1);
-        double* pp = tl.part + ((size_t)ip * g.maxent + t) * 6;
-        for (int m = 0; m < 6; ++m) pp[m] = 0.0;
+    for (int t0 = lane; t0 < total; t0 += UB * WAVE) {
+      long long tile[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int t = t0 + u * WAVE;
+        tile[u] = -1;
+        if (t >= total) continue;
+        const int ix = t % cxn, iy = (t / cxn) % cyn, iz = t / (cxn * cyn);
+        tile[u] = sp[0].at(ix) + (long long)g.ltx * (sp[1].at(iy) + (long long)g.lty * sp[2].at(iz));
+      }
+      int slot[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) slot[u] = tile[u] >= 0 ? atomicAdd(&tl.lcount[tile[u]], 1) : 0;
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        if (tile[u] < 0) continue;
+        const int t = t0 + u * WAVE;
+        if (slot[u] < g.tile_cap) {
+          tl.llist[tile[u] * g.tile_cap + slot[u]] = ip;
+          tl.lent[tile[u] * g.tile_cap + slot[u]] = t;
+        } else {
+          atomicOr(&ctr->tile_overflow, 1);
+          double* pp = tl.part + ((size_t)ip * g.maxent + t) * 6;
+          for (int m = 0; m < 6; ++m) pp[m] = 0.0;
+        }
       }
     }
   }
