@@ -211,11 +211,12 @@ hlbm_status hlbm_use_graph(hlbm_ctx *ctx, int on);
 /* Per-kernel timing of the next steps (measurement, no paper passage):
    hlbm_step records HIP events on the context stream around each of its
    kernel launches (bookkeeping clear, contact treatment, particle motion +
-   tile binning, contact carry-over, coupling map + rough detection,
-   stream-collide lattice pass with the momentum exchange of the next step,
-   and a seventh slot that stays zero: the separate momentum-exchange pass
-   runs only at initialisation) for up to max_steps steps (graphs and the
-   overlapped contact treatment are bypassed meanwhile).  hlbm_timing_end
+   tile binning + contact carry-over, an empty slot, coupling map + rough
+   detection, stream-collide lattice pass with the momentum exchange of the
+   next step, and a seventh slot that stays zero: the separate
+   momentum-exchange pass runs only at initialisation) for up to max_steps
+   steps (graphs and the overlapped contact treatment are bypassed
+   meanwhile).  hlbm_timing_end
    synchronises and returns the summed milliseconds per kernel in that
    order, kernel_ms[7], and the number of timed steps. */
 hlbm_status hlbm_timing_begin(hlbm_ctx *ctx, int max_steps);

@@ -162,8 +162,9 @@ hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev, int pre) {
   if ((e = mark())) return e;
   for (int s = 0; s < c.n_sub; ++s) {
     if (s == 0 && (pre & PRE_DONE)) {
+      // (the tile counts need no clearing here: detection and the lattice
+      // pass reset the counts they read)
       if ((e = hipStreamWaitEvent(c.stream, c.ev_treat, 0))) return e;
-      if ((e = launch_clear_step(c, c.tab[1 - t], CLEAR_TILES, c.stream))) return e;
       if ((e = mark())) return e;
     } else {
       if ((e = launch_clear_step(c, c.tab[1 - t], CLEAR_CONTACT | CLEAR_TILES, c.stream)))
@@ -172,9 +173,10 @@ hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev, int pre) {
       if ((e = launch_treat(c, c.tab[t], c.stream))) return e;
     }
     if ((e = mark())) return e;
-    if ((e = launch_particles(c, s == 0 ? 1 : 2))) return e;
+    // particle motion, tile binning and the contact carry-over in one launch
+    // (the carry-over's timing slot stays empty)
+    if ((e = launch_particles(c, s == 0 ? 1 : 2, &c.tab[t], &c.tab[1 - t]))) return e;
     if ((e = mark())) return e;
-    if ((e = launch_keep(c, c.tab[t], c.tab[1 - t]))) return e;
     if ((e = mark())) return e;
     if ((e = launch_detect(c, c.tab[1 - t]))) return e;
     if ((e = mark())) return e;

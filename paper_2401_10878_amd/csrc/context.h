@@ -48,6 +48,49 @@ struct Counters {
   double bal_b[3], bal_P[3], bal_M, bal_a[3];
 };
 
+// Carry-over of slot s of the pair table `from` into `to` when its record
+// is marked to be kept (an established contact that continues, Sec. 3.3.2):
+// the key is inserted by linear probing and the record's contact state
+// copied; a full table raises pair_overflow.
+__device__ inline void keep_slot(const PairTable& from, const PairTable& to, long long s,
+                                 Counters* ctr) {
+  const uint64_t key = from.keys[s];
+  if (key == EMPTY_KEY) return;
+  const PairRec& r = from.rec[s];
+  if (!r.keep) return;
+  const uint32_t mask = (uint32_t)to.cap - 1u;
+  uint32_t h = pair_hash(key) & mask;
+  for (int probe = 0; probe < to.cap; ++probe) {
+    unsigned long long old = atomicCAS((unsigned long long*)&to.keys[h],
+                                       (unsigned long long)EMPTY_KEY,
+                                       (unsigned long long)key);
+    if (old == EMPTY_KEY || old == key) {
+      PairRec& d = to.rec[h];
+      d.a = r.a;
+      d.b = r.b;
+      d.carried = 1;
+      d.established = r.established;
+      d.age = r.age;
+      d.n_in = r.n_in;
+      d.keep = 0;
+      for (int k = 0; k < 3; ++k) {
+        d.lo[k] = r.lo[k];
+        d.hi[k] = r.hi[k];
+        d.centroid[k] = r.centroid[k];
+        d.normal[k] = r.normal[k];
+        d.force_a[k] = r.force_a[k];
+      }
+      d.damping = r.damping;
+      d.volume = r.volume;
+      d.depth = r.depth;
+      d.fn = r.fn;
+      return;
+    }
+    h = (h + 1u) & mask;
+  }
+  atomicOr(&ctr->pair_overflow, 1);
+}
+
 // Division of 0 <= n < 2^31 by a fixed divisor d >= 1 with one multiply-high
 // and a shift (Granlund and Montgomery, PLDI 1994): with s = ceil(log2 d)
 // and m = floor(2^32 (2^s - d) / d) + 1, n / d = (mulhi(n, m) + n) >> s; the
@@ -231,7 +274,10 @@ constexpr int CLEAR_CONTACT = 1, CLEAR_TILES = 2;
 hipError_t launch_clear_step(Ctx& c, PairTable next, int what, hipStream_t s);
 // move: 0 bin only, 1 gather the hydrodynamic force and move, 2 move with
 // the stored hydrodynamic force (later sub-steps)
-hipError_t launch_particles(Ctx& c, int move);
+// keep_from / keep_to (optional, both or neither): the contact carry-over
+// from one pair table to the next runs in the same launch
+hipError_t launch_particles(Ctx& c, int move, const PairTable* keep_from = nullptr,
+                            const PairTable* keep_to = nullptr);
 hipError_t launch_keep(Ctx& c, PairTable from, PairTable to);
 hipError_t launch_detect(Ctx& c, PairTable to);
 // stream-collide src -> dst with the coupling of the current owner map

@@ -57,41 +57,7 @@ __global__ void k_clear_step(PairTable next, double* Fc, double* Tc, int np,
 __global__ void k_keep(PairTable from, PairTable to, Counters* ctr) {
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= from.cap) return;
-  const uint64_t key = from.keys[s];
-  if (key == EMPTY_KEY) return;
-  const PairRec& r = from.rec[s];
-  if (!r.keep) return;
-  const uint32_t mask = (uint32_t)to.cap - 1u;
-  uint32_t h = pair_hash(key) & mask;
-  for (int probe = 0; probe < to.cap; ++probe) {
-    unsigned long long old = atomicCAS((unsigned long long*)&to.keys[h],
-                                       (unsigned long long)EMPTY_KEY,
-                                       (unsigned long long)key);
-    if (old == EMPTY_KEY || old == key) {
-      PairRec& d = to.rec[h];
-      d.a = r.a;
-      d.b = r.b;
-      d.carried = 1;
-      d.established = r.established;
-      d.age = r.age;
-      d.n_in = r.n_in;
-      d.keep = 0;
-      for (int k = 0; k < 3; ++k) {
-        d.lo[k] = r.lo[k];
-        d.hi[k] = r.hi[k];
-        d.centroid[k] = r.centroid[k];
-        d.normal[k] = r.normal[k];
-        d.force_a[k] = r.force_a[k];
-      }
-      d.damping = r.damping;
-      d.volume = r.volume;
-      d.depth = r.depth;
-      d.fn = r.fn;
-      return;
-    }
-    h = (h + 1u) & mask;
-  }
-  atomicOr(&ctr->pair_overflow, 1);
+  keep_slot(from, to, s, ctr);
 }
 
 struct Body {

@@ -91,6 +91,12 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
   const int cnt_raw = tl.dcount[tile];
   int my_id = lane < (g.tile_cap < SPEC ? g.tile_cap : SPEC) ? list[lane] : 0;
   int cnt = __builtin_amdgcn_readfirstlane(cnt_raw);
+  // this wavefront is the count's only reader: it resets a non-zero count
+  // for the next binning as its last store (a store's completion would
+  // delay the wavefront's next wait for a load)
+  auto reset_count = [&]() {
+    if (lane == 0) tl.dcount[tile] = 0;
+  };
   cnt = cnt < g.tile_cap ? cnt : g.tile_cap;
   if (cnt == 0) {
     // no particle within reach of the tile: fluid, nothing flagged
@@ -198,7 +204,10 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
   if (valid) owner[node] = bp;
 
   // orm: candidates flagged at some node of the tile
-  if (orm == 0) return;
+  if (orm == 0) {
+    reset_count();
+    return;
+  }
   const double fx = (double)x, fy = (double)y, fz = (double)z;
   const double Lx = (double)g.nx, Ly = (double)g.ny, Lz = (double)g.nz;
   const bool wbot = valid && !perz && (fz + 0.5 < DETECT);
@@ -235,6 +244,7 @@ __global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
       if (bt) commit_pair(tab, ctr, pi, -2, bt, pt, img);
     }
   }
+  reset_count();
 }
 
 }  // namespace

@@ -922,6 +922,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     }
   }
   store_block(red, list, ent, cnt, g, tl.part);
+  // every wavefront read the block's count before the barrier in
+  // store_block: reset it for the next binning (a block with a zero count
+  // has nothing to reset)
+  if (threadIdx.x == 0) tl.lcount[nd.block] = 0;
 }
 
 // Momentum exchange, eqs. (16)-(18), over the populations f* of the last

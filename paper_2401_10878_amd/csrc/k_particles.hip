@@ -79,9 +79,17 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
                                                   double* __restrict__ Th,
                                                   double* __restrict__ Fc,
                                                   double* __restrict__ Tc,
-                                                  int move, Tiles tl, Counters* ctr) {
+                                                  int move, Tiles tl, Counters* ctr,
+                                                  PairTable keep_from, PairTable keep_to) {
   const int ip = blockIdx.x;
-  if (ip >= P.n) return;
+  if (ip >= P.n) {
+    // blocks past the particles: the contact carry-over of the pair table,
+    // one slot per thread (independent of this kernel's particle work; the
+    // detection that follows inserts into the same next table)
+    const long long s = (long long)(ip - P.n) * WAVE + threadIdx.x;
+    if (s < keep_from.cap) keep_slot(keep_from, keep_to, s, ctr);
+    return;
+  }
   const int lane = threadIdx.x;
   const bool perz = g.periodic_z != 0;
   const double L[3] = {(double)g.nx, (double)g.ny, (double)g.nz};
@@ -357,10 +365,15 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
 
 }  // namespace
 
-hipError_t launch_particles(Ctx& c, int move) {
-  if (c.np == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_particles, dim3(c.np), dim3(64), 0, c.stream, c.part,
-                     c.g, c.ph, c.Fh, c.Th, c.Fc, c.Tc, move, c.tl, c.counters);
+hipError_t launch_particles(Ctx& c, int move, const PairTable* keep_from,
+                            const PairTable* keep_to) {
+  PairTable none = {nullptr, nullptr, 0};
+  const PairTable from = keep_from ? *keep_from : none;
+  const PairTable to = keep_to ? *keep_to : none;
+  const unsigned kb = (unsigned)((from.cap + WAVE - 1) / WAVE);
+  if (c.np + kb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_particles, dim3(c.np + kb), dim3(64), 0, c.stream, c.part,
+                     c.g, c.ph, c.Fh, c.Th, c.Fc, c.Tc, move, c.tl, c.counters, from, to);
   return hipGetLastError();
 }
 
