@@ -763,6 +763,34 @@ __device__ inline double wave_sum6_scatter_f(const float* v) {
   return n;
 }
 
+// As wave_sum6_scatter_f with the first three levels (sums of eight lanes)
+// in FP32 and the last three in FP64: for per-node contributions that carry
+// FP32 rounding already, at about half the instructions of FP64 levels.
+__device__ inline double wave_sum6_scatter_f3(const float* v) {
+  const int i = threadIdx.x & 15;
+  const bool b3 = (i & 8) != 0, b2 = (i & 4) != 0, b1 = (i & 2) != 0;
+  const float s0 = b3 ? v[0] : v[4], s1 = b3 ? v[1] : v[5];
+  const float s2 = b3 ? v[2] : 0.0f, s3 = b3 ? v[3] : 0.0f;
+  float k0 = b3 ? v[4] : v[0], k1 = b3 ? v[5] : v[1];
+  float k2 = b3 ? 0.0f : v[2], k3 = b3 ? 0.0f : v[3];
+  k0 += dpp_f<0x140>(s0);
+  k1 += dpp_f<0x140>(s1);
+  k2 += dpp_f<0x140>(s2);
+  k3 += dpp_f<0x140>(s3);
+  const float t0 = b2 ? k0 : k2, t1 = b2 ? k1 : k3;
+  float m0 = b2 ? k2 : k0, m1 = b2 ? k3 : k1;
+  m0 += dpp_f<0x141>(t0);
+  m1 += dpp_f<0x141>(t1);
+  const float t = b1 ? m0 : m1;
+  float nf = b1 ? m1 : m0;
+  nf += dpp_f<0x1b>(t);
+  double n = nf;
+  n += dpp_d<0xb1>(n);
+  n += xor16_d(n);
+  n += xor32_d(n);
+  return n;
+}
+
 __device__ inline double wave_min(double v) {
   v = fmin(v, ror_d<8>(v));
   v = fmin(v, ror_d<4>(v));

@@ -499,7 +499,9 @@ __device__ inline void commit_round(int q, const C* G, const C* T, int lid,
 }
 
 // Register budget without spills: FP64 at most 128 VGPRs (four wavefronts
-// per SIMD), FP32 and binary16 at most 96 (five).  POLY: built
+// per SIMD), FP32 and binary16 at most 72 (seven: the pass is faster at
+// seven wavefronts than at six or five), 80 with both the polyhedron
+// distance and the balance sums.  POLY: built
 // with the polyhedron signed distance (scenes without polyhedra run the
 // form without it, which needs fewer registers).  BAL: with the block sums
 // and device acceleration of the zero-net-flux balance force.  WALL: z
@@ -522,7 +524,7 @@ __device__ inline void commit_round(int q, const C* G, const C* T, int lid,
 // node or a neighbour of one, skip it.
 template <typename S, bool POLY, bool BAL, bool WALL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
-    sizeof(S) == 8 ? 4 : 5, 8))) void k_lattice(const S* __restrict__ src,
+    sizeof(S) == 8 ? 4 : (POLY && BAL ? 6 : 7), 8))) void k_lattice(const S* __restrict__ src,
                                                  S* __restrict__ dst,
                                                  const int* __restrict__ owner,
                                                  Particles P, Geom g, Phys ph,
@@ -797,15 +799,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   // one commit for A and B: each distinct particle of the wavefront in
   // turn, the lanes adding the entries that name it (FP64 wave sums into
   // the block's LDS rows, which hold -sum)
+  // (pending entries as wavefront masks, the lane predicates taken from
+  // them without per-lane bookkeeping; B only in wavefronts that have one)
   {
-    bool pa = qa >= 0, pb = qb >= 0;
-    for (;;) {
-      const uint64_t ba = __ballot(pa), bb = __ballot(pb);
-      if ((ba | bb) == 0) break;
-      const int pick = ba ? __builtin_amdgcn_readlane(qa, __ffsll((long long)ba) - 1)
-                          : __builtin_amdgcn_readlane(qb, __ffsll((long long)bb) - 1);
+    uint64_t pa = __ballot(qa >= 0);
+    uint64_t pb = multi ? __ballot(qb >= 0) : 0ull;
+    while ((pa | pb) != 0) {
+      const int pick = pa ? __builtin_amdgcn_readlane(qa, __ffsll((long long)pa) - 1)
+                          : __builtin_amdgcn_readlane(qb, __ffsll((long long)pb) - 1);
       // (A and B name different particles: at most one of ta, tb holds)
-      const bool ta = pa && qa == pick, tb = pb && qb == pick;
+      const uint64_t ma = pa & __ballot(qa == pick);
+      const bool ta = __builtin_amdgcn_inverse_ballot_w64(ma);
+      pa &= ~ma;
+      const uint64_t mb = pb & __ballot(qb == pick);
+      const bool tb = __builtin_amdgcn_inverse_ballot_w64(mb);
+      pb &= ~mb;
       C vv[6];
       for (int k = 0; k < 3; ++k) {
         vv[k] = ta ? -Ga[k] : (tb ? -Gb[k] : (C)0);
@@ -813,7 +821,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
       }
       double sum;
       if constexpr (sizeof(C) == 4)
-        sum = wave_sum6_scatter_f(vv);
+        sum = wave_sum6_scatter_f3(vv);
       else
         sum = wave_sum6_scatter(vv);
       const uint64_t hit = __ballot(lid == pick);
@@ -825,8 +833,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
           atomic_add_f64(&tl.ovf[6 * pick + k], -sum);
         }
       }
-      if (ta) pa = false;
-      if (tb) pb = false;
     }
   }
   }
