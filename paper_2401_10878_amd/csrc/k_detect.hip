@@ -60,7 +60,7 @@ __device__ void commit_pair(PairTable t, Counters* ctr, int a, int b,
 }
 
 template <bool POLY>
-__global__ __launch_bounds__(256) void k_detect(Particles P, Geom g, Phys ph,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(POLY ? 6 : 8, 8))) void k_detect(Particles P, Geom g, Phys ph,
                                                 Tiles tl, int* __restrict__ owner,
                                                 PairTable tab, Counters* ctr) {
   const int lane = threadIdx.x % WAVE;
