@@ -30,6 +30,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+PEAK_FP64_TFLOPS = 78.6        # MI355X dense FP64 vector
+# FP64 operations of one midpoint sample of the contact treatment for a pair
+# of cubes (both bodies; additions, multiplications, divisions and square
+# roots count one each, comparisons and selects none): a face sample takes
+# the sample point (6), per body the offset (3), the rotation into the body
+# frame (15), |p| - h (4), the squared outside part (5), its root (1), the
+# sum with the inside part (1) and the enlargement (1); an integration
+# sample takes the point (9), per body the same 30 plus the gradient
+# (3 divisions, 3 sign products, the rotation back: 15), and the sums of
+# position, gradient difference and depth (10)
+CUBE_FLOP_FACE = 6 + 2 * 30
+CUBE_FLOP_INTEGRATION = 9 + 2 * (30 + 21) + 10
 PREC = {"fp64": 0, "fp32": 1, "fp16s": 2}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16s": "f16-storage/f32-compute"}
 VALUE_BYTES = {0: 8, 1: 4, 2: 2}
@@ -62,6 +74,21 @@ def traffic_for(prec_name, section="per_precision", field="bytes_per_launch",
         return None
     e = d.get(section, {}).get(prec_name)
     return e.get(field) if e else None
+
+
+def contact_roofline(wl, res):
+    """Algorithmic FP64 operations of the contact treatment per second (its
+    event-timed kernel time, the last step's pair count) against the FP64
+    vector peak; None unless every particle is a cube."""
+    if not all(int(s) == 1 for s in wl.scene.shape):
+        return None
+    nc = wl.params.n_c
+    flop = res["pairs"] * (6 * nc ** 2 * CUBE_FLOP_FACE + nc ** 3 * CUBE_FLOP_INTEGRATION)
+    tf = flop / (res["kernel_ms_per_step"]["treat"] * 1e-3) / 1e12
+    return dict(bound="fp64", kernel="k_treat", achieved=round(tf, 3),
+                peak=PEAK_FP64_TFLOPS, unit="TFLOP/s", frac=round(tf / PEAK_FP64_TFLOPS, 4),
+                flop_per_step=int(flop), flop_per_face_sample=CUBE_FLOP_FACE,
+                flop_per_integration_sample=CUBE_FLOP_INTEGRATION)
 
 
 def run_gpu(wl, prec, steps, warmup, graph):
@@ -408,6 +435,10 @@ def main():
         contact_samples_per_s=round(
             main_res["pairs"] * (6 * p.n_c ** 2 + p.n_c ** 3)
             / (main_res["kernel_ms_per_step"]["treat"] * 1e-3), 1),
+        # the contact treatment against the FP64 vector peak (scenes of
+        # cubes only: the FP64 operations per sample are those of a cube
+        # pair, every box face sampled)
+        contact_roofline=contact_roofline(wl, main_res),
         # the lattice pass includes the momentum exchange of the next step,
         # the particle launch the contact carry-over (their own slots stay
         # empty)
