@@ -89,33 +89,14 @@ struct Store<__half> {
   // the value st writes, read back (round to nearest even)
   __device__ static C as_stored(C v) { return __half2float(__float2half_rn(v)); }
 };
-// Non-temporal load / store of the value at byte offset b from the start
-// of a direction's array (a uniform base and a 32-bit offset: one address
-// operation per access).
-template <typename S>
-__device__ inline typename Store<S>::C ld_at(const S* base, unsigned b) {
-  if constexpr (sizeof(S) == 2)
-    return __half2float(__ushort_as_half(
-        __builtin_nontemporal_load((const unsigned short*)((const char*)base + b))));
-  else
-    return __builtin_nontemporal_load((const S*)((const char*)base + b));
-}
-template <typename S>
-__device__ inline void st_at(S* base, unsigned b, typename Store<S>::C v) {
-  if constexpr (sizeof(S) == 2)
-    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v)),
-                                (unsigned short*)((char*)base + b));
-  else
-    __builtin_nontemporal_store((S)v, (S*)((char*)base + b));
-}
 __device__ inline int owner_at(const int* owner, unsigned b) {
   return owner_id(*(const int*)((const char*)owner + b));
 }
-// The same accesses as raw buffer operations: a scalar resource over the
-// array from p (no range check is relied on; every offset lies inside the
-// array) and a 32-bit per-lane byte offset, which the hardware adds without
-// vector address arithmetic.  Populations non-temporal, owner entries
-// cached.
+// Loads and stores at byte offset b of an array as raw buffer operations: a
+// scalar resource over the array from p (no range check is relied on; every
+// offset lies inside the array) and a 32-bit per-lane byte offset, which the
+// hardware adds without vector address arithmetic.  Populations
+// non-temporal, owner entries cached.
 __device__ inline __amdgpu_buffer_rsrc_t rsrc_of(const void* p) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, -1, 0x00020000);
 }
