@@ -322,7 +322,7 @@ hipError_t snapshot_alloc(Ctx& c, Snapshot& s) {
   if ((e = hipMalloc(&s.tiles, c.tile_bytes))) return e;
   if ((e = hipMalloc(&s.psums, c.psum_bytes))) return e;
   for (int k = 0; k < 2; ++k) {
-    if ((e = hipMalloc(&s.keys[k], sizeof(uint64_t) * cap))) return e;
+    if ((e = hipMalloc(&s.keys[k], key_block_bytes((int)cap)))) return e;
     if ((e = hipMalloc(&s.rec[k], sizeof(PairRec) * cap))) return e;
   }
   if ((e = hipMalloc(&s.owner, sizeof(int) * (size_t)c.g.ncell))) return e;
@@ -351,7 +351,7 @@ hipError_t snapshot_copy(Ctx& c, Snapshot& s, int dir) {
   if ((e = cp(s.tiles, c.tile_block, c.tile_bytes))) return e;
   if ((e = cp(s.psums, c.part_sums, c.psum_bytes))) return e;
   for (int k = 0; k < 2; ++k) {
-    if ((e = cp(s.keys[k], c.tab[k].keys, sizeof(uint64_t) * cap))) return e;
+    if ((e = cp(s.keys[k], c.tab[k].keys, key_block_bytes((int)cap)))) return e;
     if ((e = cp(s.rec[k], c.tab[k].rec, sizeof(PairRec) * cap))) return e;
   }
   if ((e = cp(s.owner, c.owner, sizeof(int) * (size_t)c.g.ncell))) return e;
@@ -480,8 +480,9 @@ hlbm_status hlbm_create(const hlbm_params* params, void* stream, hlbm_ctx** out)
               hipMalloc(&c.bal_part, sizeof(double) * 4 * ((size_t)nlt + BAL_PARTS)) == hipSuccess);
   for (int k = 0; k < 2 && okm; ++k) {
     c.tab[k].cap = cap;
-    okm = hipMalloc(&c.tab[k].keys, sizeof(uint64_t) * cap) == hipSuccess &&
+    okm = hipMalloc(&c.tab[k].keys, key_block_bytes(cap)) == hipSuccess &&
           hipMalloc(&c.tab[k].rec, sizeof(PairRec) * cap) == hipSuccess;
+    if (okm) set_table_views(c.tab[k]);
   }
   if (!okm) {
     *out = h;
@@ -500,8 +501,8 @@ hlbm_status hlbm_create(const hlbm_params* params, void* stream, hlbm_ctx** out)
   hipMemsetAsync(c.counters, 0, sizeof(Counters), c.stream);
   hipMemsetAsync(c.owner, 0xff, sizeof(int) * ncell, c.stream);
   for (int k = 0; k < 2; ++k) {
-    hipMemsetAsync(c.tab[k].keys, 0xff, sizeof(uint64_t) * cap, c.stream);
-    hipMemsetAsync(c.tab[k].rec, 0, sizeof(PairRec) * cap, c.stream);
+    hipMemsetAsync(c.tab[k].list, 0, sizeof(int) * ((size_t)cap + 2), c.stream);
+    launch_clear_step(c, c.tab[k], CLEAR_ALL_SLOTS, c.stream);
   }
   if (hipStreamSynchronize(c.stream) != hipSuccess) {
     hlbm_destroy(h);
@@ -1220,7 +1221,7 @@ const char kMagic[8] = {'H', 'L', 'B', 'M', 'S', 'T', 'A', '1'};
 unsigned long long state_bytes(const Ctx& c) {
   const size_t cap = (size_t)c.tab[0].cap;
   return sizeof(StateHeader) + pop_bytes(c) + c.part_bytes + c.tile_bytes +
-         c.psum_bytes + 2 * cap * (sizeof(uint64_t) + sizeof(PairRec)) +
+         c.psum_bytes + 2 * (key_block_bytes((int)cap) + cap * sizeof(PairRec)) +
          sizeof(int) * (size_t)c.g.ncell + sizeof(Counters);
 }
 }  // namespace
@@ -1239,7 +1240,7 @@ hlbm_status hlbm_get_state(hlbm_ctx* h, void* blob, size_t* bytes) {
   StateHeader hd;
   memset(&hd, 0, sizeof hd);
   memcpy(hd.magic, kMagic, 8);
-  hd.version = 1;
+  hd.version = 2;
   hd.precision = c.precision;
   hd.nx = c.g.nx; hd.ny = c.g.ny; hd.nz = c.g.nz;
   hd.np = c.np;
@@ -1252,7 +1253,7 @@ hlbm_status hlbm_get_state(hlbm_ctx* h, void* blob, size_t* bytes) {
   hd.part_bytes = c.part_bytes;
   hd.tile_bytes = c.tile_bytes;
   hd.psum_bytes = c.psum_bytes;
-  hd.tab_bytes = cap * (sizeof(uint64_t) + sizeof(PairRec));
+  hd.tab_bytes = key_block_bytes((int)cap) + cap * sizeof(PairRec);
   hd.owner_bytes = sizeof(int) * (size_t)c.g.ncell;
   char* o = (char*)blob;
   memcpy(o, &hd, sizeof hd);
@@ -1267,7 +1268,7 @@ hlbm_status hlbm_get_state(hlbm_ctx* h, void* blob, size_t* bytes) {
   HIPCHECK(get(c.tile_block, c.tile_bytes));
   HIPCHECK(get(c.part_sums, c.psum_bytes));
   for (int k = 0; k < 2; ++k) {
-    HIPCHECK(get(c.tab[k].keys, sizeof(uint64_t) * cap));
+    HIPCHECK(get(c.tab[k].keys, key_block_bytes((int)cap)));
     HIPCHECK(get(c.tab[k].rec, sizeof(PairRec) * cap));
   }
   HIPCHECK(get(c.owner, sizeof(int) * (size_t)c.g.ncell));
@@ -1286,7 +1287,7 @@ hlbm_status hlbm_set_state(hlbm_ctx* h, const void* blob, size_t bytes) {
   if (bytes < sizeof hd) return fail(c, HLBM_E_ARG, "state blob too short");
   memcpy(&hd, blob, sizeof hd);
   const size_t cap = (size_t)c.tab[0].cap;
-  if (memcmp(hd.magic, kMagic, 8) != 0 || hd.version != 1)
+  if (memcmp(hd.magic, kMagic, 8) != 0 || hd.version != 2)
     return fail(c, HLBM_E_ARG, "not a state blob of this library");
   if (hd.precision != c.precision || hd.nx != c.g.nx || hd.ny != c.g.ny || hd.nz != c.g.nz ||
       hd.np != c.np || hd.cap != (int)cap || hd.n_sub != c.n_sub || hd.part_bytes != c.part_bytes ||
@@ -1310,7 +1311,7 @@ hlbm_status hlbm_set_state(hlbm_ctx* h, const void* blob, size_t bytes) {
   HIPCHECK(put(c.tile_block, c.tile_bytes));
   HIPCHECK(put(c.part_sums, c.psum_bytes));
   for (int k = 0; k < 2; ++k) {
-    HIPCHECK(put(c.tab[k].keys, sizeof(uint64_t) * cap));
+    HIPCHECK(put(c.tab[k].keys, key_block_bytes((int)cap)));
     HIPCHECK(put(c.tab[k].rec, sizeof(PairRec) * cap));
   }
   HIPCHECK(put(c.owner, sizeof(int) * (size_t)c.g.ncell));

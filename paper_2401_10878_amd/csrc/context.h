@@ -29,7 +29,23 @@ struct PairTable {
   uint64_t* keys;   // [cap], EMPTY_KEY when free
   PairRec* rec;     // [cap]
   int cap;          // power of two
+  // the occupied slots in order of insertion (list[0 .. *nlist)), so that
+  // the treatment and the clearing visit only those; both follow the keys
+  // in one allocation (key_block_bytes) and are copied with them
+  int* list;
+  int* nlist;
 };
+inline size_t key_block_bytes(int cap) {
+  return sizeof(uint64_t) * (size_t)cap + sizeof(int) * ((size_t)cap + 2);
+}
+inline void set_table_views(PairTable& t) {
+  t.list = (int*)(t.keys + t.cap);
+  t.nlist = t.list + t.cap;
+}
+// A key inserted into slot h (by the inserting thread only) joins the list.
+__device__ inline void list_slot(const PairTable& t, uint32_t h) {
+  t.list[atomicAdd(t.nlist, 1)] = (int)h;
+}
 
 // Device counters and flags (one small block of device memory).
 struct Counters {
@@ -64,6 +80,7 @@ __device__ inline void keep_slot(const PairTable& from, const PairTable& to, lon
     unsigned long long old = atomicCAS((unsigned long long*)&to.keys[h],
                                        (unsigned long long)EMPTY_KEY,
                                        (unsigned long long)key);
+    if (old == EMPTY_KEY) list_slot(to, h);
     if (old == EMPTY_KEY || old == key) {
       PairRec& d = to.rec[h];
       d.a = r.a;
@@ -271,6 +288,9 @@ struct Ctx {
 // what: CLEAR_CONTACT (next pair table, contact forces and slots, detection
 // counters) and/or CLEAR_TILES (detection-tile and lattice-block counts)
 constexpr int CLEAR_CONTACT = 1, CLEAR_TILES = 2;
+// CLEAR_ALL_SLOTS: every slot of the table (once, after allocation; later
+// clears visit the listed slots only)
+constexpr int CLEAR_ALL_SLOTS = 4;
 hipError_t launch_clear_step(Ctx& c, PairTable next, int what, hipStream_t s);
 // move: 0 bin only, 1 gather the hydrodynamic force and move, 2 move with
 // the stored hydrodynamic force (later sub-steps)

@@ -1,7 +1,8 @@
 // Discrete contact treatment (Sec. 3.3.1, eqs. (4)-(9)) and the per-step
 // bookkeeping of the pair tables.
 //
-// One wavefront treats one contact record:
+// One wavefront treats one contact record (the wavefronts of a fixed grid
+// take the table's occupied slots from its list in a stride):
 //   box      the carried (corrected) box of an established contact, or the
 //            rough box [min - 1/2, max + 1/2] of the flagged node images;
 //            kept in the frame of the lower-id particle a (Sec. 3.3.2)
@@ -23,35 +24,53 @@ namespace hlbm {
 
 namespace {
 
-__global__ void k_clear_step(PairTable next, double* Fc, double* Tc, int np,
-                             int* dcount, long long ndt, int* lcount,
-                             long long nlt, int* ccount, Counters* ctr, int what) {
+__device__ inline void clear_slot(const PairTable& t, long long i) {
+  t.keys[i] = EMPTY_KEY;
+  PairRec r = {};
+  for (int k = 0; k < 3; ++k) {
+    r.rlo[k] = 0x7fffffff;
+    r.rhi[k] = (int)0x80000000;
+  }
+  t.rec[i] = r;
+}
+
+// Tile counts (CLEAR_TILES) and, once after allocation, every slot of a
+// table (CLEAR_ALL_SLOTS), over a grid.
+__global__ void k_clear_step(PairTable next, int* dcount, long long ndt, int* lcount,
+                             long long nlt, int what) {
   const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long stride = (long long)gridDim.x * blockDim.x;
   if (what & CLEAR_TILES) {
     for (long long i = tid; i < ndt; i += stride) dcount[i] = 0;
     for (long long i = tid; i < nlt; i += stride) lcount[i] = 0;
   }
-  if (!(what & CLEAR_CONTACT)) return;
-  for (long long i = tid; i < next.cap; i += stride) {
-    next.keys[i] = EMPTY_KEY;
-    PairRec r = {};
-    for (int k = 0; k < 3; ++k) {
-      r.rlo[k] = 0x7fffffff;
-      r.rhi[k] = (int)0x80000000;
-    }
-    next.rec[i] = r;
-  }
-  for (long long i = tid; i < 3LL * np; i += stride) {
+  if (what & CLEAR_ALL_SLOTS)
+    for (long long i = tid; i < next.cap; i += stride) clear_slot(next, i);
+}
+
+// The next step's contact state (CLEAR_CONTACT), one workgroup: the slots
+// the table's list names, the contact forces and slots, and the detection
+// counters; the list count is reset after the workgroup barrier, when
+// every thread has read it.
+constexpr int CLEAR_THREADS = 1024;
+__global__ __launch_bounds__(CLEAR_THREADS) void k_clear_contact(PairTable next, double* Fc,
+                                                                 double* Tc, int np,
+                                                                 int* ccount, Counters* ctr) {
+  const int tid = (int)threadIdx.x;
+  const int nl = *next.nlist;
+  for (int i = tid; i < nl; i += CLEAR_THREADS) clear_slot(next, next.list[i]);
+  for (long long i = tid; i < 3LL * np; i += CLEAR_THREADS) {
     Fc[i] = 0.0;
     Tc[i] = 0.0;
   }
-  for (long long i = tid; i < np; i += stride) ccount[i] = 0;
+  for (int i = tid; i < np; i += CLEAR_THREADS) ccount[i] = 0;
   if (tid == 0) {
     ctr->det_pairs = 0;
     ctr->det_cells = 0;
     ctr->samples = 0;
   }
+  __syncthreads();
+  if (tid == 0) *next.nlist = 0;
 }
 
 __global__ void k_keep(PairTable from, PairTable to, Counters* ctr) {
@@ -112,12 +131,9 @@ __device__ void add_contact(Tiles tl, Counters* ctr, int p, int other,
 }
 
 template <bool POLY>
-__global__ __launch_bounds__(256) void k_treat(PairTable t, Particles P, Geom g,
-                                               Phys ph, Tiles tl, Counters* ctr) {
+__device__ void treat_slot(const PairTable& t, const Particles& P, const Geom& g,
+                           const Phys& ph, const Tiles& tl, Counters* ctr, int slot) {
   const int lane = threadIdx.x % WAVE;
-  const long long slot = (long long)blockIdx.x * 4 + threadIdx.x / WAVE;
-  if (slot >= t.cap) return;
-  if (t.keys[slot] == EMPTY_KEY) return;
   PairRec* rec = &t.rec[slot];
   const int a = __builtin_amdgcn_readfirstlane(rec->a);
   const int b = __builtin_amdgcn_readfirstlane(rec->b);
@@ -335,19 +351,34 @@ __global__ __launch_bounds__(256) void k_treat(PairTable t, Particles P, Geom g,
   }
 }
 
+
+constexpr int TREAT_BLOCKS = 512;   // 2048 wavefronts
+template <bool POLY>
+__global__ __launch_bounds__(256) void k_treat(PairTable t, Particles P, Geom g,
+                                               Phys ph, Tiles tl, Counters* ctr) {
+  const int n = *t.nlist;
+  const int stride = (int)gridDim.x * 4;
+  for (int i = (int)blockIdx.x * 4 + (int)(threadIdx.x / WAVE); i < n; i += stride)
+    treat_slot<POLY>(t, P, g, ph, tl, ctr, __builtin_amdgcn_readfirstlane(t.list[i]));
+}
+
 }  // namespace
 
 hipError_t launch_clear_step(Ctx& c, PairTable next, int what, hipStream_t s) {
   const long long ndt = (long long)c.g.dtx * c.g.dty * c.g.dtz;
   const long long nlt = (long long)c.g.ltx * c.g.lty * c.g.ltz;
-  long long work = next.cap;
-  if (ndt > work) work = ndt;
-  if (3LL * c.np > work) work = 3LL * c.np;
-  long long blocks = (work + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_clear_step, dim3((unsigned)blocks), dim3(256), 0,
-                     s, next, c.Fc, c.Tc, c.np, c.tl.dcount, ndt,
-                     c.tl.lcount, nlt, c.tl.ccount, c.counters, what);
+  if (what & (CLEAR_TILES | CLEAR_ALL_SLOTS)) {
+    long long work = (what & CLEAR_ALL_SLOTS) ? next.cap : 0;
+    if ((what & CLEAR_TILES) && ndt > work) work = ndt;
+    long long blocks = (work + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_clear_step, dim3((unsigned)blocks), dim3(256), 0, s, next,
+                       c.tl.dcount, ndt, c.tl.lcount, nlt, what);
+  }
+  if (what & CLEAR_CONTACT)
+    hipLaunchKernelGGL(k_clear_contact, dim3(1), dim3(CLEAR_THREADS), 0, s, next, c.Fc,
+                       c.Tc, c.np, c.tl.ccount, c.counters);
   return hipGetLastError();
 }
 
@@ -358,11 +389,12 @@ hipError_t launch_keep(Ctx& c, PairTable from, PairTable to) {
 }
 
 hipError_t launch_treat(Ctx& c, PairTable t, hipStream_t s) {
+  const unsigned nb = (unsigned)((t.cap + 3) / 4 < TREAT_BLOCKS ? (t.cap + 3) / 4 : TREAT_BLOCKS);
   if (c.has_poly)
-    hipLaunchKernelGGL(k_treat<true>, dim3((unsigned)((t.cap + 3) / 4)), dim3(256), 0,
+    hipLaunchKernelGGL(k_treat<true>, dim3(nb), dim3(256), 0,
                      s, t, c.part, c.g, c.ph, c.tl, c.counters);
   else
-    hipLaunchKernelGGL(k_treat<false>, dim3((unsigned)((t.cap + 3) / 4)), dim3(256), 0,
+    hipLaunchKernelGGL(k_treat<false>, dim3(nb), dim3(256), 0,
                      s, t, c.part, c.g, c.ph, c.tl, c.counters);
   return hipGetLastError();
 }

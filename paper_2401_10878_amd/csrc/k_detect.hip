@@ -25,6 +25,7 @@ __device__ int table_slot(PairTable t, uint64_t key, Counters* ctr) {
     unsigned long long old = atomicCAS((unsigned long long*)&t.keys[h],
                                        (unsigned long long)EMPTY_KEY,
                                        (unsigned long long)key);
+    if (old == EMPTY_KEY) list_slot(t, h);
     if (old == EMPTY_KEY || old == key) return (int)h;
     h = (h + 1u) & mask;
   }
@@ -60,7 +61,7 @@ __device__ void commit_pair(PairTable t, Counters* ctr, int a, int b,
 }
 
 template <bool POLY>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(POLY ? 6 : 8, 8))) void k_detect(Particles P, Geom g, Phys ph,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(POLY ? 5 : 8, 8))) void k_detect(Particles P, Geom g, Phys ph,
                                                 Tiles tl, int* __restrict__ owner,
                                                 PairTable tab, Counters* ctr) {
   const int lane = threadIdx.x % WAVE;

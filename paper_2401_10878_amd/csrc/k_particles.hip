@@ -367,7 +367,7 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
 
 hipError_t launch_particles(Ctx& c, int move, const PairTable* keep_from,
                             const PairTable* keep_to) {
-  PairTable none = {nullptr, nullptr, 0};
+  PairTable none = {nullptr, nullptr, 0, nullptr, nullptr};
   const PairTable from = keep_from ? *keep_from : none;
   const PairTable to = keep_to ? *keep_to : none;
   const unsigned kb = (unsigned)((from.cap + WAVE - 1) / WAVE);
