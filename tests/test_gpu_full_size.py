@@ -14,6 +14,7 @@ cores), so every output is compared, not a sample:
     state, and the final population field, within the precision's tolerance
     (forces relative to max(|F_oracle|, (s - 1) V |g|)).
 """
+import dataclasses
 import sys
 
 import numpy as np
@@ -31,13 +32,13 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _oracle_run(O, wl):
+def _oracle_run(O, wl, nsteps=NSTEPS):
     """Initial integer outputs, per-step forces and particles, final field."""
     o = O.OracleSim(wl.params.replace(precision=0), wl.scene)
     o.init_equilibrium()
     ref = dict(owner0=o.fields()["owner"], contacts0=o.contacts(),
                counters0=o.counters(), steps=[])
-    for _ in range(NSTEPS):
+    for _ in range(nsteps):
         o.step(1)
         ref["steps"].append(dict(forces=o.forces(), particles=o.particles(),
                                  contacts=o.contacts(), counters=o.counters()))
@@ -61,6 +62,7 @@ def dense_spheres(O, W):
 
 
 def _check(H, wl, ref, prec):
+    nsteps = len(ref["steps"])
     p = wl.params.replace(precision=prec)
     tol = TOL[prec]
     g = H.Simulation(p, wl.scene)
@@ -73,7 +75,7 @@ def _check(H, wl, ref, prec):
                  4.0 / 3.0 * np.pi * wl.scene.size ** 3)
     Fref = ((wl.scene.density - 1) * V).max() * abs(p.gravity[2])
     Tref = Fref * wl.scene.size.max()
-    for k in range(NSTEPS):
+    for k in range(nsteps):
         g.step(1)
         s = ref["steps"][k]
         eo, eg = s["forces"], g.forces()
@@ -101,7 +103,7 @@ def _check(H, wl, ref, prec):
     # leaves the same bits as the step-by-step run above
     g2 = H.Simulation(p, wl.scene)
     g2.init_equilibrium()
-    g2.step(NSTEPS)
+    g2.step(nsteps)
     assert np.array_equal(g2.populations(), fg)
     p2 = g2.particles()
     for k in pg:
@@ -118,6 +120,30 @@ def test_dense_cube_box_full_size(dense_cubes, H, prec):
 @pytest.mark.parametrize("prec", [0, 2])
 def test_dense_sphere_box_full_size(dense_spheres, H, prec):
     wl, ref = dense_spheres
+    _check(H, wl, ref, prec)
+
+
+TREAT_WAVES = 512 * 4    # wavefronts of the contact-treatment grid
+
+
+@pytest.fixture(scope="module")
+def crowded_cubes(O, W):
+    """The dense cube box with the contact surfaces enlarged by one lattice
+    spacing (enlargement delta_c = 1 of Sec. 3.3.1): about 5500 detected pairs,
+    so every wavefront of the treatment grid takes more than one record of
+    the pair list."""
+    wl = W.c3_dense_cubes()
+    wl = dataclasses.replace(wl, params=wl.params.replace(enlarge=1.0))
+    _say("oracle: dense cube box, delta_c = 1", wl.note)
+    return wl, _oracle_run(O, wl, nsteps=2)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_dense_cube_box_pair_list_longer_than_grid(crowded_cubes, H, prec):
+    wl, ref = crowded_cubes
+    npairs = ref["counters0"][0]
+    _say(f"  detected pairs {npairs} (treatment wavefronts {TREAT_WAVES})")
+    assert npairs > 2 * TREAT_WAVES
     _check(H, wl, ref, prec)
 
 
