@@ -152,6 +152,8 @@ static void cross(const double a[3], const double b[3], double out[3]);
 
 typedef struct {
     int nv, nf, ne;
+    int kind;                   /* 0 polyhedron, 1 ellipsoid */
+    double ax[3];               /* ellipsoid semi-axes (unit scale) */
     double v[ORC_PV][3];
     double n[ORC_PF][3], h[ORC_PF];
     int fs[ORC_PF + 1], fv[ORC_PFV];
@@ -305,6 +307,34 @@ int orc_define_polyhedron(int type, int nv, const double *v, int nf,
     return 0;
 }
 
+/* Ellipsoid type: the solid sum_k (p_k / e_k)^2 <= 1 with semi-axes e along
+   the body axes, scaled uniformly by a particle's size (the smooth convex
+   bodies of Sec. 1; the method needs only the signed distance, Sec. 3.2 and
+   Sec. 3.3.1).  Volume 4 pi e0 e1 e2 / 3; second moment about the centre
+   int p_k^2 dV = V e_k^2 / 5. */
+int orc_define_ellipsoid(int type, double a, double b, double c)
+{
+    if (type < 0 || type >= ORC_MAXPOLY) return poly_fail("type out of range");
+    g_poly_ok[type] = 0;
+    if (!(a > 0.0 && b > 0.0 && c > 0.0) || !isfinite(a) || !isfinite(b) || !isfinite(c))
+        return poly_fail("ellipsoid semi-axes must be positive and finite");
+    orc_poly P;
+    memset(&P, 0, sizeof P);
+    P.kind = 1;
+    P.ax[0] = a;
+    P.ax[1] = b;
+    P.ax[2] = c;
+    P.vol = 4.0 / 3.0 * M_PI * a * b * c;
+    P.J[0] = P.vol * a * a / 5.0;
+    P.J[4] = P.vol * b * b / 5.0;
+    P.J[8] = P.vol * c * c / 5.0;
+    P.rc = a > b ? (a > c ? a : c) : (b > c ? b : c);
+    g_poly[type] = P;
+    g_poly_ok[type] = 1;
+    g_poly_err[0] = 0;
+    return 0;
+}
+
 int orc_poly_info(int type, double *vol, double J[9], double *rc, double *v)
 {
     if (type < 0 || type >= ORC_MAXPOLY || !g_poly_ok[type]) return -1;
@@ -388,6 +418,101 @@ static double poly_sdf_unit(const orc_poly *P, const double p[3], double gb[3])
     return d;
 }
 
+/* Signed distance of the unit-scale ellipsoid with semi-axes e at body
+   point p: the Euclidean distance to the nearest surface point x, negative
+   inside, and the body-frame gradient (the unit outward normal at x).
+   By symmetry p is folded into the positive octant, y_k = |p_k|.  At the
+   nearest point y - x is along the normal (x_k / e_k^2), so x_k = e_k^2 y_k /
+   (t + e_k^2) for a multiplier t that solves
+       G(t) = sum_k (e_k y_k / (t + e_k^2))^2 - 1 = 0
+   (t > 0 outside, t < 0 inside).  With m the smallest e_k^2, G decreases
+   monotonically on t > -m (terms with y_k = 0 vanish) and its root there is
+   the nearest point when some axis with e_k^2 = m has y_k > 0 (G grows
+   without bound towards -m), or when all of those have y_k = 0 and the limit
+   of G at -m is still positive.  Otherwise (a point near the centre, on the
+   plane across the shortest axes) the nearest point has t = -m: the longer
+   axes take x_k = e_k^2 y_k / (e_k^2 - m), the first shortest axis the rest
+   of the unit sum.  The root is bracketed ([-m + e_k y_k or -m, |e y| - m],
+   with G >= 0 and G <= 0 at the ends) and bisected down to adjacent doubles. */
+static double ellipsoid_g(const double e[3], const double e2[3], const double y[3], double t)
+{
+    double g = -1.0;
+    for (int k = 0; k < 3; ++k)
+        if (y[k] > 0.0) {
+            double r = e[k] * y[k] / (t + e2[k]);
+            g += r * r;
+        }
+    return g;
+}
+
+static double ellipsoid_sdf_unit(const double e[3], const double p[3], double gb[3])
+{
+    double y[3], e2[3], x[3], t;
+    for (int k = 0; k < 3; ++k) {
+        y[k] = fabs(p[k]);
+        e2[k] = e[k] * e[k];
+    }
+    double m = e2[0];
+    for (int k = 1; k < 3; ++k)
+        if (e2[k] < m) m = e2[k];
+    int kmin = -1;                 /* first shortest axis with y_k > 0 */
+    for (int k = 0; k < 3; ++k)
+        if (kmin < 0 && e2[k] == m && y[k] > 0.0) kmin = k;
+    int root = 1;
+    if (kmin < 0) {
+        double g = -1.0;
+        for (int k = 0; k < 3; ++k)
+            if (e2[k] > m && y[k] > 0.0) {
+                double r = e[k] * y[k] / (e2[k] - m);
+                g += r * r;
+            }
+        root = g > 0.0;
+    }
+    if (root) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) s += (e[k] * y[k]) * (e[k] * y[k]);
+        double lo = kmin >= 0 ? e[kmin] * y[kmin] - m : -m;
+        double hi = sqrt(s) - m;
+        if (hi < lo) hi = lo;      /* a single term: the root is lo itself */
+        for (int it = 0; it < 2200; ++it) {
+            double tm = 0.5 * (lo + hi);
+            if (tm == lo || tm == hi) break;
+            double g = ellipsoid_g(e, e2, y, tm);
+            if (g > 0.0) lo = tm;
+            else if (g < 0.0) hi = tm;
+            else {
+                lo = tm;
+                hi = tm;
+            }
+        }
+        t = lo;
+        for (int k = 0; k < 3; ++k) x[k] = e2[k] * y[k] / (t + e2[k]);
+    } else {
+        t = -m;
+        double s = 1.0;
+        int kf = -1;
+        for (int k = 0; k < 3; ++k) {
+            if (e2[k] > m) {
+                x[k] = e2[k] * y[k] / (e2[k] - m);
+                s -= (x[k] / e[k]) * (x[k] / e[k]);
+            } else {
+                x[k] = 0.0;
+                if (kf < 0) kf = k;
+            }
+        }
+        x[kf] = e[kf] * sqrt(s > 0.0 ? s : 0.0);
+    }
+    double dx = y[0] - x[0], dy = y[1] - x[1], dz = y[2] - x[2];
+    double d = sqrt((dx * dx + dy * dy) + dz * dz);
+    if (gb) {
+        double n[3];
+        for (int k = 0; k < 3; ++k) n[k] = x[k] / e2[k];
+        double nn = sqrt((n[0] * n[0] + n[1] * n[1]) + n[2] * n[2]);
+        for (int k = 0; k < 3; ++k) gb[k] = (p[k] < 0.0 ? -n[k] : n[k]) / nn;
+    }
+    return t < 0.0 ? -d : d;
+}
+
 /* Exact Euclidean signed distance (negative inside) of a sphere (size =
    radius), cube (size = edge) or regular octahedron (size = centre-to-vertex
    distance) at world offset r from its centre.  The paper maps B from a
@@ -405,7 +530,8 @@ double orc_sdf(int shape, double size, const double R[9], const double r[3],
         double p[3], gb[3];
         for (int k = 0; k < 3; ++k)
             p[k] = (R[0 + k] * r[0] + R[3 + k] * r[1] + R[6 + k] * r[2]) / size;
-        double d = size * poly_sdf_unit(P, p, grad ? gb : NULL);
+        double d = size * (P->kind == 1 ? ellipsoid_sdf_unit(P->ax, p, grad ? gb : NULL)
+                                          : poly_sdf_unit(P, p, grad ? gb : NULL));
         if (grad)
             for (int k = 0; k < 3; ++k)
                 grad[k] = R[3 * k + 0] * gb[0] + R[3 * k + 1] * gb[1] +
@@ -847,15 +973,21 @@ static int axis_nodes(double c, double reach, int n, int periodic, int *out)
 static const double DETECT = 0.8660254037844386; /* sqrt(0.75) */
 
 /* half extent along world axis k of a particle with rotation R: exact for
-   cubes and polyhedra (largest |world coordinate| of a vertex), the
-   circumradius for spheres and octahedra */
+   cubes, polyhedra (largest |world coordinate| of a vertex) and ellipsoids,
+   the circumradius for spheres and octahedra */
 static double half_extent(const orc_particle *pp, const double R[9], int k)
 {
     double e = pp->size;
     if (pp->shape == 1)
         e = 0.5 * pp->size *
             (fabs(R[3 * k]) + fabs(R[3 * k + 1]) + fabs(R[3 * k + 2]));
-    if (pp->shape >= ORC_POLY0) {
+    if (pp->shape >= ORC_POLY0 && g_poly[pp->shape - ORC_POLY0].kind == 1) {
+        /* ellipsoid: max over the surface of a world coordinate,
+           |(R_k0 e0, R_k1 e1, R_k2 e2)| */
+        const double *ax = g_poly[pp->shape - ORC_POLY0].ax;
+        double a0 = R[3 * k] * ax[0], a1 = R[3 * k + 1] * ax[1], a2 = R[3 * k + 2] * ax[2];
+        e = pp->size * sqrt((a0 * a0 + a1 * a1) + a2 * a2);
+    } else if (pp->shape >= ORC_POLY0) {
         const orc_poly *Q = &g_poly[pp->shape - ORC_POLY0];
         e = 0.0;
         for (int i = 0; i < Q->nv; ++i) {
@@ -866,6 +998,17 @@ static double half_extent(const orc_particle *pp, const double R[9], int k)
         e *= pp->size;
     }
     return e;
+}
+
+double orc_half_extent(int shape, double size, const double q[4], int k)
+{
+    orc_particle p;
+    memset(&p, 0, sizeof p);
+    p.shape = shape;
+    p.size = size;
+    double R[9];
+    orc_rotation(q, R);
+    return half_extent(&p, R, k);
 }
 
 static int couple_and_detect_nodes(orc_sim *S)

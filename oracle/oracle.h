@@ -113,6 +113,12 @@ void orc_rotation(const double q[4], double R[9]);
 int orc_define_polyhedron(int type, int nv, const double *v, int nf,
                           const int *fsize, const int *fidx);
 const char *orc_poly_error(void);
+/* Ellipsoid type `type` (same shape codes as the polyhedra): semi-axes a, b,
+   c along the body axes at unit scale, scaled by a particle's size. */
+int orc_define_ellipsoid(int type, double a, double b, double c);
+/* half extent along world axis k of a particle (the node range visited
+   around it) */
+double orc_half_extent(int shape, double size, const double q[4], int k);
 /* unit-scale volume, second moment J = int p p^T dV about the centroid,
    circumradius, and the re-centred vertices (nv x 3) of a defined type */
 int orc_poly_info(int type, double *vol, double J[9], double *rc, double *v);

@@ -107,6 +107,10 @@ def lib():
         L.orc_define_polyhedron.argtypes = [i, i, P(d), i, P(i), P(i)]
         L.orc_define_polyhedron.restype = i
         L.orc_poly_error.restype = C.c_char_p
+        L.orc_define_ellipsoid.argtypes = [i, d, d, d]
+        L.orc_define_ellipsoid.restype = i
+        L.orc_half_extent.argtypes = [i, d, P(d), i]
+        L.orc_half_extent.restype = d
         L.orc_poly_info.argtypes = [i, P(d), P(d), P(d), P(d)]
         L.orc_poly_info.restype = i
         L.orc_poly_angular_accel.argtypes = [i, d, d, P(d), P(d), P(d)]
@@ -327,6 +331,28 @@ def define_polyhedron(ptype, vertices, faces):
                                      _ip(fs), _ip(fi))
     if rc != 0:
         raise ValueError(lib().orc_poly_error().decode())
+
+
+def define_ellipsoid(ptype, axes):
+    """Register ellipsoid type ptype (shape code POLY0 + ptype): semi-axes
+    (a, b, c) along the body axes at unit scale."""
+    a, b, c = (float(x) for x in axes)
+    if lib().orc_define_ellipsoid(int(ptype), a, b, c) != 0:
+        raise ValueError(lib().orc_poly_error().decode())
+
+
+def define_body_type(ptype, body):
+    """Register a polyhedron (vertices, faces) or an ellipsoid (axes)."""
+    if hasattr(body, "axes"):
+        define_ellipsoid(ptype, body.axes)
+    else:
+        define_polyhedron(ptype, body.vertices, body.faces)
+
+
+def half_extent(shape, size, q, k):
+    """Half extent along world axis k of a particle (rotation q)."""
+    qq = np.ascontiguousarray(q, np.float64)
+    return lib().orc_half_extent(int(shape), float(size), _dp(qq), int(k))
 
 
 def polyhedron_info(ptype, nv):

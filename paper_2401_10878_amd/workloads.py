@@ -110,7 +110,7 @@ class Workload:
     scene: Scene
     steps: int
     note: str = ""
-    polyhedra: Optional[dict] = None   # {type k: Polyhedron} for shape POLY0 + k
+    polyhedra: Optional[dict] = None   # {type k: Polyhedron or Ellipsoid} for shape POLY0 + k
     d_equiv: Optional[float] = None    # volume-equivalent sphere diameter (settling boxes)
 
 
@@ -149,6 +149,13 @@ def cube_equiv_diameter(edge: float) -> float:
 class Polyhedron:
     vertices: np.ndarray   # (nv, 3)
     faces: list            # vertex-index lists
+
+
+@dataclasses.dataclass
+class Ellipsoid:
+    """Smooth convex body type: semi-axes (a, b, c) along the body axes at
+    unit scale (registered in the same type slots as the polyhedra)."""
+    axes: tuple
 
 
 def polyhedron_cuboid(a: float, b: float, c: float) -> Polyhedron:
