@@ -67,8 +67,8 @@ typedef enum {
 
 /* Convex bodies with exact signed distances; size is the radius (sphere),
    the edge (cube), the centre-to-vertex distance (regular octahedron), or
-   the scale factor of a convex polyhedron type k defined with
-   hlbm_define_polyhedron (shape HLBM_POLYHEDRON0 + k, k < 8). */
+   the scale factor of a body type k defined with hlbm_define_polyhedron or
+   hlbm_define_ellipsoid (shape HLBM_POLYHEDRON0 + k, k < 8). */
 typedef enum { HLBM_SPHERE = 0, HLBM_CUBE = 1, HLBM_OCTAHEDRON = 2,
                HLBM_POLYHEDRON0 = 3 } hlbm_shape;
 
@@ -160,6 +160,22 @@ hlbm_status hlbm_bind_populations(hlbm_ctx *ctx, void *dev_a, void *dev_b,
 hlbm_status hlbm_define_polyhedron(hlbm_ctx *ctx, int type, int nv,
                                    const double *v, int nf, const int *fsize,
                                    const int *fidx);
+
+/* Define ellipsoid type `type` (0..7, sharing the slots of
+   hlbm_define_polyhedron; particles of shape HLBM_POLYHEDRON0 + type): the
+   solid (x/a)^2 + (y/b)^2 + (z/c)^2 <= 1 with semi-axes a, b, c > 0 along
+   the body axes, scaled uniformly by a particle's size (smooth convex
+   bodies, Sec. 1; the method needs only a signed distance and its gradient,
+   Sec. 3.2 and Sec. 3.3.1).  The signed distance is the exact Euclidean
+   distance to the surface: the nearest point's Lagrange multiplier is
+   bisected to adjacent doubles, so one evaluation costs up to about a
+   hundred FP64 iterations.  Volume 4 pi a b c / 3; eq. (3) with the
+   inertia tensor of the homogeneous solid.  HLBM_E_ARG for a type outside
+   0..7 or a semi-axis that is not positive and finite; call before
+   hlbm_init_particles (HLBM_E_STATE after).  Not supported by the
+   adjoint. */
+hlbm_status hlbm_define_ellipsoid(hlbm_ctx *ctx, int type, double a, double b,
+                                  double c);
 
 /* Upload n particles (host arrays): the state of eqs. (2)-(3), position of
    the centre of mass, orientation, velocity and angular velocity, with

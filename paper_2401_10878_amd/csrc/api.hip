@@ -697,6 +697,36 @@ hlbm_status hlbm_define_polyhedron(hlbm_ctx* h, int type, int nv, const double* 
   return HLBM_OK;
 }
 
+hlbm_status hlbm_define_ellipsoid(hlbm_ctx* h, int type, double a, double b, double cc) {
+  if (!h) return HLBM_E_ARG;
+  Ctx& c = h->c;
+  if (c.particles_ready)
+    return fail(c, HLBM_E_STATE, "define ellipsoids before init_particles");
+  if (type < 0 || type >= MAXPOLY) return fail(c, HLBM_E_ARG, "ellipsoid type must be 0..%d", MAXPOLY - 1);
+  if (!(a > 0.0 && b > 0.0 && cc > 0.0) || !isfinite(a) || !isfinite(b) || !isfinite(cc))
+    return fail(c, HLBM_E_ARG, "ellipsoid semi-axes must be positive and finite");
+  Ctx::PolyHost P;
+  PolyDev& D = P.dev;
+  memset(&D, 0, sizeof D);
+  D.kind = KIND_ELLIPSOID;
+  D.v[0][0] = a;
+  D.v[0][1] = b;
+  D.v[0][2] = cc;
+  for (int k = 0; k < 3; ++k) D.vf[0][k] = (float)D.v[0][k];
+  D.rc = a > b ? (a > cc ? a : cc) : (b > cc ? b : cc);
+  // unit-scale volume and second moment about the centre: V = 4 pi abc / 3,
+  // int p_k^2 dV = V e_k^2 / 5
+  P.vol = 4.0 / 3.0 * PI * a * b * cc;
+  P.J[0] = P.vol * a * a / 5.0;
+  P.J[4] = P.vol * b * b / 5.0;
+  P.J[8] = P.vol * cc * cc / 5.0;
+  P.ok = true;
+  if (!c.poly_dev) HIPCHECK(hipMalloc(&c.poly_dev, sizeof(PolyDev) * MAXPOLY));
+  HIPCHECK(hipMemcpy(c.poly_dev + type, &D, sizeof(PolyDev), hipMemcpyHostToDevice));
+  c.poly_host[type] = P;
+  return HLBM_OK;
+}
+
 hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const double* size,
                                 const double* density, const double* X, const double* q,
                                 const double* U, const double* omega) {
@@ -716,7 +746,7 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
     if (!poly && (shape[i] < 0 || shape[i] > 2))
       return fail(c, HLBM_E_ARG,
                   "particle %d: shape must be 0 (sphere), 1 (cube), 2 (octahedron) or a "
-                  "defined polyhedron type (3 + k)", i);
+                  "defined polyhedron type or ellipsoid type (3 + k)", i);
     if (!(size[i] > 0.0) || !(density[i] > 0.0) || !isfinite(size[i]) || !isfinite(density[i]))
       return fail(c, HLBM_E_ARG, "particle %d: size and density must be positive", i);
     sh[i] = shape[i];
@@ -792,7 +822,12 @@ hlbm_status hlbm_init_particles(hlbm_ctx* h, int n, const int* shape, const doub
   c.part.Iinv = diinv;
   c.part.poly = c.poly_dev;
   c.has_poly = false;
-  for (int i = 0; i < n; ++i) c.has_poly = c.has_poly || sh[i] >= POLY0;
+  c.has_ellipsoid = false;
+  for (int i = 0; i < n; ++i) {
+    c.has_poly = c.has_poly || sh[i] >= POLY0;
+    c.has_ellipsoid = c.has_ellipsoid ||
+                      (sh[i] >= POLY0 && c.poly_host[sh[i] - POLY0].dev.kind == KIND_ELLIPSOID);
+  }
   int* dsh = (int*)d;
   c.part.n = n;
   c.part.shape = dsh; c.part.size = dsz; c.part.dens = dds; c.part.vol = dvol;

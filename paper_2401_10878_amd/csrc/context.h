@@ -256,6 +256,8 @@ struct Ctx {
   } poly_host[MAXPOLY];
   PolyDev* poly_dev = nullptr;
   bool has_poly = false;  // some particle is a polyhedron: kernels with that path
+  bool has_ellipsoid = false;  // some particle is an ellipsoid type: the variants
+                               // that also evaluate smooth bodies
   int tcur;               // tab[tcur] = current contact list
   Counters* counters;     // device
   double* scratch;        // [ncell] FP64 staging for host conversions

@@ -72,11 +72,14 @@ __host__ __device__ constexpr double wgt(int i) {
 // Convex polyhedron type (shape POLY0 + k): vertices re-centred at the
 // solid's centroid, face planes n . p <= h (n, h per face), face vertex
 // lists (fs[f] .. fs[f+1] into fv, counter-clockwise seen from outside),
-// undirected edges, circumradius; all at unit scale.
+// undirected edges, circumradius; all at unit scale.  An ellipsoid type
+// (kind 1) uses the same slot: semi-axes in v[0] (vf[0] rounded), rc the
+// longest, no faces.
 constexpr int POLY0 = 3, MAXPOLY = 8;
 constexpr int PV = 64, PF = 64, PFV = 384, PE = 128;
+constexpr int KIND_POLY = 0, KIND_ELLIPSOID = 1;
 struct PolyDev {
-  int nv, nf, ne, pad;
+  int nv, nf, ne, kind;
   double rc;
   double v[PV][3];
   double pl[PF][4];
@@ -127,14 +130,20 @@ struct Particles {
   const PolyDev* poly;  // [MAXPOLY] polyhedron types
 };
 
-// Half extent along world axis k of a body with rotation R: exact for cubes
-// and polyhedra (largest |world coordinate| of a vertex), the circumradius
-// for spheres and octahedra.
+// Half extent along world axis k of a body with rotation R: exact for
+// cubes, polyhedra (largest |world coordinate| of a vertex) and ellipsoids,
+// the circumradius for spheres and octahedra.
 __device__ inline double half_extent(int shape, double size, const double* R, int k,
                                      const PolyDev* poly) {
   double e = size;
   if (shape == 1) e = 0.5 * size * (fabs(R[3 * k]) + fabs(R[3 * k + 1]) + fabs(R[3 * k + 2]));
-  if (poly && shape >= POLY0) {
+  if (poly && shape >= POLY0 && ((CPoly*)poly + (shape - POLY0))->kind == KIND_ELLIPSOID) {
+    // ellipsoid: the largest world coordinate over the surface,
+    // |(R_k0 e0, R_k1 e1, R_k2 e2)|
+    const HLBM_CONST double* ax = ((CPoly*)poly + (shape - POLY0))->v[0];
+    const double a0 = R[3 * k] * ax[0], a1 = R[3 * k + 1] * ax[1], a2 = R[3 * k + 2] * ax[2];
+    e = size * sqrt((a0 * a0 + a1 * a1) + a2 * a2);
+  } else if (poly && shape >= POLY0) {
     CPoly* pd = (CPoly*)poly + (shape - POLY0);
     e = 0.0;
     for (int i = 0; i < pd->nv; ++i) {
@@ -268,8 +277,161 @@ __device__ inline bool poly_face_contains(CPoly* P, int f, const T* p) {
   return inside;
 }
 
-template <typename T>
+// Signed distance of a unit-scale ellipsoid (semi-axes e) at body point p,
+// negative inside, with the body-frame gradient (unit outward normal at the
+// nearest surface point x), in the oracle's FP64 arithmetic.  Folded into
+// the positive octant (y = |p|), the nearest point is x_k = e_k^2 y_k /
+// (t + e_k^2) where G(t) = sum_k (e_k y_k / (t + e_k^2))^2 - 1 vanishes; G
+// decreases on t > -m (m the smallest e_k^2; terms with y_k = 0 vanish).
+// The root there is the answer when a shortest axis has y_k > 0, or when
+// those components are all zero and G's limit at -m is positive; otherwise
+// t = -m, the longer axes take x_k = e_k^2 y_k / (e_k^2 - m) and the first
+// shortest axis the rest of the unit sum.  The root is bisected from the
+// bracket [e_k y_k - m (or -m), |e y| - m] until the midpoint repeats an
+// end.  With far < inf, a point with |p| - rc > far returns that lower
+// bound with gradient p / |p|.
+// G(t) over the three axes in order (terms with y_k = 0 vanish).
+// (e_k^2 recomputed rather than held: the same rounded value, fewer live
+// registers inside the loop)
+__device__ inline double ellip_g(double e0, double e1, double e2, double y0, double y1,
+                                 double y2, double t) {
+  double g = -1.0;
+  if (y0 > 0.0) {
+    const double r = e0 * y0 / (t + e0 * e0);
+    g += r * r;
+  }
+  if (y1 > 0.0) {
+    const double r = e1 * y1 / (t + e1 * e1);
+    g += r * r;
+  }
+  if (y2 > 0.0) {
+    const double r = e2 * y2 / (t + e2 * e2);
+    g += r * r;
+  }
+  return g;
+}
+
+// (scalars rather than small arrays, so that nothing lands in scratch)
+__device__ inline double ellip_sdf_unit(CPoly* P, const double* p, double* gb, double far) {
+  if (far < 1e300) {
+    const double r = sqrt((p[0] * p[0] + p[1] * p[1]) + p[2] * p[2]);
+    const double lb = r - P->rc;
+    if (lb > far) {
+      if (gb) {
+        gb[0] = p[0] / r;
+        gb[1] = p[1] / r;
+        gb[2] = p[2] / r;
+      }
+      return lb;
+    }
+  }
+  const double e0 = P->v[0][0], e1 = P->v[0][1], e2 = P->v[0][2];
+  const double y0 = fabs(p[0]), y1 = fabs(p[1]), y2 = fabs(p[2]);
+  const double q0 = e0 * e0, q1 = e1 * e1, q2 = e2 * e2;   // e_k^2
+  double m = q0;
+  if (q1 < m) m = q1;
+  if (q2 < m) m = q2;
+  // first shortest axis with y_k > 0
+  const int kmin = (q0 == m && y0 > 0.0) ? 0
+                 : ((q1 == m && y1 > 0.0) ? 1 : ((q2 == m && y2 > 0.0) ? 2 : -1));
+  bool root = true;
+  if (kmin < 0) {
+    double g = -1.0;
+    if (q0 > m && y0 > 0.0) {
+      const double r = e0 * y0 / (q0 - m);
+      g += r * r;
+    }
+    if (q1 > m && y1 > 0.0) {
+      const double r = e1 * y1 / (q1 - m);
+      g += r * r;
+    }
+    if (q2 > m && y2 > 0.0) {
+      const double r = e2 * y2 / (q2 - m);
+      g += r * r;
+    }
+    root = g > 0.0;
+  }
+  double x0, x1, x2, t;
+  if (root) {
+    double s = 0.0;
+    s += (e0 * y0) * (e0 * y0);
+    s += (e1 * y1) * (e1 * y1);
+    s += (e2 * y2) * (e2 * y2);
+    const double ek = kmin == 0 ? e0 : (kmin == 1 ? e1 : e2);
+    const double yk = kmin == 0 ? y0 : (kmin == 1 ? y1 : y2);
+    double lo = kmin >= 0 ? ek * yk - m : -m;
+    double hi = sqrt(s) - m;
+    if (hi < lo) hi = lo;
+#pragma unroll 1
+    for (int it = 0; it < 2200; ++it) {
+      const double tm = 0.5 * (lo + hi);
+      if (tm == lo || tm == hi) break;
+      const double g = ellip_g(e0, e1, e2, y0, y1, y2, tm);
+      if (g > 0.0) lo = tm;
+      else if (g < 0.0) hi = tm;
+      else {
+        lo = tm;
+        hi = tm;
+      }
+    }
+    t = lo;
+    x0 = q0 * y0 / (t + q0);
+    x1 = q1 * y1 / (t + q1);
+    x2 = q2 * y2 / (t + q2);
+  } else {
+    t = -m;
+    double s = 1.0;
+    int kf = -1;
+    x0 = 0.0;
+    x1 = 0.0;
+    x2 = 0.0;
+    if (q0 > m) {
+      x0 = q0 * y0 / (q0 - m);
+      s -= (x0 / e0) * (x0 / e0);
+    } else if (kf < 0) {
+      kf = 0;
+    }
+    if (q1 > m) {
+      x1 = q1 * y1 / (q1 - m);
+      s -= (x1 / e1) * (x1 / e1);
+    } else if (kf < 0) {
+      kf = 1;
+    }
+    if (q2 > m) {
+      x2 = q2 * y2 / (q2 - m);
+      s -= (x2 / e2) * (x2 / e2);
+    } else if (kf < 0) {
+      kf = 2;
+    }
+    const double xf = sqrt(s > 0.0 ? s : 0.0);
+    if (kf == 0) x0 = e0 * xf;
+    if (kf == 1) x1 = e1 * xf;
+    if (kf == 2) x2 = e2 * xf;
+  }
+  const double dx = y0 - x0, dy = y1 - x1, dz = y2 - x2;
+  const double d = sqrt((dx * dx + dy * dy) + dz * dz);
+  if (gb) {
+    const double n0 = x0 / q0, n1 = x1 / q1, n2 = x2 / q2;
+    const double nn = sqrt((n0 * n0 + n1 * n1) + n2 * n2);
+    gb[0] = (p[0] < 0.0 ? -n0 : n0) / nn;
+    gb[1] = (p[1] < 0.0 ? -n1 : n1) / nn;
+    gb[2] = (p[2] < 0.0 ? -n2 : n2) / nn;
+  }
+  return t < 0.0 ? -d : d;
+}
+
+template <typename T, bool ELL = false>
 __device__ inline T poly_sdf_unit(CPoly* P, const T* p, T* gb, T far) {
+  if (ELL && P->kind == KIND_ELLIPSOID) {
+    // smooth body: the exact FP64 distance in every form (rounded to T)
+    const double pd[3] = {(double)p[0], (double)p[1], (double)p[2]};
+    const double fd = far >= (T)1e30 ? 1e300 : (double)far;
+    if (!gb) return (T)ellip_sdf_unit(P, pd, nullptr, fd);
+    double gd[3];
+    const double d = ellip_sdf_unit(P, pd, gd, fd);
+    for (int k = 0; k < 3; ++k) gb[k] = (T)gd[k];
+    return (T)d;
+  }
   const int nf = P->nf;
   T best = (T)-1e30;
   int fm = 0;
@@ -345,12 +507,15 @@ __device__ inline T poly_sdf_unit(CPoly* P, const T* p, T* gb, T far) {
 
 // poly_sdf_unit for polyhedron type t of the table: when every active lane
 // of the wavefront asks for the same type, the table address is uniform.
-template <typename T>
+template <typename T, bool ELL = false>
 __device__ inline T poly_sdf(const PolyDev* table, int t, const T* p, T* gb, T far) {
   CPoly* base = (CPoly*)table;
+  // ellipsoid types first, one evaluation for every lane (a copy in each
+  // branch below would double the inlined code)
+  if (ELL && base[t].kind == KIND_ELLIPSOID) return poly_sdf_unit<T, true>(base + t, p, gb, far);
   const int t0 = __builtin_amdgcn_readfirstlane(t);
-  if (__ballot(t != t0) == 0) return poly_sdf_unit<T>(base + t0, p, gb, far);
-  return poly_sdf_unit<T>(base + t, p, gb, far);
+  if (__ballot(t != t0) == 0) return poly_sdf_unit<T, false>(base + t0, p, gb, far);
+  return poly_sdf_unit<T, false>(base + t, p, gb, far);
 }
 
 // The same distance in the oracle's own arithmetic, for the FP64 decisions
@@ -363,8 +528,10 @@ __device__ inline T poly_sdf(const PolyDev* table, int t, const T* p, T* gb, T f
 // |e|^2), faces first and then edges in table order on ties.  With far <
 // inf, an outside point whose largest plane distance exceeds far returns
 // that lower bound (for the integration's inside test only).
+template <bool ELL = false>
 __device__ inline double poly_sdf_exact_unit(CPoly* P, const double* p, double* gb,
                                              double far) {
+  if (ELL && P->kind == KIND_ELLIPSOID) return ellip_sdf_unit(P, p, gb, far);
   const int nf = P->nf;
   double best = -1e300;
   int fm = 0;
@@ -437,17 +604,19 @@ __device__ inline double poly_sdf_exact_unit(CPoly* P, const double* p, double* 
   }
   return d;
 }
+template <bool ELL = false>
 __device__ inline double poly_sdf_exact(const PolyDev* table, int t, const double* p,
                                         double* gb, double far) {
   CPoly* base = (CPoly*)table;
   const int t0 = __builtin_amdgcn_readfirstlane(t);
-  if (__ballot(t != t0) == 0) return poly_sdf_exact_unit(base + t0, p, gb, far);
-  return poly_sdf_exact_unit(base + t, p, gb, far);
+  if (__ballot(t != t0) == 0) return poly_sdf_exact_unit<ELL>(base + t0, p, gb, far);
+  return poly_sdf_exact_unit<ELL>(base + t, p, gb, far);
 }
 
 // Exact signed distance (negative inside) at world offset r from the centre.
 // sphere: |r| - radius.  cube (edge a): body offset p = R^T r,
 // q_k = |p_k| - a/2, d = |max(q, 0)| + min(max_k q_k, 0).
+template <bool ELL = false>
 __device__ inline double sdf(int shape, double size, const double* R,
                              double r0, double r1, double r2,
                              const PolyDev* poly) {
@@ -457,7 +626,7 @@ __device__ inline double sdf(int shape, double size, const double* R,
     p[0] = (R[0] * r0 + R[3] * r1 + R[6] * r2) * is;
     p[1] = (R[1] * r0 + R[4] * r1 + R[7] * r2) * is;
     p[2] = (R[2] * r0 + R[5] * r1 + R[8] * r2) * is;
-    return size * poly_sdf<double>(poly, shape - POLY0, p, nullptr, 1e300);
+    return size * poly_sdf<double, ELL>(poly, shape - POLY0, p, nullptr, 1e300);
   }
   if (shape == 2) {
     const double p0 = R[0] * r0 + R[3] * r1 + R[6] * r2;
@@ -485,6 +654,7 @@ __device__ inline double sdf(int shape, double size, const double* R,
 // (the body offset divided by the scale, poly_sdf_exact): the forms of the
 // FP64 decisions; the other shapes share sdf / sdf_grad, which already
 // follow it.
+template <bool ELL = false>
 __device__ inline double sdf_exact(int shape, double size, const double* R,
                                    double r0, double r1, double r2, const PolyDev* poly) {
   if (poly && shape >= POLY0) {
@@ -492,16 +662,16 @@ __device__ inline double sdf_exact(int shape, double size, const double* R,
     p[0] = (R[0] * r0 + R[3] * r1 + R[6] * r2) / size;
     p[1] = (R[1] * r0 + R[4] * r1 + R[7] * r2) / size;
     p[2] = (R[2] * r0 + R[5] * r1 + R[8] * r2) / size;
-    return size * poly_sdf_exact(poly, shape - POLY0, p, nullptr, 1e300);
+    return size * poly_sdf_exact<ELL>(poly, shape - POLY0, p, nullptr, 1e300);
   }
-  return sdf(shape, size, R, r0, r1, r2, poly);
+  return sdf<ELL>(shape, size, R, r0, r1, r2, poly);
 }
 
 // The same signed distance in FP32 arithmetic (inputs rounded to FP32, the
 // rotation given in FP64 or already rounded; the hardware square root,
 // within 1 ulp): its error is below 1e-6 (|r|_1 + size) plus a few units in
 // the last place.
-template <typename RT>
+template <bool ELL = false, typename RT>
 __device__ inline float sdf32(int shape, float size, const RT* R, float r0,
                               float r1, float r2, const PolyDev* poly) {
   if (shape == 0) return __builtin_amdgcn_sqrtf(r0 * r0 + r1 * r1 + r2 * r2) - size;
@@ -513,7 +683,7 @@ __device__ inline float sdf32(int shape, float size, const RT* R, float r0,
     p[0] = ((float)R[0] * r0 + (float)R[3] * r1 + (float)R[6] * r2) * is;
     p[1] = ((float)R[1] * r0 + (float)R[4] * r1 + (float)R[7] * r2) * is;
     p[2] = ((float)R[2] * r0 + (float)R[5] * r1 + (float)R[8] * r2) * is;
-    return size * poly_sdf<float>(poly, shape - POLY0, p, nullptr, 1e30f);
+    return size * poly_sdf<float, ELL>(poly, shape - POLY0, p, nullptr, 1e30f);
   }
   const float h = 0.5f * size;
   const float p0 = (float)R[0] * r0 + (float)R[3] * r1 + (float)R[6] * r2;
@@ -529,6 +699,7 @@ __device__ inline float sdf32(int shape, float size, const RT* R, float r0,
 // (within 1 ulp; used for screening against an error bound).  Products and
 // sums may fuse here: a fused multiply-add rounds once, which keeps the
 // error within the same bound.
+template <bool ELL = false>
 __device__ inline float sdf32_r(int shape, float size, const float* R, float r0,
                                 float r1, float r2, const PolyDev* poly, float far) {
 #pragma clang fp contract(fast)
@@ -540,7 +711,7 @@ __device__ inline float sdf32_r(int shape, float size, const float* R, float r0,
     p[0] = (R[0] * r0 + R[3] * r1 + R[6] * r2) * is;
     p[1] = (R[1] * r0 + R[4] * r1 + R[7] * r2) * is;
     p[2] = (R[2] * r0 + R[5] * r1 + R[8] * r2) * is;
-    return size * poly_sdf<float>(poly, shape - POLY0, p, nullptr, far * is);
+    return size * poly_sdf<float, ELL>(poly, shape - POLY0, p, nullptr, far * is);
   }
   const float h = 0.5f * size;
   const float p0 = R[0] * r0 + R[3] * r1 + R[6] * r2;
@@ -558,6 +729,7 @@ __device__ inline float sdf32_r(int shape, float size, const float* R, float r0,
 // at a sphere's centre it is zero.
 // A polyhedron point farther outside than far (cells) may return the largest
 // plane distance, a lower bound, with that face's normal.
+template <bool ELL = false>
 __device__ inline double sdf_grad(int shape, double size, const double* R,
                                   const double* r, double* g, const PolyDev* poly,
                                   double far = 1e300) {
@@ -566,7 +738,7 @@ __device__ inline double sdf_grad(int shape, double size, const double* R,
     double p[3], gb[3];
     #pragma unroll
     for (int k = 0; k < 3; ++k) p[k] = (R[0 + k] * r[0] + R[3 + k] * r[1] + R[6 + k] * r[2]) * is;
-    const double d = size * poly_sdf<double>(poly, shape - POLY0, p, gb, far * is);
+    const double d = size * poly_sdf<double, ELL>(poly, shape - POLY0, p, gb, far * is);
     #pragma unroll
     for (int k = 0; k < 3; ++k)
       g[k] = R[3 * k + 0] * gb[0] + R[3 * k + 1] * gb[1] + R[3 * k + 2] * gb[2];
@@ -621,6 +793,7 @@ __device__ inline double sdf_grad(int shape, double size, const double* R,
   return outside + inside;
 }
 
+template <bool ELL = false>
 __device__ inline double sdf_grad_exact(int shape, double size, const double* R,
                                         const double* r, double* g, const PolyDev* poly,
                                         double far = 1e300) {
@@ -628,13 +801,13 @@ __device__ inline double sdf_grad_exact(int shape, double size, const double* R,
     double p[3], gb[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) p[k] = (R[0 + k] * r[0] + R[3 + k] * r[1] + R[6 + k] * r[2]) / size;
-    const double d = size * poly_sdf_exact(poly, shape - POLY0, p, gb, far / size);
+    const double d = size * poly_sdf_exact<ELL>(poly, shape - POLY0, p, gb, far / size);
 #pragma unroll
     for (int k = 0; k < 3; ++k)
       g[k] = R[3 * k + 0] * gb[0] + R[3 * k + 1] * gb[1] + R[3 * k + 2] * gb[2];
     return d;
   }
-  return sdf_grad(shape, size, R, r, g, poly, far);
+  return sdf_grad<ELL>(shape, size, R, r, g, poly, far);
 }
 
 // Coupling weight B(d): 1 for d <= -eps/2, 0 for d >= eps/2, cos^2 ramp.

@@ -88,18 +88,20 @@ struct Body {
 // With a gradient, a point farther outside a polyhedron than far may return
 // a lower bound of the distance (far = delta: only points inside the
 // enlarged body need the exact value and gradient).
+template <bool ELL>
 __device__ inline double body_sdf(const Body& b, const double* y, double* g,
                                   double far = 1e300) {
   const double r[3] = {y[0] - b.X[0], y[1] - b.X[1], y[2] - b.X[2]};
-  if (g) return sdf_grad_exact(b.shape, b.size, b.R, r, g, b.poly, far);
-  return sdf_exact(b.shape, b.size, b.R, r[0], r[1], r[2], b.poly);
+  if (g) return sdf_grad_exact<ELL>(b.shape, b.size, b.R, r, g, b.poly, far);
+  return sdf_exact<ELL>(b.shape, b.size, b.R, r[0], r[1], r[2], b.poly);
 }
 
 // enlarged distance of member b (particle, or wall -1 bottom / -2 top)
+template <bool ELL>
 __device__ inline double member_sdf(const Body& b, int bid, double delta,
                                     double nz, const double* y, double* g,
                                     double far = 1e300) {
-  if (bid >= 0) return body_sdf(b, y, g, far) - delta;
+  if (bid >= 0) return body_sdf<ELL>(b, y, g, far) - delta;
   if (bid == -1) {
     if (g) { g[0] = 0.0; g[1] = 0.0; g[2] = 1.0; }
     return y[2] + 0.5;
@@ -130,7 +132,7 @@ __device__ void add_contact(Tiles tl, Counters* ctr, int p, int other,
   }
 }
 
-template <bool POLY>
+template <bool POLY, bool ELL>
 __device__ void treat_slot(const PairTable& t, const Particles& P, const Geom& g,
                            const Phys& ph, const Tiles& tl, Counters* ctr, int slot) {
   const int lane = threadIdx.x % WAVE;
@@ -208,8 +210,8 @@ __device__ void treat_slot(const PairTable& t, const Particles& P, const Geom& g
       y[k] = plus ? hi[k] : lo[k];
       y[u] = lo[u] + ((double)j + 0.5) * hu;
       y[v] = lo[v] + ((double)l + 0.5) * hv;
-      const double da = body_sdf(A, y, nullptr) - delta;
-      const double db = member_sdf(Bb, b, delta, L[2], y, nullptr);
+      const double da = body_sdf<ELL>(A, y, nullptr) - delta;
+      const double db = member_sdf<ELL>(Bb, b, delta, L[2], y, nullptr);
       smin = fmin(smin, fmax(da, db));
     }
     smin = wave_min(smin);
@@ -236,8 +238,8 @@ __device__ void treat_slot(const PairTable& t, const Particles& P, const Geom& g
       y[2] = lo[2] + ((double)l + 0.5) * h[2];
       // a sample counts when inside both enlarged bodies: beyond delta
       // outside either, the lower bound decides
-      const double da = body_sdf(A, y, ga, delta) - delta;
-      const double db = member_sdf(Bb, b, delta, L[2], y, gb, delta);
+      const double da = body_sdf<ELL>(A, y, ga, delta) - delta;
+      const double db = member_sdf<ELL>(Bb, b, delta, L[2], y, gb, delta);
       if (fmax(da, db) < 0.0) {
         n_in++;
         dmax = fmax(dmax, -(da + db));
@@ -353,13 +355,13 @@ __device__ void treat_slot(const PairTable& t, const Particles& P, const Geom& g
 
 
 constexpr int TREAT_BLOCKS = 512;   // 2048 wavefronts
-template <bool POLY>
+template <bool POLY, bool ELL = false>
 __global__ __launch_bounds__(256) void k_treat(PairTable t, Particles P, Geom g,
                                                Phys ph, Tiles tl, Counters* ctr) {
   const int n = *t.nlist;
   const int stride = (int)gridDim.x * 4;
   for (int i = (int)blockIdx.x * 4 + (int)(threadIdx.x / WAVE); i < n; i += stride)
-    treat_slot<POLY>(t, P, g, ph, tl, ctr, __builtin_amdgcn_readfirstlane(t.list[i]));
+    treat_slot<POLY, ELL>(t, P, g, ph, tl, ctr, __builtin_amdgcn_readfirstlane(t.list[i]));
 }
 
 }  // namespace
@@ -390,7 +392,10 @@ hipError_t launch_keep(Ctx& c, PairTable from, PairTable to) {
 
 hipError_t launch_treat(Ctx& c, PairTable t, hipStream_t s) {
   const unsigned nb = (unsigned)((t.cap + 3) / 4 < TREAT_BLOCKS ? (t.cap + 3) / 4 : TREAT_BLOCKS);
-  if (c.has_poly)
+  if (c.has_ellipsoid)
+    hipLaunchKernelGGL((k_treat<true, true>), dim3(nb), dim3(256), 0,
+                     s, t, c.part, c.g, c.ph, c.tl, c.counters);
+  else if (c.has_poly)
     hipLaunchKernelGGL(k_treat<true>, dim3(nb), dim3(256), 0,
                      s, t, c.part, c.g, c.ph, c.tl, c.counters);
   else

@@ -60,8 +60,8 @@ __device__ void commit_pair(PairTable t, Counters* ctr, int a, int b,
   }
 }
 
-template <bool POLY>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(POLY ? 5 : 8, 8))) void k_detect(Particles P, Geom g, Phys ph,
+template <bool POLY, bool ELL = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(POLY ? (ELL ? 4 : 5) : 8, 8))) void k_detect(Particles P, Geom g, Phys ph,
                                                 Tiles tl, int* __restrict__ owner,
                                                 PairTable tab, Counters* ctr) {
   const int lane = threadIdx.x % WAVE;
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(POLY ? 5 : 
     const float f1 = minimg_f(fyf - xr[1], Lyf, true);
     const float f2 = minimg_f(fzf - xr[2], Lzf, perz);
     // a polyhedron's plane lower bound beyond both thresholds ends its search
-    const float d = sdf32_r(shape, xr[17], xr + 3, f0, f1, f2, POLY ? P.poly : nullptr,
+    const float d = sdf32_r<ELL>(shape, xr[17], xr + 3, f0, f1, f2, POLY ? P.poly : nullptr,
                             xr[16]);
     const bool may_own = valid & (d < xr[12]), may_det = valid & (d < xr[14]);
     nown += may_own ? 1 : 0;
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(POLY ? 5 : 
         const double r0 = minimg(fx - X0, Lx, true);
         const double r1 = minimg(fy - X1, Ly, true);
         const double r2 = minimg(fz - X2, Lz, perz);
-        const double d = sdf_exact(P.shape[p], P.size[p], R, r0, r1, r2, POLY ? P.poly : nullptr);
+        const double d = sdf_exact<ELL>(P.shape[p], P.size[p], R, r0, r1, r2, POLY ? P.poly : nullptr);
         if (own_open && d < own_t && (d < bd || (d == bd && p < ep))) {
           bd = d;
           ep = p;
@@ -253,7 +253,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(POLY ? 5 : 
 hipError_t launch_detect(Ctx& c, PairTable to) {
   const long long ntiles = (long long)c.g.dtx * c.g.dty * c.g.dtz;
   const unsigned blocks = (unsigned)((ntiles + 3) / 4);
-  if (c.has_poly)
+  if (c.has_ellipsoid)
+    hipLaunchKernelGGL((k_detect<true, true>), dim3(blocks), dim3(256), 0, c.stream, c.part,
+                     c.g, c.ph, c.tl, c.owner, to, c.counters);
+  else if (c.has_poly)
     hipLaunchKernelGGL(k_detect<true>, dim3(blocks), dim3(256), 0, c.stream, c.part,
                      c.g, c.ph, c.tl, c.owner, to, c.counters);
   else

@@ -36,7 +36,7 @@ __global__ void k_coupling_field(const int* __restrict__ owner, Particles P,
                          minimg((double)y - P.X[3 * o + 1], (double)g.ny, true),
                          minimg((double)z - P.X[3 * o + 2], (double)g.nz, g.periodic_z != 0)};
     if (comp < 0) {
-      v = weight(sdf(P.shape[o], P.size[o], P.R + 9 * o, r[0], r[1], r[2], P.poly), ph.eps);
+      v = weight(sdf<true>(P.shape[o], P.size[o], P.R + 9 * o, r[0], r[1], r[2], P.poly), ph.eps);
     } else {
       const double* W = P.W + 3 * o;
       const double wr[3] = {W[1] * r[2] - W[2] * r[1], W[2] * r[0] - W[0] * r[2],

@@ -503,9 +503,9 @@ __device__ inline void commit_round(int q, const C* G, const C* T, int lid,
 // or f_i - w_i (FP64).  Blocks whose candidate list is empty (no particle
 // owns a node within one node of the block), and wavefronts without an owned
 // node or a neighbour of one, skip it.
-template <typename S, bool POLY, bool BAL, bool WALL>
+template <typename S, bool POLY, bool BAL, bool WALL, bool ELL = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
-    sizeof(S) == 8 ? 4 : (POLY && BAL ? 6 : 7), 8))) void k_lattice(const S* __restrict__ src,
+    sizeof(S) == 8 ? 4 : (ELL ? 5 : (POLY && BAL ? 6 : 7)), 8))) void k_lattice(const S* __restrict__ src,
                                                  S* __restrict__ dst,
                                                  const int* __restrict__ owner,
                                                  Particles P, Geom g, Phys ph,
@@ -606,7 +606,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
       const float4* rec = (const float4*)(P.LR32 + LREC * o);
       const float4 ra = rec[3], rb = rec[4], rc = rec[5];
       const float Rf[9] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w, rc.x};
-      const C d = sdf32(__float_as_int(rc.z), rc.y, Rf, rp[0], rp[1], rp[2],
+      const C d = sdf32<ELL>(__float_as_int(rc.z), rc.y, Rf, rp[0], rp[1], rp[2],
                         POLY ? P.poly : nullptr);
       B = weight32(d, ph.eps_h32, ph.eps_q32);
     } else {
@@ -615,7 +615,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
       double Ro[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) Ro[k] = P.R[9 * o + k];
-      const C d = sdf(shape, size, Ro, rp[0], rp[1], rp[2], POLY ? P.poly : nullptr);
+      const C d = sdf<ELL>(shape, size, Ro, rp[0], rp[1], rp[2], POLY ? P.poly : nullptr);
       B = weight(d, ph.eps);
     }
   }
@@ -1151,7 +1151,11 @@ static unsigned tile_blocks(const Geom& g) {
 template <typename S>
 static void run_lattice(Ctx& c, const void* src, void* dst) {
   const bool bal = c.ph.bal_mode == 2, wall = c.g.periodic_z == 0;
-  auto k = c.has_poly
+  auto k = c.has_ellipsoid
+               ? (bal ? k_lattice<S, true, true, false, true>
+                      : (wall ? k_lattice<S, true, false, true, true>
+                              : k_lattice<S, true, false, false, true>))
+           : c.has_poly
                ? (bal ? k_lattice<S, true, true, false>
                       : (wall ? k_lattice<S, true, false, true> : k_lattice<S, true, false, false>))
                : (bal ? k_lattice<S, false, true, false>

@@ -300,8 +300,14 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
           for (int k = 0; k < 3; ++k)
             pb[k] = ((float)R[k] * (float)rc[0] + (float)R[3 + k] * (float)rc[1] +
                      (float)R[6 + k] * (float)rc[2]) * is;
-          const float d = (float)size * poly_sdf<float>(P.poly, shape - POLY0, pb, nullptr,
-                                                        (float)reach * is);
+          // (an ellipsoid type: the circumsphere lower bound |p| - rc)
+          const CPoly* pt = (CPoly*)P.poly + (shape - POLY0);
+          const float d =
+              pt->kind == KIND_ELLIPSOID
+                  ? (float)size * (sqrtf((pb[0] * pb[0] + pb[1] * pb[1]) + pb[2] * pb[2]) -
+                                   (float)pt->rc)
+                  : (float)size * poly_sdf<float>(P.poly, shape - POLY0, pb, nullptr,
+                                                  (float)reach * is);
           const double tol = 1e-3 + 1e-5 * (fabs(rc[0]) + fabs(rc[1]) + fabs(rc[2]) + size);
           if ((double)d > reach + tol) continue;
         } else if (sdf(shape, size, R, rc[0], rc[1], rc[2], P.poly) > reach) {

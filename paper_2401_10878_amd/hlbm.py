@@ -88,6 +88,7 @@ def load():
     L.hlbm_bind_populations.argtypes = [v, v, v, C.c_size_t]
     L.hlbm_init_particles.argtypes = [v, i, P(i), P(d), P(d), P(d), P(d), P(d), P(d)]
     L.hlbm_define_polyhedron.argtypes = [v, i, i, P(d), i, P(i), P(i)]
+    L.hlbm_define_ellipsoid.argtypes = [v, i, d, d, d]
     L.hlbm_init_fluid_equilibrium.argtypes = [v, d, P(d)]
     L.hlbm_set_populations.argtypes = [v, P(d)]
     L.hlbm_step.argtypes = [v, i]
@@ -151,7 +152,8 @@ class Simulation:
     """One coupled HLBM + contact simulation on one GPU.
 
     params: workloads.Params; scene: workloads.Scene; polyhedra: optional
-    {type k: workloads.Polyhedron} for particles of shape POLY0 + k.  The two
+    {type k: workloads.Polyhedron or workloads.Ellipsoid} for particles of
+    shape POLY0 + k.  The two
     population buffers are torch device tensors lent to the library; the
     library runs on a dedicated torch stream (default priority).
     """
@@ -183,6 +185,10 @@ class Simulation:
             self.h, C.c_void_p(self.fa.data_ptr()), C.c_void_p(self.fb.data_ptr()),
             nbytes))
         for k, poly in (polyhedra or {}).items():
+            if hasattr(poly, "axes"):
+                a, b, c = (float(x) for x in poly.axes)
+                self._check(self.L.hlbm_define_ellipsoid(self.h, int(k), a, b, c))
+                continue
             v = np.ascontiguousarray(poly.vertices, np.float64).reshape(-1)
             fs = np.array([len(f) for f in poly.faces], np.int32)
             fi = np.array([j for f in poly.faces for j in f], np.int32)
