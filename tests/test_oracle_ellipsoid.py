@@ -22,7 +22,8 @@ import pytest
 from scipy.optimize import minimize
 
 T_E = 6          # type slots used here (the polyhedron tests use 0..4, 7)
-AXES = [(1.0, 0.6, 0.35), (2.0, 1.0, 1.0), (0.5, 0.5, 1.2), (0.8, 1.3, 0.8)]
+AXES = [(1.0, 0.6, 0.35), (2.0, 1.0, 1.0), (0.5, 0.5, 1.2), (0.8, 1.3, 0.8),
+        (1.0, 1.0, 0.5)]
 IDENT = np.array([1.0, 0.0, 0.0, 0.0])
 
 
