@@ -17,7 +17,7 @@ Prints ONE JSON line with the metric, the roofline of the dominant kernel
 bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--precision fp32|fp64|fp16s]
-                    [--workload C1|C2|C3|C3B|C4|C5] [--stream]
+                    [--workload C1|C2|C3|C3B|C3E|C4|C5] [--stream]
 """
 import argparse
 import hashlib
@@ -165,10 +165,14 @@ def reference_force(wl):
                  np.where(sc.shape == 2, 4.0 / 3.0, 1.0) * sc.size ** 3)
     for k, P in (wl.polyhedra or {}).items():
         # a normalising scale only: the volume of the polyhedron by the
-        # divergence theorem over its faces, fanned into triangles
-        v = P.vertices
-        vol = sum(np.dot(v[f[0]], np.cross(v[f[j]], v[f[j + 1]]))
-                  for f in P.faces for j in range(1, len(f) - 1)) / 6.0
+        # divergence theorem over its faces, fanned into triangles (of an
+        # ellipsoid type, 4 pi abc / 3)
+        if hasattr(P, "axes"):
+            vol = 4.0 / 3.0 * np.pi * float(np.prod(P.axes))
+        else:
+            v = P.vertices
+            vol = sum(np.dot(v[f[0]], np.cross(v[f[j]], v[f[j + 1]]))
+                      for f in P.faces for j in range(1, len(f) - 1)) / 6.0
         m = sc.shape == W_POLY0 + k
         V[m] = vol * sc.size[m] ** 3
     return ((sc.density - 1.0) * V).max() * g
@@ -215,7 +219,7 @@ def cpu_baseline(wl, steps):
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
     for k, P in (wl.polyhedra or {}).items():
-        O.define_polyhedron(k, P.vertices, P.faces)
+        O.define_body_type(k, P)
     s = O.OracleSim(wl.params, wl.scene)
     s.init_equilibrium()
     # one step per call, so that the flagged contact cells of each step can
@@ -351,7 +355,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", default="fp32", choices=sorted(PREC))
-    ap.add_argument("--workload", default="C3", choices=["C1", "C2", "C3", "C3B", "C4", "C5"])
+    ap.add_argument("--workload", default="C3", choices=["C1", "C2", "C3", "C3B", "C3E", "C4", "C5"])
     ap.add_argument("--stream", action="store_true",
                     help="time stream launches instead of captured HIP graphs")
     ap.add_argument("--other-precisions", type=int, default=1,

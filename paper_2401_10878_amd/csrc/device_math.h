@@ -420,15 +420,137 @@ __device__ inline double ellip_sdf_unit(CPoly* P, const double* p, double* gb, d
   return t < 0.0 ? -d : d;
 }
 
+// The same distance for the forms that need its value, not the oracle's
+// bits (the lattice pass's coupling weight, the detection screen, the
+// fields): the multiplier by Newton's method instead of bisection.  G is
+// convex and decreasing on t > -m, so Newton steps from the bracket's lower
+// end (G >= 0) rise monotonically to the root (each lands at or left of
+// it) and stop when a step no longer changes t; the free branch is the
+// exact form's.  A few steps against up to a hundred halvings, so a
+// wavefront with one band node in it does not wait for the bisection.
+__device__ inline double ellip_sdf_newton(CPoly* P, const double* p, double* gb, double far) {
+  if (far < 1e300) {
+    const double r = sqrt((p[0] * p[0] + p[1] * p[1]) + p[2] * p[2]);
+    const double lb = r - P->rc;
+    if (lb > far) {
+      if (gb) {
+        gb[0] = p[0] / r;
+        gb[1] = p[1] / r;
+        gb[2] = p[2] / r;
+      }
+      return lb;
+    }
+  }
+  const double e0 = P->v[0][0], e1 = P->v[0][1], e2 = P->v[0][2];
+  const double y0 = fabs(p[0]), y1 = fabs(p[1]), y2 = fabs(p[2]);
+  const double q0 = e0 * e0, q1 = e1 * e1, q2 = e2 * e2;
+  double m = q0;
+  if (q1 < m) m = q1;
+  if (q2 < m) m = q2;
+  const int kmin = (q0 == m && y0 > 0.0) ? 0
+                 : ((q1 == m && y1 > 0.0) ? 1 : ((q2 == m && y2 > 0.0) ? 2 : -1));
+  bool root = true;
+  if (kmin < 0) {
+    double g = -1.0;
+    if (q0 > m && y0 > 0.0) g += (e0 * y0 / (q0 - m)) * (e0 * y0 / (q0 - m));
+    if (q1 > m && y1 > 0.0) g += (e1 * y1 / (q1 - m)) * (e1 * y1 / (q1 - m));
+    if (q2 > m && y2 > 0.0) g += (e2 * y2 / (q2 - m)) * (e2 * y2 / (q2 - m));
+    root = g > 0.0;
+  }
+  double x0 = 0.0, x1 = 0.0, x2 = 0.0, t;
+  if (root) {
+    const double ek = kmin == 0 ? e0 : (kmin == 1 ? e1 : e2);
+    const double yk = kmin == 0 ? y0 : (kmin == 1 ? y1 : y2);
+    t = kmin >= 0 ? ek * yk - m : -m;
+#pragma unroll 1
+    for (int it = 0; it < 100; ++it) {
+      const double a0 = y0 > 0.0 ? e0 * y0 / (t + q0) : 0.0;
+      const double a1 = y1 > 0.0 ? e1 * y1 / (t + q1) : 0.0;
+      const double a2 = y2 > 0.0 ? e2 * y2 / (t + q2) : 0.0;
+      const double g = ((a0 * a0 + a1 * a1) + a2 * a2) - 1.0;
+      if (!(g > 0.0)) break;
+      // -G'(t) / 2 (terms with y_k = 0 are zero; t may start at -m, where
+      // such a term's denominator vanishes)
+      const double h0 = y0 > 0.0 ? a0 * a0 / (t + q0) : 0.0;
+      const double h1 = y1 > 0.0 ? a1 * a1 / (t + q1) : 0.0;
+      const double h2 = y2 > 0.0 ? a2 * a2 / (t + q2) : 0.0;
+      const double h = (h0 + h1) + h2;
+      const double tn = t + 0.5 * g / h;
+      if (!(tn > t)) break;
+      t = tn;
+    }
+    x0 = y0 > 0.0 ? q0 * y0 / (t + q0) : 0.0;
+    x1 = y1 > 0.0 ? q1 * y1 / (t + q1) : 0.0;
+    x2 = y2 > 0.0 ? q2 * y2 / (t + q2) : 0.0;
+  } else {
+    t = -m;
+    double s = 1.0;
+    int kf = -1;
+    if (q0 > m) {
+      x0 = q0 * y0 / (q0 - m);
+      s -= (x0 / e0) * (x0 / e0);
+    } else if (kf < 0) {
+      kf = 0;
+    }
+    if (q1 > m) {
+      x1 = q1 * y1 / (q1 - m);
+      s -= (x1 / e1) * (x1 / e1);
+    } else if (kf < 0) {
+      kf = 1;
+    }
+    if (q2 > m) {
+      x2 = q2 * y2 / (q2 - m);
+      s -= (x2 / e2) * (x2 / e2);
+    } else if (kf < 0) {
+      kf = 2;
+    }
+    const double xf = sqrt(s > 0.0 ? s : 0.0);
+    if (kf == 0) x0 = e0 * xf;
+    if (kf == 1) x1 = e1 * xf;
+    if (kf == 2) x2 = e2 * xf;
+  }
+  const double dx = y0 - x0, dy = y1 - x1, dz = y2 - x2;
+  const double d = sqrt((dx * dx + dy * dy) + dz * dz);
+  if (gb) {
+    const double n0 = x0 / q0, n1 = x1 / q1, n2 = x2 / q2;
+    const double nn = sqrt((n0 * n0 + n1 * n1) + n2 * n2);
+    gb[0] = (p[0] < 0.0 ? -n0 : n0) / nn;
+    gb[1] = (p[1] < 0.0 ? -n1 : n1) / nn;
+    gb[2] = (p[2] < 0.0 ? -n2 : n2) / nn;
+  }
+  return t < 0.0 ? -d : d;
+}
+
+// Bounds of an ellipsoid's signed distance from its scaled copies: with
+// s = sqrt(sum_k (p_k / e_k)^2), p lies on the surface of sE, and since E
+// = sE + (1 - s)E contains sE plus the ball of radius (1 - s) e_min (and
+// sE = E + (s - 1)E for s > 1), d lies in [(s - 1) e_min, (s - 1) e_max]
+// outside and in [(s - 1) e_max, (s - 1) e_min] inside (unit scale; the
+// nearest point of the scaled surface point is at most (1 - s) |z| <=
+// (1 - s) e_max away).  Used to skip the nearest-point solve where only a
+// comparison with a threshold far from d is needed.
+template <typename T>
+__device__ inline void ellip_bounds(CPoly* P, const T* p, T& dlo, T& dhi) {
+  const HLBM_CONST double* e = P->v[0];
+  const T e0 = (T)e[0], e1 = (T)e[1], e2 = (T)e[2];
+  const T q0 = p[0] / e0, q1 = p[1] / e1, q2 = p[2] / e2;
+  const T s = sqrt((q0 * q0 + q1 * q1) + q2 * q2);
+  const T emin = e0 < e1 ? (e0 < e2 ? e0 : e2) : (e1 < e2 ? e1 : e2);
+  const T emax = (T)P->rc;
+  const T sm = s - (T)1;
+  dlo = sm * (sm >= (T)0 ? emin : emax);
+  dhi = sm * (sm >= (T)0 ? emax : emin);
+}
+
 template <typename T, bool ELL = false>
 __device__ inline T poly_sdf_unit(CPoly* P, const T* p, T* gb, T far) {
   if (ELL && P->kind == KIND_ELLIPSOID) {
-    // smooth body: the exact FP64 distance in every form (rounded to T)
+    // smooth body: the FP64 distance by Newton's method (rounded to T)
     const double pd[3] = {(double)p[0], (double)p[1], (double)p[2]};
     const double fd = far >= (T)1e30 ? 1e300 : (double)far;
-    if (!gb) return (T)ellip_sdf_unit(P, pd, nullptr, fd);
+    if (!gb) return (T)ellip_sdf_newton(P, pd, nullptr, fd);
     double gd[3];
-    const double d = ellip_sdf_unit(P, pd, gd, fd);
+    const double d = ellip_sdf_newton(P, pd, gd, fd);
     for (int k = 0; k < 3; ++k) gb[k] = (T)gd[k];
     return (T)d;
   }
@@ -699,11 +821,29 @@ __device__ inline float sdf32(int shape, float size, const RT* R, float r0,
 // (within 1 ulp; used for screening against an error bound).  Products and
 // sums may fuse here: a fused multiply-add rounds once, which keeps the
 // error within the same bound.
+// With ELL, an ellipsoid type returns a bound instead of the distance when
+// the bound settles both thresholds: its lower bound when that exceeds far,
+// its upper bound when that lies below inner (the rest, the exact distance).
 template <bool ELL = false>
 __device__ inline float sdf32_r(int shape, float size, const float* R, float r0,
-                                float r1, float r2, const PolyDev* poly, float far) {
+                                float r1, float r2, const PolyDev* poly, float far,
+                                float inner = -1e30f) {
 #pragma clang fp contract(fast)
   if (shape == 0) return __builtin_amdgcn_sqrtf(r0 * r0 + r1 * r1 + r2 * r2) - size;
+  if (ELL && poly && shape >= POLY0 &&
+      ((CPoly*)poly + (shape - POLY0))->kind == KIND_ELLIPSOID) {
+    CPoly* P = (CPoly*)poly + (shape - POLY0);
+    const float is = 1.0f / size;
+    float p[3];
+    p[0] = (R[0] * r0 + R[3] * r1 + R[6] * r2) * is;
+    p[1] = (R[1] * r0 + R[4] * r1 + R[7] * r2) * is;
+    p[2] = (R[2] * r0 + R[5] * r1 + R[8] * r2) * is;
+    float dlo, dhi;
+    ellip_bounds<float>(P, p, dlo, dhi);
+    if (size * dlo > far) return size * dlo;
+    if (size * dhi < inner) return size * dhi;
+    return size * poly_sdf_unit<float, true>(P, p, nullptr, 1e30f);
+  }
   if (poly && shape >= POLY0) {
     // beyond far cells outside the plane lower bound is returned
     const float is = 1.0f / size;
@@ -808,6 +948,27 @@ __device__ inline double sdf_grad_exact(int shape, double size, const double* R,
     return d;
   }
   return sdf_grad<ELL>(shape, size, R, r, g, poly, far);
+}
+
+// For an ellipsoid type at world offset r: 1 when its distance bounds put
+// r inside by more than eh + margin (B = 1), 0 when outside by more (B =
+// 0), -1 otherwise and for other shapes (evaluate the distance).
+template <typename T, typename RT>
+__device__ inline int ellip_band(const PolyDev* poly, int shape, T size, const RT* R, T r0,
+                                 T r1, T r2, T eh, T margin) {
+  if (!(poly && shape >= POLY0)) return -1;
+  CPoly* P = (CPoly*)poly + (shape - POLY0);
+  if (P->kind != KIND_ELLIPSOID) return -1;
+  const T is = (T)1 / size;
+  T p[3];
+  p[0] = ((T)R[0] * r0 + (T)R[3] * r1 + (T)R[6] * r2) * is;
+  p[1] = ((T)R[1] * r0 + (T)R[4] * r1 + (T)R[7] * r2) * is;
+  p[2] = ((T)R[2] * r0 + (T)R[5] * r1 + (T)R[8] * r2) * is;
+  T dlo, dhi;
+  ellip_bounds<T>(P, p, dlo, dhi);
+  if (size * dhi <= -eh - margin) return 1;
+  if (size * dlo >= eh + margin) return 0;
+  return -1;
 }
 
 // Coupling weight B(d): 1 for d <= -eps/2, 0 for d >= eps/2, cos^2 ramp.

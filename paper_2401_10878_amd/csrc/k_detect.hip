@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(POLY ? (ELL
     const float f2 = minimg_f(fzf - xr[2], Lzf, perz);
     // a polyhedron's plane lower bound beyond both thresholds ends its search
     const float d = sdf32_r<ELL>(shape, xr[17], xr + 3, f0, f1, f2, POLY ? P.poly : nullptr,
-                            xr[16]);
+                                 xr[16], ELL ? src[19] : -1e30f);
     const bool may_own = valid & (d < xr[12]), may_det = valid & (d < xr[14]);
     nown += may_own ? 1 : 0;
     bp = may_own ? p : bp;

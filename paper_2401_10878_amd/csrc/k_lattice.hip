@@ -606,17 +606,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
       const float4* rec = (const float4*)(P.LR32 + LREC * o);
       const float4 ra = rec[3], rb = rec[4], rc = rec[5];
       const float Rf[9] = {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w, rc.x};
-      const C d = sdf32<ELL>(__float_as_int(rc.z), rc.y, Rf, rp[0], rp[1], rp[2],
-                        POLY ? P.poly : nullptr);
-      B = weight32(d, ph.eps_h32, ph.eps_q32);
+      // (an ellipsoid beyond the band either way: B from its bounds)
+      const int band = ELL ? ellip_band<float>(P.poly, __float_as_int(rc.z), rc.y, Rf, rp[0],
+                                               rp[1], rp[2], ph.eps_h32, 1e-3f)
+                           : -1;
+      if (band >= 0) {
+        B = (C)band;
+      } else {
+        const C d = sdf32<ELL>(__float_as_int(rc.z), rc.y, Rf, rp[0], rp[1], rp[2],
+                               POLY ? P.poly : nullptr);
+        B = weight32(d, ph.eps_h32, ph.eps_q32);
+      }
     } else {
       const int shape = P.shape[o];
       const double size = P.size[o];
       double Ro[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) Ro[k] = P.R[9 * o + k];
-      const C d = sdf<ELL>(shape, size, Ro, rp[0], rp[1], rp[2], POLY ? P.poly : nullptr);
-      B = weight(d, ph.eps);
+      const int band = ELL ? ellip_band<double>(P.poly, shape, size, Ro, (double)rp[0],
+                                                (double)rp[1], (double)rp[2], 0.5 * ph.eps, 1e-9)
+                           : -1;
+      if (band >= 0) {
+        B = (C)band;
+      } else {
+        const C d = sdf<ELL>(shape, size, Ro, rp[0], rp[1], rp[2], POLY ? P.poly : nullptr);
+        B = weight(d, ph.eps);
+      }
     }
   }
   // uniform fluid acceleration: fixed, or the zero-net-flux controller's

@@ -229,7 +229,7 @@ __global__ __launch_bounds__(64) void k_particles(Particles P, Geom g, Phys ph,
     rec[16] = fmaxf(ot, dt) + tol;
     rec[17] = fs;
     rec[18] = __int_as_float(sh);
-    rec[19] = 0.0f;
+    rec[19] = fminf(ot, dt) - tol;   // below both (the ellipsoid screen's bound)
     // the lattice pass's kinematic record: centre split into an integer part
     // and its fraction (exact in FP64, the fraction then rounded to FP32)
     float* lr = P.LR32 + LREC * ip;

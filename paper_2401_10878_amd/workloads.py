@@ -569,6 +569,38 @@ def c3_dense_boxes(seed: int = 3, L: int = 256, phi: float = 0.30,
                     polyhedra={0: polyhedron_cuboid(*dims3)})
 
 
+def c3_dense_ellipsoids(seed: int = 3, L: int = 256, phi: float = 0.12,
+                        edge: float = 14.0, margin: float = 0.3) -> Workload:
+    """256^3 periodic box of ellipsoids with semi-axes ratio 1 : 1.25 : 1.6
+    and the volume of the cube of edge 14, as an ellipsoid type (the smooth
+    convex body; exact distance by its nearest-point multiplier).
+
+    Orientations are drawn as for the boxes with the ellipsoids' bounding
+    boxes (half extents the semi-axes): bounding boxes that do not overlap
+    keep the ellipsoids apart.  Those boxes hold twice the body volume, so
+    the fill is phi 0.12 (734 bodies) rather than the cubes' 0.30; the
+    lattice sites then sit 30 cells apart, more than two long semi-axes, so
+    (as in the sphere box) no pair is in contact at the start.
+    """
+    s, ar, tau = 1.5, 1000.0, 0.55
+    dsph = cube_equiv_diameter(edge)
+    lu = lattice_units(dsph, s, ar, tau)
+    n = round(phi * L ** 3 / edge ** 3)
+    a = (edge ** 3 / (4.0 / 3.0 * math.pi * 2.0)) ** (1.0 / 3.0)
+    axes = np.array([a, 1.25 * a, 1.6 * a])
+    X = _dense_centres(seed, L, n, dsph)
+    rng = np.random.default_rng(seed + 3000)
+    q = box_orientations(rng, X, axes, (L, L, L), (True, True, True), margin=margin)
+    sc = Scene(np.full(n, POLY0, np.int32), np.ones(n), np.full(n, s), X,
+               q, np.zeros((n, 3)), np.zeros((n, 3)))
+    p = _base_params((L, L, L), 1, tau, lu, 2).replace(
+        max_pairs=max(1024, 8 * n), tile_capacity=48, precision=1)
+    return Workload("C3E", p, sc, 1000,
+                    f"{L}^3 periodic, {n} ellipsoids {axes[0]:.2f} x {axes[1]:.2f} x "
+                    f"{axes[2]:.2f} (semi-axes), phi~{phi}, s=1.5, Ar=1000",
+                    polyhedra={0: Ellipsoid(tuple(float(x) for x in axes))})
+
+
 def c4_dense_spheres(seed: int = 3, L: int = 256, phi: float = 0.30,
                      edge: float = 14.0) -> Workload:
     """256^3 periodic, 1834 spheres of the cubes' volume-equivalent diameter;
@@ -742,6 +774,7 @@ WORKLOADS = {
     "C2": c2_settling_walls,
     "C3": c3_dense_cubes,
     "C3B": c3_dense_boxes,
+    "C3E": c3_dense_ellipsoids,
     "C4": c4_dense_spheres,
     "C5": c5_adjoint_cubes,
 }

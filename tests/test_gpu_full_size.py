@@ -24,6 +24,8 @@ from test_gpu_parity import TOL, compare_contacts, force_err, rel_field
 
 pytestmark = pytest.mark.gpu
 
+W_POLY0 = 3      # first body-type shape code
+
 NSTEPS = 3
 
 
@@ -65,7 +67,7 @@ def _check(H, wl, ref, prec):
     nsteps = len(ref["steps"])
     p = wl.params.replace(precision=prec)
     tol = TOL[prec]
-    g = H.Simulation(p, wl.scene)
+    g = H.Simulation(p, wl.scene, polyhedra=wl.polyhedra)
     g.init_equilibrium()
     assert np.array_equal(g.fields()["owner"], ref["owner0"])
     compare_contacts(ref["contacts0"], g.contacts(), 0.0)
@@ -73,6 +75,9 @@ def _check(H, wl, ref, prec):
     assert (c["pairs"], c["cells"]) == ref["counters0"]
     V = np.where(wl.scene.shape == 1, wl.scene.size ** 3,
                  4.0 / 3.0 * np.pi * wl.scene.size ** 3)
+    for k, T in (wl.polyhedra or {}).items():     # ellipsoid types here
+        m = wl.scene.shape == W_POLY0 + k
+        V[m] = 4.0 / 3.0 * np.pi * float(np.prod(T.axes)) * wl.scene.size[m] ** 3
     Fref = ((wl.scene.density - 1) * V).max() * abs(p.gravity[2])
     Tref = Fref * wl.scene.size.max()
     for k in range(nsteps):
@@ -101,7 +106,7 @@ def _check(H, wl, ref, prec):
     # the benchmark's launch sequence: the same steps in one call (the
     # contact treatment of steps 2..n beside the previous lattice passes)
     # leaves the same bits as the step-by-step run above
-    g2 = H.Simulation(p, wl.scene)
+    g2 = H.Simulation(p, wl.scene, polyhedra=wl.polyhedra)
     g2.init_equilibrium()
     g2.step(nsteps)
     assert np.array_equal(g2.populations(), fg)
@@ -120,6 +125,23 @@ def test_dense_cube_box_full_size(dense_cubes, H, prec):
 @pytest.mark.parametrize("prec", [0, 2])
 def test_dense_sphere_box_full_size(dense_spheres, H, prec):
     wl, ref = dense_spheres
+    _check(H, wl, ref, prec)
+
+
+@pytest.fixture(scope="module")
+def dense_ellipsoids(O, W):
+    wl = W.c3_dense_ellipsoids()
+    for k, T in wl.polyhedra.items():
+        O.define_body_type(k, T)
+    _say("oracle: dense ellipsoid box", wl.note)
+    return wl, _oracle_run(O, wl, nsteps=2)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_dense_ellipsoid_box_full_size(dense_ellipsoids, H, prec):
+    """The ellipsoid benchmark box (734 ellipsoids, 256^3): every node's
+    owner from the exact ellipsoid distance, bit-exact in FP64."""
+    wl, ref = dense_ellipsoids
     _check(H, wl, ref, prec)
 
 
