@@ -167,9 +167,12 @@ hlbm_status hlbm_define_polyhedron(hlbm_ctx *ctx, int type, int nv,
    the body axes, scaled uniformly by a particle's size (smooth convex
    bodies, Sec. 1; the method needs only a signed distance and its gradient,
    Sec. 3.2 and Sec. 3.3.1).  The signed distance is the exact Euclidean
-   distance to the surface: the nearest point's Lagrange multiplier is
-   bisected to adjacent doubles, so one evaluation costs up to about a
-   hundred FP64 iterations.  Volume 4 pi a b c / 3; eq. (3) with the
+   distance to the surface, from the nearest point's Lagrange multiplier:
+   the FP64 ownership, detection and contact decisions bisect it to
+   adjacent doubles (up to about a hundred iterations); the coupling weight
+   and the detection screen take Newton steps, and skip the solve where
+   bounds from the scaled ellipsoids already decide.  Volume 4 pi a b c / 3;
+   eq. (3) with the
    inertia tensor of the homogeneous solid.  HLBM_E_ARG for a type outside
    0..7 or a semi-axis that is not positive and finite; call before
    hlbm_init_particles (HLBM_E_STATE after).  Not supported by the
