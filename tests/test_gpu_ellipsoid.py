@@ -3,7 +3,8 @@ against the FP64 oracle: a triaxial ellipsoid and a spheroid (two equal
 shortest axes) mixed with a box and spheres in a periodic box, an
 axis-aligned ellipsoid centred on a node (nodes on its symmetry planes and
 axes take the degenerate branches of the nearest-point solve) next to a
-second one, and ellipsoids on a wall.  Owners, pair sets and overlap counts
+second one, two chains of overlapping ellipsoids (37 ellipsoid pairs), and
+ellipsoids on a wall.  Owners, pair sets and overlap counts
 bit-exact at the start and after every FP64 step; forces, torques, angular
 velocities and positions within the precision's tolerance; malformed
 definitions rejected."""
@@ -121,6 +122,47 @@ def test_ellipsoid_axis_aligned_on_node(O, W, H, prec):
     _say("ellipsoid on a node, precision", prec)
     oc, gc = _run(O, W, H, p, sc, types, None, 3, 1e-4 * 0.5 * 4 / 3 * math.pi * 6 ** 3 * 0.24)
     assert any(c["b"] == 1 for c in oc)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ellipsoid_contact_chains(O, W, H, prec):
+    """Two periodic chains, tilted triaxial ellipsoids tip to tip and
+    spheroids beside them, every neighbour overlapping its enlarged
+    surface: 37 ellipsoid-ellipsoid pairs, across the periodic boundary and
+    between the chains, through the box correction and the overlap
+    integration with gradients."""
+    types = {0: W.Ellipsoid((1.0, 0.6, 0.4)), 1: W.Ellipsoid((0.7, 0.7, 1.1))}
+    _define(O, types)
+    rng = np.random.default_rng(21)
+    L, n0, n1 = 40, 6, 12
+
+    def tilt(ang):
+        ax = rng.normal(size=3)
+        ax /= np.linalg.norm(ax)
+        a = rng.uniform(-ang, ang)
+        return np.array([math.cos(a / 2), *(math.sin(a / 2) * ax)])
+
+    X, q, sh, sz = [], [], [], []
+    for i in range(n0):
+        X.append([i * L / n0 + 1.3, 6.0, 12.0])
+        q.append(tilt(0.2))
+        sh.append(W.POLY0)
+        sz.append(3.5)
+    for i in range(n1):
+        X.append([i * L / n1 + 0.4, 9.6, 12.3])
+        q.append(tilt(0.25))
+        sh.append(W.POLY0 + 1)
+        sz.append(2.5)
+    n = n0 + n1
+    sc = W.Scene(np.array(sh, np.int32), np.array(sz), np.full(n, 1.5), np.array(X),
+                 np.array(q), rng.uniform(-0.002, 0.002, (n, 3)),
+                 rng.uniform(-0.001, 0.001, (n, 3)))
+    p = W.Params(nx=L, ny=20, nz=24, periodic_z=1, tau=0.7, gravity=(0.0, 0.0, -1e-4),
+                 balance=1, young=0.4, u_k=3e-4, max_pairs=256, tile_capacity=24,
+                 precision=prec)
+    _say("ellipsoid chains, precision", prec)
+    oc, gc = _run(O, W, H, p, sc, types, None, 3, 1e-4 * 0.5 * 4 / 3 * math.pi * 2.5 ** 3)
+    assert len(oc) >= 30
 
 
 def test_ellipsoid_on_wall(O, W, H):
