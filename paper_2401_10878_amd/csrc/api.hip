@@ -110,14 +110,23 @@ void drop_graphs(Ctx& c) {
   for (int k = 0; k < 4; ++k) {
     if (c.graph_ready[k]) hipGraphExecDestroy(c.gexec[k]);
     c.graph_ready[k] = false;
-    if (c.graph_n_ready[k]) hipGraphExecDestroy(c.gexec_n[k]);
-    c.graph_n_ready[k] = false;
+    for (int v = 0; v < 4; ++v) {
+      if (c.graph_n_ready[k][v]) hipGraphExecDestroy(c.gexec_n[k][v]);
+      c.graph_n_ready[k][v] = false;
+      c.graph_n_run[k][v] = false;
+    }
   }
 }
 
 // steps per multi-step graph (even: the population and table parities come
 // back to their starting values)
 constexpr int GRAPH_STEPS = 8;
+// The first replay of a multi-step graph carries a one-time setup on the
+// device (about 0.15 ms, measured; uploading the graph beforehand does not
+// remove it).  A call of fewer steps than this replays only graphs that
+// have run before and otherwise keeps to stream launches, which are as fast
+// per step; a longer call replays (and so prepares) them.
+constexpr int GRAPH_COLD_CALL = 64;
 
 hlbm_status prepare_graphs(Ctx& c);
 
@@ -151,8 +160,11 @@ hlbm_status prologue(Ctx& c) {
 // can run beside them on the side stream.  pre & PRE_DONE: this step's
 // treatment already ran there (wait for it, then clear the tile counts the
 // previous momentum-exchange pass read); pre & PRE_NEXT: after detection,
-// start the next step's treatment on the side stream.
-constexpr int PRE_DONE = 1, PRE_NEXT = 2;
+// start the next step's treatment on the side stream; pre & PRE_JOINED
+// (with PRE_DONE): that treatment, and the balance sums, are complete in
+// stream order already (a graph that started them joined them before its
+// end), so no event wait.
+constexpr int PRE_DONE = 1, PRE_NEXT = 2, PRE_JOINED = 4;
 hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev, int pre) {
   hipError_t e;
   int m = 0;
@@ -164,7 +176,7 @@ hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev, int pre) {
     if (s == 0 && (pre & PRE_DONE)) {
       // (the tile counts need no clearing here: detection and the lattice
       // pass reset the counts they read)
-      if ((e = hipStreamWaitEvent(c.stream, c.ev_treat, 0))) return e;
+      if (!(pre & PRE_JOINED) && (e = hipStreamWaitEvent(c.stream, c.ev_treat, 0))) return e;
       if ((e = mark())) return e;
     } else {
       if ((e = launch_clear_step(c, c.tab[1 - t], CLEAR_CONTACT | CLEAR_TILES, c.stream)))
@@ -198,7 +210,9 @@ hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev, int pre) {
   // bookkeeping, particle motion and detection, and the next lattice pass
   // waits for them.
   const bool bal = c.ph.bal_mode == 2;
-  if (bal && (pre & PRE_DONE) && (e = hipStreamWaitEvent(c.stream, c.ev_bal, 0))) return e;
+  if (bal && (pre & PRE_DONE) && !(pre & PRE_JOINED) &&
+      (e = hipStreamWaitEvent(c.stream, c.ev_bal, 0)))
+    return e;
   if ((e = launch_lattice(c, c.fbuf[p], c.fbuf[1 - p]))) return e;
   if (bal && (pre & PRE_NEXT)) {
     if ((e = hipEventRecord(c.ev_lat, c.stream))) return e;
@@ -213,19 +227,25 @@ hipError_t enqueue_step(Ctx& c, int p, int t, hipEvent_t* ev, int pre) {
 }
 
 // Capture and instantiate the graph of one step (multi = false) or of
-// GRAPH_STEPS steps with the overlapped contact treatment (multi = true)
-// starting from population parity key / 2 and table parity key % 2.
-// Capturing runs nothing.
-hlbm_status capture_graph(Ctx& c, int key, bool multi) {
+// GRAPH_STEPS steps with the overlapped contact treatment (multi = true,
+// variant v as in Ctx::gexec_n) starting from population parity key / 2 and
+// table parity key % 2.  Capturing runs nothing.
+hlbm_status capture_graph(Ctx& c, int key, bool multi, int v = 0) {
   const int p = key / 2, t = key % 2;
   hipGraph_t gr;
   HIPCHECK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
   if (multi) {
+    const bool first_done = v & 1, last_next = v & 2;
     for (int j = 0; j < GRAPH_STEPS && e == hipSuccess; ++j) {
-      const int pre = (j > 0 ? PRE_DONE : 0) | (j + 1 < GRAPH_STEPS ? PRE_NEXT : 0);
+      const int pre = (j > 0 ? PRE_DONE : (first_done ? PRE_DONE | PRE_JOINED : 0)) |
+                      (j + 1 < GRAPH_STEPS || last_next ? PRE_NEXT : 0);
       e = enqueue_step(c, p ^ (j & 1), t ^ (j & 1), nullptr, pre);
     }
+    // the next step's treatment (and the balance sums after it) joined
+    // back, so that the graph ends with nothing pending
+    if (e == hipSuccess && last_next)
+      e = hipStreamWaitEvent(c.stream, c.ph.bal_mode == 2 ? c.ev_bal : c.ev_treat, 0);
   } else {
     e = enqueue_step(c, p, t, nullptr, 0);
   }
@@ -233,12 +253,17 @@ hlbm_status capture_graph(Ctx& c, int key, bool multi) {
   if (e != hipSuccess || e2 != hipSuccess)
     return fail(c, HLBM_E_DEVICE, "graph capture: %s",
                 hipGetErrorString(e != hipSuccess ? e : e2));
-  hipGraphExec_t* slot = multi ? &c.gexec_n[key] : &c.gexec[key];
+  hipGraphExec_t* slot = multi ? &c.gexec_n[key][v] : &c.gexec[key];
   e = hipGraphInstantiate(slot, gr, nullptr, nullptr, 0);
   hipGraphDestroy(gr);
   if (e != hipSuccess)
     return fail(c, HLBM_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
-  (multi ? c.graph_n_ready : c.graph_ready)[key] = true;
+  // upload now, so that the first replay does not carry it
+  e = hipGraphUpload(*slot, c.stream);
+  if (e != hipSuccess)
+    return fail(c, HLBM_E_DEVICE, "graph upload: %s", hipGetErrorString(e));
+  if (multi) c.graph_n_ready[key][v] = true;
+  else c.graph_ready[key] = true;
   return HLBM_OK;
 }
 
@@ -256,10 +281,11 @@ hlbm_status prepare_graphs(Ctx& c) {
       const hlbm_status st = capture_graph(c, key, false);
       if (st != HLBM_OK) return st;
     }
-    if (c.n_sub == 1 && c.side && !c.graph_n_ready[key]) {
-      const hlbm_status st = capture_graph(c, key, true);
-      if (st != HLBM_OK) return st;
-    }
+    for (int v = 0; v < 4 && c.n_sub == 1 && c.side; ++v)
+      if (!c.graph_n_ready[key][v]) {
+        const hlbm_status st = capture_graph(c, key, true, v);
+        if (st != HLBM_OK) return st;
+      }
   }
   return HLBM_OK;
 }
@@ -937,25 +963,37 @@ hlbm_status hlbm_step(hlbm_ctx* h, int nsteps) {
   Ctx& c = h->c;
   if (!c.fluid_ready) return fail(c, HLBM_E_STATE, "initialise particles and fluid first");
   if (nsteps < 0) return fail(c, HLBM_E_ARG, "nsteps must be >= 0");
+  // With graphs on (one contact sub-step), a call of two or more steps
+  // replays multi-step graphs first and runs the remaining steps as stream
+  // launches; the contact treatment overlaps the previous lattice pass at
+  // every step but the call's first, across graph boundaries too (a graph
+  // followed by more steps starts the next step's treatment and joins it
+  // before it ends; the step after it takes it as done).  The same bits as
+  // stream launches.  A single step replays its single-step graph.
+  const bool chain = c.use_graph && !c.timing && c.n_sub == 1 && c.side != nullptr;
+  bool after_graph = false;   // the previous step ended a graph that joined
+  bool streamed = false;      // a stream launch of this call may have left the
+                              // next step's treatment pending: no graph after it
   for (int s = 0; s < nsteps; ++s) {
+    const int key = 2 * c.cur + c.tcur;
+    const int v = (s > 0 ? 1 : 0) | (s + GRAPH_STEPS < nsteps ? 2 : 0);
     if (c.timing) {
       if (c.tused >= c.tcap)
         return fail(c, HLBM_E_CAPACITY, "timing window of %d steps is full", c.tcap);
       HIPCHECK(run_step(c, c.tev + (size_t)c.tused * c.ev_per_step));
       c.tused++;
-    } else if (c.use_graph && c.n_sub == 1 && nsteps - s >= GRAPH_STEPS && c.side) {
-      // GRAPH_STEPS steps in one graph; the side stream joins the capture at
-      // the first fork and is joined back by the last step
-      const int key = 2 * c.cur + c.tcur;
-      if (!c.graph_n_ready[key]) {
-        const hlbm_status st = capture_graph(c, key, true);
+    } else if (chain && !streamed && nsteps - s >= GRAPH_STEPS &&
+               (c.graph_n_run[key][v] || nsteps >= GRAPH_COLD_CALL)) {
+      if (!c.graph_n_ready[key][v]) {
+        const hlbm_status st = capture_graph(c, key, true, v);
         if (st != HLBM_OK) return st;
       }
-      HIPCHECK(hipGraphLaunch(c.gexec_n[key], c.stream));
+      HIPCHECK(hipGraphLaunch(c.gexec_n[key][v], c.stream));
+      c.graph_n_run[key][v] = true;
       c.step += GRAPH_STEPS;
       s += GRAPH_STEPS - 1;
-    } else if (c.use_graph) {
-      const int key = 2 * c.cur + c.tcur;
+      after_graph = true;
+    } else if (c.use_graph && !(chain && nsteps >= 2)) {
       if (!c.graph_ready[key]) {
         const hlbm_status st = capture_graph(c, key, false);
         if (st != HLBM_OK) return st;
@@ -969,7 +1007,10 @@ hlbm_status hlbm_step(hlbm_ctx* h, int nsteps) {
       // with the previous step's lattice passes; the last step leaves none
       // pending, so the state after the call is that of whole steps
       const bool ovl = c.n_sub == 1 && c.side != nullptr;
-      const int pre = (ovl && s > 0 ? PRE_DONE : 0) | (ovl && s + 1 < nsteps ? PRE_NEXT : 0);
+      const int pre = (ovl && s > 0 ? PRE_DONE | (after_graph ? PRE_JOINED : 0) : 0) |
+                      (ovl && s + 1 < nsteps ? PRE_NEXT : 0);
+      after_graph = false;
+      streamed = true;
       const hipError_t e = run_step(c, nullptr, pre);
       if (e != hipSuccess) {
         // whatever the side stream has queued is joined before reporting

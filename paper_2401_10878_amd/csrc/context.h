@@ -274,13 +274,18 @@ struct Ctx {
   size_t part_bytes = 0, tile_bytes = 0, psum_bytes = 0;
   Adjoint adj;
   // graphs: one per (population parity, contact-table parity) for a single
-  // step, and (one contact sub-step) one for GRAPH_STEPS steps with the
-  // overlapped contact treatment inside
+  // step, and (one contact sub-step) GRAPH_STEPS steps with the overlapped
+  // contact treatment inside, in four variants v: v & 1, the first step's
+  // treatment already ran (the previous graph's last step started it);
+  // v & 2, the last step starts the next step's treatment and the graph
+  // joins it before it ends
   bool use_graph;
   hipGraphExec_t gexec[4];
   bool graph_ready[4];
-  hipGraphExec_t gexec_n[4];
-  bool graph_n_ready[4] = {false, false, false, false};
+  hipGraphExec_t gexec_n[4][4];
+  bool graph_n_ready[4][4] = {};
+  bool graph_n_run[4][4] = {};   // replayed at least once (its one-time
+                                 // setup on the device is done)
   int n_sub;
   int ev_per_step;        // timing events per step: 2 + 5 n_sub
   char err[512] = {};     // last error message (fixed: error paths allocate nothing)

@@ -170,16 +170,16 @@ def test_dense_cube_box_pair_list_longer_than_grid(crowded_cubes, H, prec):
 
 
 def test_dense_cube_box_graphs_match_stream(W, H):
-    """The benchmark's launch mode at full size: 11 FP32 steps in one call
-    replayed as graphs (one captured 8-step graph with the overlapped
-    contact treatment, then three single-step graphs) leave the same bits as
-    11 stream-launched steps."""
+    """The benchmark's launch mode at full size: 67 FP32 steps in one call
+    replayed as graphs (eight chained 8-step graphs with the overlapped
+    contact treatment, then three stream steps) leave the same bits as 67
+    stream-launched steps."""
     wl = W.c3_dense_cubes()
     out = []
     for graph in (False, True):
         g = H.Simulation(wl.params, wl.scene, graph=graph)
         g.init_equilibrium()
-        g.step(11)
+        g.step(67)
         out.append((g.particles(), g.forces(), g.populations()[:, ::5, ::3, :].copy(),
                     [(c["a"], c["b"], c["count"], c["fn"]) for c in g.contacts()]))
         g.close()

@@ -229,9 +229,16 @@ def test_overlapped_treatment_matches_ordered_steps(W, H, prec):
 
 
 def test_multistep_graph_matches_stream(W, H):
-    """Calls of 19 steps replayed as graphs (two captured 8-step graphs with
-    the overlapped contact treatment inside, then three single-step graphs)
-    leave the same bits as the stream launches."""
+    """Calls replayed as graphs leave the same bits as stream launches, on
+    every path a call can take (8-step graphs with the overlapped contact
+    treatment inside, chained across graph boundaries): a long call that
+    replays graphs not run before (70 steps: graphs, then six stream steps
+    after a joined graph); a short call of graphs already run (19: two
+    graphs, three stream steps); a short call whose graphs have not run (19
+    from the other parity: stream launches only); a graph whose successor
+    has not run (16: one graph, then stream); 64 steps ending in the graph
+    that starts no further treatment; that graph chained after another
+    (16); one step (its single-step graph); five steps (stream)."""
     sc = W.random_small_scene(31, (26, 22, 20), 9, size_range=(1.8, 3.0),
                               gap=-0.7, speed=0.01, spin=0.004)
     p = W.Params(nx=26, ny=22, nz=20, tau=0.7, young=0.4, u_k=3e-4,
@@ -242,15 +249,15 @@ def test_multistep_graph_matches_stream(W, H):
     a.init_equilibrium(u=(0.002, -0.001, 0))
     b.init_equilibrium(u=(0.002, -0.001, 0))
     assert len(a.contacts()) > 0
-    for _ in range(2):
-        a.step(19)
-        b.step(19)
+    for n in (70, 19, 19, 16, 64, 16, 1, 5):
+        a.step(n)
+        b.step(n)
         a.sync()
         b.sync()
-        assert np.array_equal(a.populations(), b.populations())
+        assert np.array_equal(a.populations(), b.populations()), n
         pa, pb = a.particles(), b.particles()
         for k in pa:
-            assert np.array_equal(pa[k], pb[k]), k
+            assert np.array_equal(pa[k], pb[k]), (n, k)
         ca, cb = a.contacts(), b.contacts()
         assert [_key(c) for c in ca] == [_key(c) for c in cb]
         assert a.counters() == b.counters()
