@@ -219,12 +219,17 @@ hlbm_status hlbm_set_populations(hlbm_ctx *ctx, const double *f);
 hlbm_status hlbm_step(hlbm_ctx *ctx, int nsteps);
 
 /* Use (1) or stop using (0) captured HIP graphs for hlbm_step (the step of
-   Algorithm 1 as one launch): with one contact sub-step, calls replay
-   8-step graphs (the overlapped contact treatment captured inside) while
-   at least 8 steps remain, and single-step graphs for the rest.  The graphs
-   of the parities the next steps can reach are captured (not run) when
-   graphs are switched on, at initialisation and after hlbm_set_state, so
-   that later hlbm_step calls only launch them. */
+   Algorithm 1 as one launch).  With one contact sub-step, a call of two or
+   more steps replays 8-step graphs (the overlapped contact treatment
+   captured inside, and carried across graph boundaries) while at least 8
+   steps remain, and runs the rest as overlapped stream launches; a single
+   step replays a single-step graph.  A graph's first replay carries a
+   one-time setup, so a call of fewer than 64 steps replays only graphs
+   that have run before (else it keeps to stream launches).  Results are
+   those of stream launches, bit for bit.  The graphs of the parities the
+   next steps can reach are captured, instantiated and uploaded (not run)
+   when graphs are switched on, at initialisation and after hlbm_set_state,
+   so that later hlbm_step calls only launch them. */
 hlbm_status hlbm_use_graph(hlbm_ctx *ctx, int on);
 
 /* Per-kernel timing of the next steps (measurement, no paper passage):
