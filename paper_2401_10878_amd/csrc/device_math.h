@@ -428,10 +428,11 @@ __device__ inline double ellip_sdf_unit(CPoly* P, const double* p, double* gb, d
 // it) and stop when a step no longer changes t; the free branch is the
 // exact form's.  A few steps against up to a hundred halvings, so a
 // wavefront with one band node in it does not wait for the bisection.
-__device__ inline double ellip_sdf_newton(CPoly* P, const double* p, double* gb, double far) {
-  if (far < 1e300) {
-    const double r = sqrt((p[0] * p[0] + p[1] * p[1]) + p[2] * p[2]);
-    const double lb = r - P->rc;
+template <typename T>
+__device__ inline T ellip_sdf_newton(CPoly* P, const T* p, T* gb, T far) {
+  if (far < (T)1e30) {
+    const T r = sqrt((p[0] * p[0] + p[1] * p[1]) + p[2] * p[2]);
+    const T lb = r - (T)P->rc;
     if (lb > far) {
       if (gb) {
         gb[0] = p[0] / r;
@@ -441,50 +442,50 @@ __device__ inline double ellip_sdf_newton(CPoly* P, const double* p, double* gb,
       return lb;
     }
   }
-  const double e0 = P->v[0][0], e1 = P->v[0][1], e2 = P->v[0][2];
-  const double y0 = fabs(p[0]), y1 = fabs(p[1]), y2 = fabs(p[2]);
-  const double q0 = e0 * e0, q1 = e1 * e1, q2 = e2 * e2;
-  double m = q0;
+  const T e0 = (T)P->v[0][0], e1 = (T)P->v[0][1], e2 = (T)P->v[0][2];
+  const T y0 = fabs(p[0]), y1 = fabs(p[1]), y2 = fabs(p[2]);
+  const T q0 = e0 * e0, q1 = e1 * e1, q2 = e2 * e2;
+  T m = q0;
   if (q1 < m) m = q1;
   if (q2 < m) m = q2;
-  const int kmin = (q0 == m && y0 > 0.0) ? 0
-                 : ((q1 == m && y1 > 0.0) ? 1 : ((q2 == m && y2 > 0.0) ? 2 : -1));
+  const int kmin = (q0 == m && y0 > (T)0) ? 0
+                 : ((q1 == m && y1 > (T)0) ? 1 : ((q2 == m && y2 > (T)0) ? 2 : -1));
   bool root = true;
   if (kmin < 0) {
-    double g = -1.0;
-    if (q0 > m && y0 > 0.0) g += (e0 * y0 / (q0 - m)) * (e0 * y0 / (q0 - m));
-    if (q1 > m && y1 > 0.0) g += (e1 * y1 / (q1 - m)) * (e1 * y1 / (q1 - m));
-    if (q2 > m && y2 > 0.0) g += (e2 * y2 / (q2 - m)) * (e2 * y2 / (q2 - m));
-    root = g > 0.0;
+    T g = -(T)1;
+    if (q0 > m && y0 > (T)0) g += (e0 * y0 / (q0 - m)) * (e0 * y0 / (q0 - m));
+    if (q1 > m && y1 > (T)0) g += (e1 * y1 / (q1 - m)) * (e1 * y1 / (q1 - m));
+    if (q2 > m && y2 > (T)0) g += (e2 * y2 / (q2 - m)) * (e2 * y2 / (q2 - m));
+    root = g > (T)0;
   }
-  double x0 = 0.0, x1 = 0.0, x2 = 0.0, t;
+  T x0 = (T)0, x1 = (T)0, x2 = (T)0, t;
   if (root) {
-    const double ek = kmin == 0 ? e0 : (kmin == 1 ? e1 : e2);
-    const double yk = kmin == 0 ? y0 : (kmin == 1 ? y1 : y2);
+    const T ek = kmin == 0 ? e0 : (kmin == 1 ? e1 : e2);
+    const T yk = kmin == 0 ? y0 : (kmin == 1 ? y1 : y2);
     t = kmin >= 0 ? ek * yk - m : -m;
 #pragma unroll 1
     for (int it = 0; it < 100; ++it) {
-      const double a0 = y0 > 0.0 ? e0 * y0 / (t + q0) : 0.0;
-      const double a1 = y1 > 0.0 ? e1 * y1 / (t + q1) : 0.0;
-      const double a2 = y2 > 0.0 ? e2 * y2 / (t + q2) : 0.0;
-      const double g = ((a0 * a0 + a1 * a1) + a2 * a2) - 1.0;
-      if (!(g > 0.0)) break;
+      const T a0 = y0 > (T)0 ? e0 * y0 / (t + q0) : (T)0;
+      const T a1 = y1 > (T)0 ? e1 * y1 / (t + q1) : (T)0;
+      const T a2 = y2 > (T)0 ? e2 * y2 / (t + q2) : (T)0;
+      const T g = ((a0 * a0 + a1 * a1) + a2 * a2) - (T)1;
+      if (!(g > (T)0)) break;
       // -G'(t) / 2 (terms with y_k = 0 are zero; t may start at -m, where
       // such a term's denominator vanishes)
-      const double h0 = y0 > 0.0 ? a0 * a0 / (t + q0) : 0.0;
-      const double h1 = y1 > 0.0 ? a1 * a1 / (t + q1) : 0.0;
-      const double h2 = y2 > 0.0 ? a2 * a2 / (t + q2) : 0.0;
-      const double h = (h0 + h1) + h2;
-      const double tn = t + 0.5 * g / h;
+      const T h0 = y0 > (T)0 ? a0 * a0 / (t + q0) : (T)0;
+      const T h1 = y1 > (T)0 ? a1 * a1 / (t + q1) : (T)0;
+      const T h2 = y2 > (T)0 ? a2 * a2 / (t + q2) : (T)0;
+      const T h = (h0 + h1) + h2;
+      const T tn = t + (T)0.5 * g / h;
       if (!(tn > t)) break;
       t = tn;
     }
-    x0 = y0 > 0.0 ? q0 * y0 / (t + q0) : 0.0;
-    x1 = y1 > 0.0 ? q1 * y1 / (t + q1) : 0.0;
-    x2 = y2 > 0.0 ? q2 * y2 / (t + q2) : 0.0;
+    x0 = y0 > (T)0 ? q0 * y0 / (t + q0) : (T)0;
+    x1 = y1 > (T)0 ? q1 * y1 / (t + q1) : (T)0;
+    x2 = y2 > (T)0 ? q2 * y2 / (t + q2) : (T)0;
   } else {
     t = -m;
-    double s = 1.0;
+    T s = (T)1;
     int kf = -1;
     if (q0 > m) {
       x0 = q0 * y0 / (q0 - m);
@@ -504,21 +505,21 @@ __device__ inline double ellip_sdf_newton(CPoly* P, const double* p, double* gb,
     } else if (kf < 0) {
       kf = 2;
     }
-    const double xf = sqrt(s > 0.0 ? s : 0.0);
+    const T xf = sqrt(s > (T)0 ? s : (T)0);
     if (kf == 0) x0 = e0 * xf;
     if (kf == 1) x1 = e1 * xf;
     if (kf == 2) x2 = e2 * xf;
   }
-  const double dx = y0 - x0, dy = y1 - x1, dz = y2 - x2;
-  const double d = sqrt((dx * dx + dy * dy) + dz * dz);
+  const T dx = y0 - x0, dy = y1 - x1, dz = y2 - x2;
+  const T d = sqrt((dx * dx + dy * dy) + dz * dz);
   if (gb) {
-    const double n0 = x0 / q0, n1 = x1 / q1, n2 = x2 / q2;
-    const double nn = sqrt((n0 * n0 + n1 * n1) + n2 * n2);
-    gb[0] = (p[0] < 0.0 ? -n0 : n0) / nn;
-    gb[1] = (p[1] < 0.0 ? -n1 : n1) / nn;
-    gb[2] = (p[2] < 0.0 ? -n2 : n2) / nn;
+    const T n0 = x0 / q0, n1 = x1 / q1, n2 = x2 / q2;
+    const T nn = sqrt((n0 * n0 + n1 * n1) + n2 * n2);
+    gb[0] = (p[0] < (T)0 ? -n0 : n0) / nn;
+    gb[1] = (p[1] < (T)0 ? -n1 : n1) / nn;
+    gb[2] = (p[2] < (T)0 ? -n2 : n2) / nn;
   }
-  return t < 0.0 ? -d : d;
+  return t < (T)0 ? -d : d;
 }
 
 // Bounds of an ellipsoid's signed distance from its scaled copies: with
@@ -545,14 +546,9 @@ __device__ inline void ellip_bounds(CPoly* P, const T* p, T& dlo, T& dhi) {
 template <typename T, bool ELL = false>
 __device__ inline T poly_sdf_unit(CPoly* P, const T* p, T* gb, T far) {
   if (ELL && P->kind == KIND_ELLIPSOID) {
-    // smooth body: the FP64 distance by Newton's method (rounded to T)
-    const double pd[3] = {(double)p[0], (double)p[1], (double)p[2]};
-    const double fd = far >= (T)1e30 ? 1e300 : (double)far;
-    if (!gb) return (T)ellip_sdf_newton(P, pd, nullptr, fd);
-    double gd[3];
-    const double d = ellip_sdf_newton(P, pd, gd, fd);
-    for (int k = 0; k < 3; ++k) gb[k] = (T)gd[k];
-    return (T)d;
+    // smooth body: the distance by Newton's method in T (FP32 forms
+    // evaluate it only near the surface, where it is well conditioned)
+    return ellip_sdf_newton<T>(P, p, gb, far);
   }
   const int nf = P->nf;
   T best = (T)-1e30;
