@@ -137,7 +137,7 @@ def dense_ellipsoids(O, W):
     return wl, _oracle_run(O, wl, nsteps=2)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_dense_ellipsoid_box_full_size(dense_ellipsoids, H, prec):
     """The ellipsoid benchmark box (734 ellipsoids, 256^3): every node's
     owner from the exact ellipsoid distance, bit-exact in FP64."""
